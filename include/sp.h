@@ -1,0 +1,261 @@
+/*
+ * sp.h — C ABI of the MI355X (gfx950) betweenness-centrality library
+ * (libsp.so).
+ *
+ * The library computes Brandes betweenness centrality over a source list on
+ * a simple, undirected, unweighted graph held as int32 CSR, on one AMD GPU.
+ * The operation is the paper's computeBC (Appendix, Fig. "BC computation in
+ * StarPlat"): BC is zeroed, then for every source a level-synchronous
+ * breadth-first pass counts shortest paths (sigma[w] += sigma[v] over BFS-DAG
+ * children, Section 2.3.2 "iterateInBFS") and a reverse level-order pass
+ * accumulates delta[v] += (sigma[v] / sigma[w]) * (1 + delta[w]) over the same
+ * DAG children and adds delta[v] to BC[v] for every v other than the source
+ * ("iterateInReverse").  All arithmetic is IEEE binary64 (the paper declares
+ * BC and delta float; this library keeps every quantity in double).  No
+ * halving for undirected graphs and no normalisation: every ordered
+ * (source, target) pair contributes.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: SP_OK (0); a negative SP_ERR_* code, in which case no
+ *     output buffer has been written; or a positive SP_WARN_* bit mask, in
+ *     which case outputs were written and carry the stated caveat.
+ *   - Streams: `sp_stream` is a hipStream_t (NULL = the default stream).
+ *     Work is ordered on that stream.  Entry points that return a warning
+ *     synchronise the stream before returning, so the status is final.
+ *   - Host pointers are read before the call returns and never retained.
+ *   - Device output buffers are caller-owned and must be valid device
+ *     memory (e.g. a torch CUDA tensor on the current device).
+ *   - The source list is a list, not a set: a vertex listed twice
+ *     contributes twice.
+ *   - Thread safety: distinct sp_graph handles are independent; one handle
+ *     may be used by several threads when each passes its own stream (each
+ *     call takes its own workspace).  A server (sp_server) is thread-safe.
+ *   - Every entry point is exception-free and never aborts the process;
+ *     sp_last_error() returns a thread-local human-readable detail of the
+ *     last failure on the calling thread.
+ */
+#ifndef SP_H
+#define SP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sp_status;
+
+#define SP_OK 0
+/* Warning bit: some path count sigma exceeded 1e300 or was not finite; BC
+ * may hold inf or NaN (the paper's sigma is double and overflows the same
+ * way).  Outputs are written. */
+#define SP_WARN_SIGMA_LARGE 1
+#define SP_ERR_INVALID_ARGUMENT (-1) /* null pointer, bad size, source out of range, malformed CSR */
+#define SP_ERR_OUT_OF_MEMORY (-2)    /* device or host allocation failed, or memory budget exceeded */
+#define SP_ERR_DEVICE (-3)           /* HIP runtime error; detail in sp_last_error() */
+#define SP_ERR_NOT_SUPPORTED (-4)    /* no usable gfx950 device, or a request outside documented limits */
+#define SP_ERR_REJECTED (-5)         /* serving: request can never fit, or the server is shutting down */
+#define SP_ERR_TIMEOUT (-6)          /* serving: wait timed out (request still in flight) */
+#define SP_ERR_CANCELLED (-7)        /* serving: request was cancelled before it ran */
+
+/* Upload flags. */
+#define SP_PTR_DEVICE 1u /* row_ptr/col_idx are device pointers (else host) */
+#define SP_VALIDATE 2u   /* check: offsets monotone, ids in range, rows sorted and
+                            duplicate-free, no self-loops, symmetric */
+
+typedef struct sp_graph_s *sp_graph;
+typedef struct sp_server_s *sp_server;
+typedef struct sp_request_s *sp_request;
+typedef void *sp_stream;
+
+/* ------------------------------------------------------------------------
+ * Status and diagnostics
+ * ------------------------------------------------------------------------ */
+
+/* Static text of a status code. Never NULL. */
+const char *sp_status_string(sp_status s);
+
+/* Thread-local detail of the last failure on this thread ("" if none).
+ * Valid until the next library call on this thread. */
+const char *sp_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t sp_version(void);
+
+/* ------------------------------------------------------------------------
+ * Graphs (paper Section 2.3.1 "Data Types": CSR offsets + neighbour lists;
+ * Section 3 "Backend graph library": the CSR is copied to the device once)
+ * ------------------------------------------------------------------------ */
+
+/* Copy a CSR graph into library-owned device memory on the current device.
+ *   n_vertices  V >= 0; vertex ids are [0, V).  V < 2^31 - 1.
+ *   nnz         number of CSR entries (2x the undirected edges), 0 <= nnz < 2^31.
+ *   row_ptr     V + 1 int32 offsets, row_ptr[0] = 0, row_ptr[V] = nnz.
+ *   col_idx     nnz int32 neighbour ids.  An undirected edge {u, w} must
+ *               appear as w in row u and as u in row w.
+ *   flags       SP_PTR_DEVICE if the two arrays are device pointers (else
+ *               host); SP_VALIDATE to check the CSR (on the host, copying
+ *               device arrays back first) before uploading.
+ *   s           stream used for the copies; the call synchronises it.
+ *   out         receives the handle (unchanged on error).
+ * Without SP_VALIDATE the CSR is trusted; a malformed one gives undefined
+ * results (never out-of-bounds access: ids are masked into range). */
+sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out);
+
+/* Free the graph's device memory.  The caller must ensure no call using the
+ * graph is still running.  NULL is accepted (no-op). */
+sp_status sp_graph_release(sp_graph g);
+
+/* Sizes of an uploaded graph.  Any output pointer may be NULL. */
+sp_status sp_graph_info(sp_graph g, int32_t *n_vertices, int64_t *nnz, size_t *device_bytes);
+
+/* ------------------------------------------------------------------------
+ * Betweenness centrality
+ * ------------------------------------------------------------------------ */
+
+/* Tuning of the batched path.  Zero in a field means "choose automatically"
+ * (autotuned value cached per graph, else the built-in default). */
+typedef struct sp_batch_config {
+    int32_t batch_width;  /* sources per multi-source pass, 1..64 */
+    int32_t block_size;   /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    double alpha;         /* bottom-up when frontier edges * alpha > unsettled edges */
+    double beta;          /* back to top-down when frontier vertices * beta < V */
+    int32_t chunk_levels; /* levels enqueued (or captured in one hipGraph) between
+                             host checks of the device "done" flag; < 0 disables capture */
+    int32_t reserved[3];  /* must be zero */
+} sp_batch_config;
+
+/* Counters of the last sp_bc / sp_bc_batch call on the calling thread. */
+typedef struct sp_stats {
+    int32_t n_sources;
+    int32_t n_passes;        /* BFS passes: sources for sp_bc, batches for sp_bc_batch */
+    int32_t max_levels;      /* deepest BFS (levels incl. level 0) over all passes */
+    int32_t sigma_flagged;   /* passes in which some sigma > 1e300 or not finite */
+    int64_t levels_total;    /* sum of levels over passes */
+    int64_t topdown_levels;  /* levels expanded top-down (frontier push) */
+    int64_t bottomup_levels; /* levels expanded bottom-up (unvisited pull) */
+    int64_t reached_total;   /* sum over sources of reached vertices */
+    double sigma_max;        /* largest path count seen */
+    double device_ms;        /* time from the first init kernel to BC ready (HIP events) */
+    int32_t batch_width;     /* configuration actually used */
+    int32_t block_size;
+    double alpha, beta;
+    int32_t chunk_levels;
+    int32_t graph_launches;  /* hipGraph launches used */
+} sp_stats;
+
+/* Per-source path: one BFS pass per source, sources in list order.
+ *   sources    host array of n_sources vertex ids in [0, V).
+ *   out_bc     device array of V doubles: zeroed, then receives BC.
+ * Returns SP_OK or SP_WARN_SIGMA_LARGE (synchronises the stream). */
+sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
+                sp_stream s);
+
+/* Batched path: sources are cut, in list order, into batches of
+ * cfg->batch_width; each batch runs as one multi-source BFS with a 64-bit
+ * source bitmap per vertex (one bit per batch slot), all slots advancing level
+ * by level together.  Same inputs, outputs and status as sp_bc; cfg may be
+ * NULL.  BC is accumulated per vertex in source-list order. */
+sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
+                      const sp_batch_config *cfg, sp_stream s);
+
+/* Counters of the last sp_bc / sp_bc_batch call on this thread. */
+sp_status sp_get_last_stats(sp_stats *out);
+
+/* Forward pass of one source through the per-source path:
+ *   out_dist   device int32[V]: BFS distance, -1 where unreached.
+ *   out_sigma  device double[V] (nullable): shortest-path counts, 0 where unreached.
+ *   out_delta  device double[V] (nullable): when given, the reverse pass runs too
+ *              and delta is written (0 at the source and where unreached). */
+sp_status sp_bfs_levels(sp_graph g, int32_t source, int32_t *out_dist, double *out_sigma,
+                        double *out_delta, sp_stream s);
+
+/* One multi-source pass (at most 64 sources) through the batched path,
+ * exposing per-source results, source-major: entry [i * V + v] belongs to
+ * sources[i].  Any output may be NULL except out_dist. Used to check that the
+ * batched path reaches the same distances and counts as the per-source one. */
+sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources,
+                          int32_t *out_dist, double *out_sigma, double *out_delta,
+                          const sp_batch_config *cfg, sp_stream s);
+
+/* Device workspace the batched path allocates for one pass of `batch_width`
+ * slots on this graph (bytes). */
+sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes);
+
+/* Autotuner: times candidate configurations of the batched path on a sample
+ * of `sources` (at most n_sources) and writes the fastest to *out.  The
+ * choice is cached on the graph and used whenever a later call passes a
+ * zero field.  Output buffers are not touched.  Synchronises the stream. */
+sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_sources,
+                      sp_batch_config *out, sp_stream s);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching over several resident graphs
+ * ------------------------------------------------------------------------ */
+
+typedef struct sp_server_config {
+    size_t memory_budget;  /* device bytes the server may hold for workspaces (0 = 25% of free) */
+    int32_t max_batch;     /* slots per multi-source pass, 1..64 (0 = 64) */
+    int32_t n_streams;     /* concurrent passes on the device, 1..8 (0 = 2) */
+    int32_t reserved[4];   /* must be zero */
+} sp_server_config;
+
+typedef struct sp_server_stats {
+    int64_t submitted, completed, failed, cancelled, rejected;
+    int64_t passes;          /* multi-source passes run */
+    int64_t slots_used;      /* sum over passes of filled slots */
+    int64_t edges_traversed; /* sum over completed sources of undirected edge count */
+    size_t admitted_bytes;   /* workspace bytes currently held */
+    size_t peak_admitted_bytes;
+    int32_t queue_depth;     /* sources waiting */
+    int32_t in_flight;       /* passes on the device */
+} sp_server_stats;
+
+/* Start a server: a scheduler thread packs queued sources of each graph into
+ * multi-source passes and runs them on its own HIP streams (on the device
+ * current at creation).  Workspaces are admitted against memory_budget. */
+sp_status sp_server_create(const sp_server_config *cfg, sp_server *out);
+
+/* Make an uploaded graph servable.  The graph must outlive the server. */
+sp_status sp_server_add_graph(sp_server srv, sp_graph g, int32_t *graph_id);
+
+/* Queue BC over `sources` on graph `graph_id`.  out_bc: device double[V],
+ * zeroed by the server before the first contribution and complete when the
+ * request completes.  The request's sources may share passes with other
+ * requests; each request's BC is accumulated per vertex in its own
+ * source-list order, so the result is the same alone or in a mix.
+ * out_req receives a handle to wait on and release. */
+sp_status sp_stream_submit(sp_server srv, int32_t graph_id, const int32_t *sources,
+                           int32_t n_sources, double *out_bc, sp_request *out_req);
+
+/* Wait until the request finishes or timeout_us passes (< 0 waits forever).
+ * Returns SP_OK when finished (its status in *result), SP_ERR_TIMEOUT
+ * otherwise. */
+sp_status sp_request_wait(sp_request r, int64_t timeout_us, sp_status *result);
+
+/* Non-blocking: 1 in *done if finished (status in *result), else 0. */
+sp_status sp_request_poll(sp_request r, int32_t *done, sp_status *result);
+
+/* Cancel a request whose sources have not started; returns SP_ERR_REJECTED
+ * if it is already running or finished (it then completes normally). */
+sp_status sp_request_cancel(sp_request r);
+
+/* Submission-to-completion latency in microseconds (after completion). */
+sp_status sp_request_latency_us(sp_request r, double *latency_us);
+
+/* Release a request handle (after completion or cancellation). */
+sp_status sp_request_release(sp_request r);
+
+sp_status sp_server_get_stats(sp_server srv, sp_server_stats *out);
+
+/* Stop accepting work, finish everything queued, free workspaces, join the
+ * scheduler thread.  Requests not yet released stay valid handles. */
+sp_status sp_server_destroy(sp_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP_H */

@@ -1,0 +1,671 @@
+// C ABI of the library: argument checks, graph upload, workspace pools and
+// the per-source / batched BC entry points.  Every entry point catches all
+// C++ exceptions and returns a status; nothing here aborts the process.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+
+#include "common.h"
+#include "devutil.h"
+
+namespace sp {
+
+// ---------------------------------------------------------------------------
+// Errors, stats, allocation
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512];
+static thread_local sp_stats g_stats;
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+sp_stats &tls_stats() { return g_stats; }
+
+static std::atomic<long long> g_alloc_count{0};
+static long long alloc_fail_after() {
+    static long long v = [] {
+        const char *e = std::getenv("SP_TEST_FAIL_ALLOC_AFTER");
+        return e ? std::atoll(e) : -1ll;
+    }();
+    return v;
+}
+
+sp_status dev_alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    const long long lim = alloc_fail_after();
+    if (lim >= 0 && g_alloc_count.fetch_add(1) >= lim) {
+        set_error("device allocation of %zu bytes refused by SP_TEST_FAIL_ALLOC_AFTER", bytes);
+        return SP_ERR_OUT_OF_MEMORY;
+    }
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? SP_ERR_OUT_OF_MEMORY : SP_ERR_DEVICE;
+    }
+    return SP_OK;
+}
+
+void dev_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+int device_cu_count() {
+    static int cus[64] = {0};
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return 256;
+    if (!cus[d]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || c <= 0)
+            c = 256;
+        cus[d] = c;
+    }
+    return cus[d];
+}
+
+int grid_for(int64_t items, int block, int max_blocks) {
+    int64_t g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > max_blocks) g = max_blocks;
+    return (int)g;
+}
+
+// The library runs on gfx950 only; checked once per device.
+static sp_status check_device(int *dev_out) {
+    int d = -1;
+    hipError_t e = hipGetDevice(&d);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("no HIP device: %s", hipGetErrorString(e));
+        return SP_ERR_NOT_SUPPORTED;
+    }
+    static std::atomic<int> ok[64];
+    if (d < 0 || d >= 64) return SP_ERR_NOT_SUPPORTED;
+    if (ok[d].load() == 0) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, d) != hipSuccess) {
+            set_error("hipGetDeviceProperties failed");
+            return SP_ERR_DEVICE;
+        }
+        ok[d].store(std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 2);
+    }
+    if (ok[d].load() != 1) {
+        set_error("device %d is not gfx950", d);
+        return SP_ERR_NOT_SUPPORTED;
+    }
+    if (dev_out) *dev_out = d;
+    return SP_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != d) (void)hipSetDevice(d);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// CSR checks
+// ---------------------------------------------------------------------------
+// Device-side range check run on every upload: offsets monotone within
+// [0, nnz], ids within [0, n).  bad[0] counts violations.
+__global__ void k_check_csr(const int32_t *rp, const int32_t *ci, int32_t n, int64_t nnz,
+                            unsigned int *bad) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned int b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)n + 1; i += stride) {
+        const int32_t r = rp[i];
+        if (r < 0 || (int64_t)r > nnz) ++b;
+        if (i == 0 && r != 0) ++b;
+        if (i == n && (int64_t)r != nnz) ++b;
+        if (i < n && rp[i + 1] < r) ++b;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) {
+        const int32_t c = ci[i];
+        if (c < 0 || c >= n) ++b;
+    }
+    if (b) atomicAdd(bad, b);
+}
+
+// Host check of the full contract (SP_VALIDATE).
+static bool host_validate(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci) {
+    if (rp[0] != 0 || (int64_t)rp[n] != nnz) {
+        set_error("row_ptr[0] must be 0 and row_ptr[V] must equal nnz");
+        return false;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (rp[v + 1] < rp[v]) {
+            set_error("row_ptr decreases at vertex %d", v);
+            return false;
+        }
+        for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+            const int32_t w = ci[e];
+            if (w < 0 || w >= n) {
+                set_error("col_idx[%d] = %d out of range", e, w);
+                return false;
+            }
+            if (w == v) {
+                set_error("self-loop at vertex %d", v);
+                return false;
+            }
+            if (e > rp[v] && ci[e - 1] >= w) {
+                set_error("row %d not strictly ascending (unsorted or duplicate)", v);
+                return false;
+            }
+            // symmetric: v must appear in row w (binary search, rows sorted)
+            const int32_t *b = ci + rp[w], *en = ci + rp[w + 1];
+            const int32_t *f = std::lower_bound(b, en, v);
+            if (f == en || *f != v) {
+                set_error("edge %d->%d has no reverse entry", v, w);
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace pools
+// ---------------------------------------------------------------------------
+static sp_status acquire_source_ws(sp_graph g, SourceWorkspace **out) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->src_pool.empty()) {
+            *out = g->src_pool.back();
+            g->src_pool.pop_back();
+            return SP_OK;
+        }
+    }
+    auto *ws = new (std::nothrow) SourceWorkspace;
+    if (!ws) return SP_ERR_OUT_OF_MEMORY;
+    sp_status st = source_ws_create(g, *ws);
+    if (st < 0) {
+        source_ws_destroy(*ws);
+        delete ws;
+        return st;
+    }
+    *out = ws;
+    return SP_OK;
+}
+
+static void release_source_ws(sp_graph g, SourceWorkspace *ws) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->src_pool.push_back(ws);
+}
+
+int64_t initial_qcap(int32_t n, int32_t width) {
+    const int64_t V = std::max(n, 1);
+    return V * std::min(width, 16) + kSlots;
+}
+
+sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->batch_pool.empty()) {
+            *out = g->batch_pool.back();
+            g->batch_pool.pop_back();
+            return SP_OK;
+        }
+    }
+    auto *ws = new (std::nothrow) BatchWorkspace;
+    if (!ws) return SP_ERR_OUT_OF_MEMORY;
+    sp_status st = batch_ws_create(g, initial_qcap(g->n, width), *ws);
+    if (st < 0) {
+        batch_ws_destroy(*ws);
+        delete ws;
+        return st;
+    }
+    *out = ws;
+    return SP_OK;
+}
+
+void release_batch_ws(sp_graph g, BatchWorkspace *ws) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->batch_pool.push_back(ws);
+}
+
+static sp_status check_sources(sp_graph g, const int32_t *sources, int32_t n_sources) {
+    if (n_sources < 0 || (n_sources > 0 && !sources)) {
+        set_error("sources must be a host array of n_sources >= 0 ids");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    for (int32_t i = 0; i < n_sources; ++i)
+        if (sources[i] < 0 || sources[i] >= g->n) {
+            set_error("sources[%d] = %d outside [0, %d)", i, sources[i], g->n);
+            return SP_ERR_INVALID_ARGUMENT;
+        }
+    return SP_OK;
+}
+
+// Effective batched configuration: explicit fields, else tuned, else defaults.
+BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *width) {
+    sp_batch_config t{};
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->tuned.valid) t = g->tuned.cfg;
+    }
+    auto pick_i = [](int32_t a, int32_t b, int32_t d) { return a ? a : (b ? b : d); };
+    auto pick_d = [](double a, double b, double d) { return a > 0 ? a : (b > 0 ? b : d); };
+    BatchRunOpts o;
+    *width = pick_i(cfg ? cfg->batch_width : 0, t.batch_width, 64);
+    o.block = pick_i(cfg ? cfg->block_size : 0, t.block_size, 256);
+    o.alpha = pick_d(cfg ? cfg->alpha : 0, t.alpha, 15.0);
+    o.beta = pick_d(cfg ? cfg->beta : 0, t.beta, 24.0);
+    o.chunk_levels = pick_i(cfg ? cfg->chunk_levels : 0, t.chunk_levels, 8);
+    return o;
+}
+
+static sp_status check_batch_cfg(const sp_batch_config *cfg) {
+    if (!cfg) return SP_OK;
+    if (cfg->batch_width < 0 || cfg->batch_width > kSlots) {
+        set_error("batch_width %d outside 0..64", cfg->batch_width);
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    const int b = cfg->block_size;
+    if (b != 0 && b != 128 && b != 256 && b != 512) {
+        set_error("block_size %d not one of 128, 256, 512", b);
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    if (cfg->alpha < 0 || cfg->beta < 0 || !std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta)) {
+        set_error("alpha/beta must be finite and >= 0");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    for (int r : cfg->reserved)
+        if (r) {
+            set_error("reserved fields must be zero");
+            return SP_ERR_INVALID_ARGUMENT;
+        }
+    return SP_OK;
+}
+
+// Export helpers for sp_bfs_levels.
+__global__ void k_src_export(int32_t n, const int32_t *dist, const double *sigma, const double *delta,
+                             int32_t *out_dist, double *out_sigma, double *out_delta) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int32_t d = dist[v];
+        out_dist[v] = d;
+        if (out_sigma) out_sigma[v] = d >= 0 ? sigma[v] : 0.0;
+        if (out_delta) out_delta[v] = d > 0 ? delta[v] : 0.0;
+    }
+}
+
+}  // namespace sp
+
+using namespace sp;
+
+#define SP_GUARD_BEGIN try {
+#define SP_GUARD_END                                       \
+    }                                                      \
+    catch (const std::bad_alloc &) {                       \
+        set_error("host allocation failed");               \
+        return SP_ERR_OUT_OF_MEMORY;                       \
+    }                                                      \
+    catch (...) {                                          \
+        set_error("unexpected C++ exception");             \
+        return SP_ERR_DEVICE;                              \
+    }
+
+extern "C" {
+
+const char *sp_status_string(sp_status s) {
+    switch (s) {
+        case SP_OK: return "ok";
+        case SP_WARN_SIGMA_LARGE: return "warning: some path count exceeded 1e300 or was not finite";
+        case SP_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case SP_ERR_OUT_OF_MEMORY: return "out of memory";
+        case SP_ERR_DEVICE: return "device error";
+        case SP_ERR_NOT_SUPPORTED: return "not supported";
+        case SP_ERR_REJECTED: return "rejected";
+        case SP_ERR_TIMEOUT: return "timed out";
+        case SP_ERR_CANCELLED: return "cancelled";
+        default: return s > 0 ? "warning" : "unknown error";
+    }
+}
+
+const char *sp_last_error(void) { return g_err; }
+
+int32_t sp_version(void) { return 100; }
+
+sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!out || n_vertices < 0 || n_vertices == INT32_MAX || nnz < 0 || nnz >= INT32_MAX ||
+        !row_ptr || (nnz > 0 && !col_idx) || (flags & ~(SP_PTR_DEVICE | SP_VALIDATE))) {
+        set_error("sp_graph_upload: bad arguments");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    int dev = 0;
+    SP_TRY(check_device(&dev));
+    hipStream_t st = (hipStream_t)s;
+    const bool on_dev = flags & SP_PTR_DEVICE;
+    if (flags & SP_VALIDATE) {
+        std::vector<int32_t> hr, hc;
+        const int32_t *rp = row_ptr, *ci = col_idx;
+        if (on_dev) {
+            hr.resize((size_t)n_vertices + 1);
+            hc.resize((size_t)nnz);
+            SP_HIP(hipMemcpyAsync(hr.data(), row_ptr, hr.size() * 4, hipMemcpyDeviceToHost, st));
+            if (nnz) SP_HIP(hipMemcpyAsync(hc.data(), col_idx, hc.size() * 4, hipMemcpyDeviceToHost, st));
+            SP_HIP(hipStreamSynchronize(st));
+            rp = hr.data();
+            ci = hc.data();
+        }
+        if (!host_validate(n_vertices, nnz, rp, ci)) return SP_ERR_INVALID_ARGUMENT;
+    }
+    auto *g = new sp_graph_s;
+    g->device = dev;
+    g->n = n_vertices;
+    g->nnz = nnz;
+    sp_status rc = dev_alloc((void **)&g->row_ptr, ((size_t)n_vertices + 1) * 4);
+    if (rc == SP_OK) rc = dev_alloc((void **)&g->col_idx, (size_t)std::max<int64_t>(nnz, 1) * 4);
+    unsigned int *bad = nullptr;
+    if (rc == SP_OK) rc = dev_alloc((void **)&bad, 4);
+    if (rc != SP_OK) {
+        dev_free(g->row_ptr);
+        dev_free(g->col_idx);
+        dev_free(bad);
+        delete g;
+        return rc;
+    }
+    auto fail = [&](sp_status code) {
+        dev_free(g->row_ptr);
+        dev_free(g->col_idx);
+        dev_free(bad);
+        delete g;
+        return code;
+    };
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    unsigned int h_bad = 0;
+    std::vector<int32_t> deg_rp;
+    hipError_t e = hipMemcpyAsync(g->row_ptr, row_ptr, ((size_t)n_vertices + 1) * 4, kind, st);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(g->col_idx, col_idx, (size_t)nnz * 4, kind, st);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, 4, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_check_csr, dim3(grid_for(std::max<int64_t>(nnz, n_vertices + 1), 256, 2048)),
+                           dim3(256), 0, st, (const int32_t *)g->row_ptr, (const int32_t *)g->col_idx,
+                           n_vertices, nnz, bad);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_bad, bad, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) {
+        deg_rp.resize((size_t)n_vertices + 1);
+        e = hipMemcpyAsync(deg_rp.data(), g->row_ptr, deg_rp.size() * 4, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error("graph upload failed: %s", hipGetErrorString(e));
+        return fail(SP_ERR_DEVICE);
+    }
+    if (h_bad) {
+        set_error("CSR has %u out-of-range offsets or ids", h_bad);
+        return fail(SP_ERR_INVALID_ARGUMENT);
+    }
+    dev_free(bad);
+    bad = nullptr;
+    int32_t md = 0;
+    for (int32_t v = 0; v < n_vertices; ++v) md = std::max(md, deg_rp[v + 1] - deg_rp[v]);
+    g->max_degree = md;
+    g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
+    *out = g;
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_graph_release(sp_graph g) {
+    SP_GUARD_BEGIN
+    if (!g) return SP_OK;
+    DeviceGuard dg(g->device);
+    (void)hipDeviceSynchronize();
+    for (auto *ws : g->src_pool) {
+        source_ws_destroy(*ws);
+        delete ws;
+    }
+    for (auto *ws : g->batch_pool) {
+        batch_ws_destroy(*ws);
+        delete ws;
+    }
+    dev_free(g->row_ptr);
+    dev_free(g->col_idx);
+    delete g;
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_graph_info(sp_graph g, int32_t *n_vertices, int64_t *nnz, size_t *device_bytes) {
+    if (!g) {
+        set_error("null graph");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    if (n_vertices) *n_vertices = g->n;
+    if (nnz) *nnz = g->nnz;
+    if (device_bytes) *device_bytes = g->bytes;
+    return SP_OK;
+}
+
+sp_status sp_get_last_stats(sp_stats *out) {
+    if (!out) return SP_ERR_INVALID_ARGUMENT;
+    *out = g_stats;
+    return SP_OK;
+}
+
+sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc, sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || (g->n > 0 && !out_bc)) {
+        set_error("sp_bc: null graph or output");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    SP_TRY(check_sources(g, sources, n_sources));
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    sp_stats stats{};
+    stats.n_sources = n_sources;
+    if (g->n == 0) {
+        g_stats = stats;
+        return SP_OK;
+    }
+    SourceWorkspace *ws = nullptr;
+    SP_TRY(acquire_source_ws(g, &ws));
+    struct Rel {
+        sp_graph g;
+        SourceWorkspace *ws;
+        ~Rel() { release_source_ws(g, ws); }
+    } rel{g, ws};
+    sp_batch_config tcfg{};
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->tuned.valid) tcfg = g->tuned.cfg;
+    }
+    SourceRunOpts o;
+    if (tcfg.block_size) o.block = tcfg.block_size;
+    SP_HIP(hipEventRecord(ws->ev0, st));
+    SP_TRY(launch_fill_f64(out_bc, g->n, 0.0, st));
+    bool flagged = false;
+    for (int32_t i = 0; i < n_sources; ++i) {
+        SourceResult r;
+        SP_TRY(source_run(g, *ws, sources[i], out_bc, true, o, st, &r));
+        stats.n_passes++;
+        stats.max_levels = std::max(stats.max_levels, r.levels);
+        stats.levels_total += r.levels;
+        stats.topdown_levels += r.td;
+        stats.bottomup_levels += r.bu;
+        stats.reached_total += r.reached;
+        stats.sigma_max = std::max(stats.sigma_max, r.sigma_max);
+        if (r.flagged) {
+            stats.sigma_flagged++;
+            flagged = true;
+        }
+    }
+    SP_HIP(hipEventRecord(ws->ev1, st));
+    SP_HIP(hipEventSynchronize(ws->ev1));
+    float ms = 0;
+    SP_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+    stats.device_ms = ms;
+    stats.batch_width = 1;
+    stats.block_size = o.block;
+    stats.alpha = o.alpha;
+    stats.beta = o.beta;
+    stats.chunk_levels = o.chunk_levels;
+    g_stats = stats;
+    return flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
+                      const sp_batch_config *cfg, sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || (g->n > 0 && !out_bc)) {
+        set_error("sp_bc_batch: null graph or output");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    SP_TRY(check_sources(g, sources, n_sources));
+    SP_TRY(check_batch_cfg(cfg));
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    int32_t width = 64;
+    const BatchRunOpts o = resolve_batch(g, cfg, &width);
+    sp_stats stats{};
+    stats.n_sources = n_sources;
+    stats.batch_width = width;
+    stats.block_size = o.block;
+    stats.alpha = o.alpha;
+    stats.beta = o.beta;
+    stats.chunk_levels = o.chunk_levels;
+    if (g->n == 0) {
+        g_stats = stats;
+        return SP_OK;
+    }
+    BatchWorkspace *ws = nullptr;
+    SP_TRY(acquire_batch_ws(g, width, &ws));
+    struct Rel {
+        sp_graph g;
+        BatchWorkspace *ws;
+        ~Rel() { release_batch_ws(g, ws); }
+    } rel{g, ws};
+    hipEvent_t e0, e1;
+    SP_HIP(hipEventCreate(&e0));
+    SP_HIP(hipEventCreate(&e1));
+    struct EvRel {
+        hipEvent_t a, b;
+        ~EvRel() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } evrel{e0, e1};
+    SP_HIP(hipEventRecord(e0, st));
+    SP_TRY(launch_fill_f64(out_bc, g->n, 0.0, st));
+    double *slots[kSlots];
+    for (auto &p : slots) p = out_bc;
+    bool flagged = false;
+    for (int32_t b = 0; b < n_sources; b += width) {
+        const int32_t nb = std::min(width, n_sources - b);
+        BatchResult r;
+        SP_TRY(batch_run(g, *ws, sources + b, nb, slots, o, st, &r, false));
+        stats.n_passes++;
+        stats.max_levels = std::max(stats.max_levels, r.levels);
+        stats.levels_total += r.levels;
+        stats.topdown_levels += r.td;
+        stats.bottomup_levels += r.bu;
+        stats.reached_total += r.reached;
+        stats.sigma_max = std::max(stats.sigma_max, r.sigma_max);
+        stats.graph_launches += r.graph_launches;
+        if (r.flagged) {
+            stats.sigma_flagged += r.flagged;
+            flagged = true;
+        }
+    }
+    SP_HIP(hipEventRecord(e1, st));
+    SP_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    SP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    stats.device_ms = ms;
+    g_stats = stats;
+    return flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_bfs_levels(sp_graph g, int32_t source, int32_t *out_dist, double *out_sigma,
+                        double *out_delta, sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || !out_dist || source < 0 || source >= g->n) {
+        set_error("sp_bfs_levels: null graph/output or source out of range");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    SourceWorkspace *ws = nullptr;
+    SP_TRY(acquire_source_ws(g, &ws));
+    struct Rel {
+        sp_graph g;
+        SourceWorkspace *ws;
+        ~Rel() { release_source_ws(g, ws); }
+    } rel{g, ws};
+    SourceRunOpts o;
+    SourceResult r;
+    SP_TRY(source_run(g, *ws, source, nullptr, out_delta != nullptr, o, st, &r));
+    hipLaunchKernelGGL(k_src_export, dim3(grid_for(g->n, 256, 4096)), dim3(256), 0, st, g->n,
+                       (const int32_t *)ws->dist, (const double *)ws->sigma,
+                       (const double *)ws->delta, out_dist, out_sigma, out_delta);
+    SP_HIP(hipGetLastError());
+    SP_HIP(hipStreamSynchronize(st));
+    return r.flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources, int32_t *out_dist,
+                          double *out_sigma, double *out_delta, const sp_batch_config *cfg,
+                          sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || !out_dist || n_sources < 1 || n_sources > kSlots) {
+        set_error("sp_batch_levels: null graph/output or n_sources outside 1..64");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    SP_TRY(check_sources(g, sources, n_sources));
+    SP_TRY(check_batch_cfg(cfg));
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    int32_t width = 64;
+    const BatchRunOpts o = resolve_batch(g, cfg, &width);
+    BatchWorkspace *ws = nullptr;
+    SP_TRY(acquire_batch_ws(g, n_sources, &ws));
+    struct Rel {
+        sp_graph g;
+        BatchWorkspace *ws;
+        ~Rel() { release_batch_ws(g, ws); }
+    } rel{g, ws};
+    BatchResult r;
+    SP_TRY(batch_run(g, *ws, sources, n_sources, nullptr, o, st, &r, true));
+    SP_TRY(batch_extract(g, *ws, n_sources, out_dist, out_sigma, out_delta, st));
+    SP_HIP(hipStreamSynchronize(st));
+    return r.flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes) {
+    if (!g || !bytes || batch_width < 1 || batch_width > kSlots) {
+        set_error("sp_bc_workspace_bytes: bad arguments");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    *bytes = batch_ws_bytes(g->n, initial_qcap(g->n, batch_width), std::max(g->n, 1) + 2);
+    return SP_OK;
+}
+
+}  // extern "C"

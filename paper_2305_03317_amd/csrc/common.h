@@ -1,0 +1,213 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sp.h"
+
+namespace sp {
+
+// ---------------------------------------------------------------------------
+// Errors: a thread-local detail string plus status codes; no exceptions cross
+// the C ABI.
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define SP_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::sp::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                            __FILE__, __LINE__);                                      \
+            return e_ == hipErrorOutOfMemory ? SP_ERR_OUT_OF_MEMORY : SP_ERR_DEVICE;  \
+        }                                                                             \
+    } while (0)
+
+#define SP_TRY(expr)                        \
+    do {                                    \
+        sp_status st_ = (expr);             \
+        if (st_ < 0) return st_;            \
+    } while (0)
+
+// Device allocation with an optional global test hook that makes the n-th
+// allocation fail (environment SP_TEST_FAIL_ALLOC_AFTER=n), so the
+// out-of-memory paths can be exercised without a full device.
+sp_status dev_alloc(void **p, size_t bytes);
+void dev_free(void *p);
+
+// ---------------------------------------------------------------------------
+// Graph
+// ---------------------------------------------------------------------------
+struct BatchWorkspace;
+struct SourceWorkspace;
+
+struct TuneEntry {
+    bool valid = false;
+    sp_batch_config cfg{};
+};
+
+}  // namespace sp
+
+struct sp_graph_s {
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t *row_ptr = nullptr;  // device, n + 1
+    int32_t *col_idx = nullptr;  // device, nnz (>= 1 element allocated)
+    int32_t max_degree = 0;
+    size_t bytes = 0;
+    std::mutex mu;               // guards `tuned` and the workspace pools
+    sp::TuneEntry tuned;
+    std::vector<sp::SourceWorkspace *> src_pool;
+    std::vector<sp::BatchWorkspace *> batch_pool;
+};
+
+namespace sp {
+
+// Per-thread stats of the last BC call.
+sp_stats &tls_stats();
+
+// ---------------------------------------------------------------------------
+// Level-loop control block shared by the kernels of one BFS pass.  It lives in
+// device memory; the kernels of a level read it, the `advance` kernel updates
+// it, and the host reads it back once per chunk of levels.
+// ---------------------------------------------------------------------------
+enum : int32_t { MODE_TOPDOWN = 0, MODE_BOTTOMUP = 1 };
+
+struct LevelCtl {
+    int32_t level;      // level of the current frontier
+    int32_t lo, hi;     // current frontier = queue[lo, hi)
+    int32_t tail;       // append position for the next frontier (starts at hi)
+    int32_t done;       // 1 once a level produced no new vertex
+    int32_t mode;       // MODE_* chosen for expanding the current frontier
+    int32_t overflow;   // batched path: queue capacity exceeded
+    int32_t pad0;
+    unsigned long long front_deg;  // adjacency entries of the current frontier
+    unsigned long long next_deg;   // adjacency entries of the next frontier (accumulating)
+    unsigned long long unset_deg;  // adjacency entries of vertices not yet reached
+    unsigned long long reached_pairs;   // batched path: (slot, vertex) pairs reached
+    unsigned long long sigma_max_bits;  // bit pattern of the largest sigma (>= 0, so
+                                        // integer order = value order; NaN sorts above inf)
+    unsigned long long flagged_slots;   // batched path: slots with sigma > 1e300 / non-finite
+    unsigned long long settled_deg;     // batched path: adjacency entries of vertices that
+                                        // became reached by every slot at this level
+    double alpha, beta;                 // direction thresholds
+    int32_t n_vertices;
+    int32_t topdown_levels, bottomup_levels;
+    int32_t pad1;
+};
+
+constexpr int kMaxLevelsHost = 1 << 22;  // sanity bound on BFS depth (V < 2^31)
+
+// Launch shape helpers.
+int device_cu_count();
+int grid_for(int64_t items, int block, int max_blocks);
+
+// ---------------------------------------------------------------------------
+// Per-source path (source_path.hip)
+// ---------------------------------------------------------------------------
+struct SourceWorkspace {
+    int device = -1;
+    int32_t n = 0;
+    int32_t *dist = nullptr;
+    double *sigma = nullptr;
+    double *delta = nullptr;
+    int32_t *queue = nullptr;
+    int32_t *level_off = nullptr;  // device, levels + 2
+    int32_t level_cap = 0;
+    LevelCtl *ctl = nullptr;       // device
+    LevelCtl *ctl_host = nullptr;  // pinned mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+sp_status source_ws_create(sp_graph g, SourceWorkspace &ws);
+void source_ws_destroy(SourceWorkspace &ws);
+
+struct SourceRunOpts {
+    double alpha = 15.0, beta = 24.0;
+    int block = 256;
+    int chunk_levels = 8;
+};
+struct SourceResult {
+    int32_t levels = 0;   // levels including level 0
+    int32_t reached = 0;
+    double sigma_max = 0.0;
+    bool flagged = false;  // some sigma > 1e300 or not finite
+    int32_t td = 0, bu = 0;
+};
+// One source: forward (+ backward when with_backward); bc may be null.
+sp_status source_run(sp_graph g, SourceWorkspace &ws, int32_t src, double *bc, bool with_backward,
+                     const SourceRunOpts &o, hipStream_t s, SourceResult *res);
+
+// ---------------------------------------------------------------------------
+// Batched path (batch_path.hip)
+// ---------------------------------------------------------------------------
+constexpr int kSlots = 64;  // bits per source bitmap; also the slot stride of sigma/delta rows
+
+struct BatchWorkspace {
+    int device = -1;
+    int32_t n = 0;
+    unsigned long long *seen = nullptr;  // V: slots that reached v at any level so far
+    unsigned long long *nxt = nullptr;   // V: slots discovering v at the level being built
+    uint4 *front[2] = {nullptr, nullptr};  // V: {mask lo, mask hi, level tag, pad} by level parity
+    double *sigma = nullptr;             // V x 64, vertex-major: sigma[v * 64 + slot]
+    double *delta = nullptr;             // V x 64
+    int32_t *queue = nullptr;            // entries: vertex ids, levels concatenated
+    unsigned long long *qmask = nullptr; // entries: slot mask of the vertex at that level
+    int64_t qcap = 0;
+    int32_t *level_off = nullptr;        // device, level_cap + 2
+    int32_t level_cap = 0;
+    int32_t *slot_src = nullptr;         // device, 64: source vertex of each slot (-1 = empty)
+    LevelCtl *ctl = nullptr;
+    LevelCtl *ctl_host = nullptr;
+    void *staging = nullptr;             // pinned: level-0 entries and slot sources
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    size_t bytes = 0;
+    std::vector<int32_t> kept_off;       // level offsets of the last pass (host copy)
+};
+size_t batch_ws_bytes(int32_t n, int64_t qcap, int32_t level_cap);
+sp_status batch_ws_create(sp_graph g, int64_t qcap, BatchWorkspace &ws);
+void batch_ws_destroy(BatchWorkspace &ws);
+
+struct BatchRunOpts {
+    double alpha = 15.0, beta = 24.0;
+    int block = 256;
+    int chunk_levels = 8;
+};
+
+// One multi-source pass over up to 64 sources (slot i <- srcs[i]).
+//   bc_of_slot: per slot, the device BC array its delta is added to (may repeat);
+//     slots are reduced in ascending slot order per vertex.
+struct BatchResult {
+    int32_t levels = 0;
+    int64_t reached = 0;    // (slot, vertex) pairs reached
+    int64_t entries = 0;    // (vertex, level) entries
+    double sigma_max = 0.0;
+    int32_t flagged = 0;    // slots with some sigma > 1e300 or not finite
+    int32_t td = 0, bu = 0;
+    int32_t graph_launches = 0;
+};
+sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
+                    double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
+                    BatchResult *res, bool keep_levels = false);
+// After batch_run(keep_levels = true): per-slot dist/sigma/delta, source-major.
+sp_status batch_extract(sp_graph g, BatchWorkspace &ws, int32_t nslots, int32_t *out_dist,
+                        double *out_sigma, double *out_delta, hipStream_t s);
+
+// Workspace pools and configuration shared by the entry points and the server.
+int64_t initial_qcap(int32_t n, int32_t width);
+sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out);
+void release_batch_ws(sp_graph g, BatchWorkspace *ws);
+BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *width);
+
+// Kernels used by several files.
+sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+sp_status launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+}  // namespace sp

@@ -1,0 +1,164 @@
+// Device-side helpers for wave64 (CDNA) kernels: lane queries, wave-level
+// reductions in a fixed order, block scans, and an LDS-staged append buffer
+// that turns per-vertex queue appends into one global atomic per flush.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sp {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ int32_t shfl_i32(int32_t v, int src) { return __shfl(v, src, kWave); }
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
+    return __shfl(v, src, kWave);
+}
+
+__device__ __forceinline__ double shfl_f64(double v, int src) { return __shfl(v, src, kWave); }
+
+// Number of set lanes of `m` below the calling lane.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    const int l = lane_id();
+    return __popcll(m & ((l == 0) ? 0ull : (~0ull >> (64 - l))));
+}
+
+// Sum over the 64 lanes by a fixed xor butterfly: the same inputs give the
+// same bits on every run.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ double wave_max_f64(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+
+// Inclusive prefix sum over the lanes of one wave.
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int32_t y = __shfl_up(x, o, kWave);
+        if (l >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive prefix sum over a block of BS threads; *total receives the sum.
+// Uses BS / 64 + 1 ints of LDS at `scratch`.  All threads must call.
+template <int BS>
+__device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t *scratch, int32_t *total) {
+    constexpr int NW = BS / kWave;
+    const int w = threadIdx.x / kWave, l = lane_id();
+    int32_t incl = wave_incl_scan(x);
+    if (l == kWave - 1) scratch[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int i = 0; i < NW; ++i) {
+            int32_t t = scratch[i];
+            scratch[i] = run;
+            run += t;
+        }
+        scratch[NW] = run;
+    }
+    __syncthreads();
+    int32_t ex = scratch[w] + incl - x;
+    *total = scratch[NW];
+    __syncthreads();
+    return ex;
+}
+
+// Non-negative doubles compare like their bit patterns (NaN above +inf), so a
+// running maximum of sigma can use the integer atomic.
+__device__ __forceinline__ void atomic_max_nonneg_f64(unsigned long long *bits, double v) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > *(volatile unsigned long long *)bits) atomicMax(bits, b);
+}
+
+__device__ __forceinline__ bool sigma_is_large(double s) { return !(s <= 1e300); }
+
+// LDS-staged append buffer.  Threads stage values in LDS; the block moves
+// them to the global queue with one atomic per flush.  Every thread of the
+// block must call stage() and finish() the same number of times.
+template <int BS, int CAP>
+struct StagedQueue {
+    static_assert(CAP >= 2 * BS, "capacity must hold two rounds");
+    int32_t *buf;   // LDS, CAP entries
+    int32_t *meta;  // LDS, 2 entries: [0] count, [1] global base
+
+    __device__ void init(int32_t *lds_buf, int32_t *lds_meta) {
+        buf = lds_buf;
+        meta = lds_meta;
+        if (threadIdx.x == 0) meta[0] = 0;
+        __syncthreads();
+    }
+
+    __device__ void flush(int32_t *g_tail, int32_t *g_queue, int64_t qcap, int32_t *overflow) {
+        // caller has synchronised; meta[0] is stable
+        const int32_t cnt = meta[0];
+        if (cnt == 0) return;
+        if (threadIdx.x == 0) meta[1] = atomicAdd(g_tail, cnt);
+        __syncthreads();
+        const int32_t base = meta[1];
+        for (int32_t i = threadIdx.x; i < cnt; i += BS) {
+            int64_t p = (int64_t)base + i;
+            if (p < qcap) g_queue[p] = buf[i];
+        }
+        if (threadIdx.x == 0) {
+            if ((int64_t)base + cnt > qcap) *overflow = 1;
+            meta[0] = 0;
+        }
+        __syncthreads();
+    }
+
+    // Stage `val` when `take`; flush if the next round might not fit.
+    __device__ void stage(bool take, int32_t val, int32_t *g_tail, int32_t *g_queue, int64_t qcap,
+                          int32_t *overflow) {
+        unsigned long long m = __ballot(take);
+        int32_t base = 0;
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            if (lane_id() == leader) base = atomicAdd(&meta[0], __popcll(m));
+            base = shfl_i32(base, leader);
+            if (take) buf[base + lanes_below(m)] = val;
+        }
+        __syncthreads();
+        const int32_t staged = meta[0];
+        __syncthreads();  // every thread has read the count before anyone stages again
+        if (staged > CAP - BS) flush(g_tail, g_queue, qcap, overflow);
+    }
+
+    __device__ void finish(int32_t *g_tail, int32_t *g_queue, int64_t qcap, int32_t *overflow) {
+        __syncthreads();
+        flush(g_tail, g_queue, qcap, overflow);
+    }
+};
+
+// Block-wide sum of a per-thread value, added to *dst by one atomic.
+template <int BS>
+__device__ __forceinline__ void block_add_u64(unsigned long long x, unsigned long long *lds2,
+                                              unsigned long long *dst) {
+    x = wave_sum_u64(x);
+    if (threadIdx.x == 0) lds2[0] = 0;
+    __syncthreads();
+    if (lane_id() == 0 && x) atomicAdd(&lds2[0], x);
+    __syncthreads();
+    if (threadIdx.x == 0 && lds2[0]) atomicAdd(dst, lds2[0]);
+}
+
+}  // namespace sp

@@ -1,0 +1,309 @@
+"""Python binding of ``libsp.so`` (C ABI in ``include/sp.h``).
+
+Argument marshalling only: every step of the BC computation runs in the HIP
+library.  torch supplies device memory (CUDA tensors) and the current stream;
+functions take and return torch tensors.  The library must be built
+(``python -m paper_2305_03317_amd._build``); importing this module without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsp.so")
+
+SP_OK = 0
+SP_WARN_SIGMA_LARGE = 1
+SP_ERR_INVALID_ARGUMENT = -1
+SP_ERR_OUT_OF_MEMORY = -2
+SP_ERR_DEVICE = -3
+SP_ERR_NOT_SUPPORTED = -4
+SP_ERR_REJECTED = -5
+SP_ERR_TIMEOUT = -6
+SP_ERR_CANCELLED = -7
+SP_PTR_DEVICE = 1
+SP_VALIDATE = 2
+
+
+class sp_batch_config(ctypes.Structure):
+    _fields_ = [("batch_width", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("chunk_levels", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class sp_stats(ctypes.Structure):
+    _fields_ = [("n_sources", ctypes.c_int32), ("n_passes", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("sigma_flagged", ctypes.c_int32),
+                ("levels_total", ctypes.c_int64), ("topdown_levels", ctypes.c_int64),
+                ("bottomup_levels", ctypes.c_int64), ("reached_total", ctypes.c_int64),
+                ("sigma_max", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("batch_width", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("chunk_levels", ctypes.c_int32), ("graph_launches", ctypes.c_int32)]
+
+
+class sp_server_config(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class sp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("cancelled", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("passes", ctypes.c_int64),
+                ("slots_used", ctypes.c_int64), ("edges_traversed", ctypes.c_int64),
+                ("admitted_bytes", ctypes.c_size_t), ("peak_admitted_bytes", ctypes.c_size_t),
+                ("queue_depth", ctypes.c_int32), ("in_flight", ctypes.c_int32)]
+
+
+def _struct_dict(s):
+    return {k: (list(getattr(s, k)) if k == "reserved" else getattr(s, k)) for k, _ in s._fields_}
+
+
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_VP = ctypes.c_void_p
+_ST = ctypes.c_int32
+
+# (name, restype, argtypes) of every exported entry point.
+SIGNATURES = [
+    ("sp_status_string", ctypes.c_char_p, [_ST]),
+    ("sp_last_error", ctypes.c_char_p, []),
+    ("sp_version", ctypes.c_int32, []),
+    ("sp_graph_upload", _ST, [ctypes.c_int32, ctypes.c_int64, _VP, _VP, ctypes.c_uint32, _VP,
+                              ctypes.POINTER(_VP)]),
+    ("sp_graph_release", _ST, [_VP]),
+    ("sp_graph_info", _ST, [_VP, _I32P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]),
+    ("sp_bc", _ST, [_VP, _I32P, ctypes.c_int32, _VP, _VP]),
+    ("sp_bc_batch", _ST, [_VP, _I32P, ctypes.c_int32, _VP, ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_get_last_stats", _ST, [ctypes.POINTER(sp_stats)]),
+    ("sp_bfs_levels", _ST, [_VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
+    ("sp_batch_levels", _ST, [_VP, _I32P, ctypes.c_int32, _VP, _VP, _VP,
+                              ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_bc_workspace_bytes", _ST, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sp_autotune", _ST, [_VP, _I32P, ctypes.c_int32, ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_server_create", _ST, [ctypes.POINTER(sp_server_config), ctypes.POINTER(_VP)]),
+    ("sp_server_add_graph", _ST, [_VP, _VP, _I32P]),
+    ("sp_stream_submit", _ST, [_VP, ctypes.c_int32, _I32P, ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
+    ("sp_request_wait", _ST, [_VP, ctypes.c_int64, _I32P]),
+    ("sp_request_poll", _ST, [_VP, _I32P, _I32P]),
+    ("sp_request_cancel", _ST, [_VP]),
+    ("sp_request_latency_us", _ST, [_VP, ctypes.POINTER(ctypes.c_double)]),
+    ("sp_request_release", _ST, [_VP]),
+    ("sp_server_get_stats", _ST, [_VP, ctypes.POINTER(sp_server_stats)]),
+    ("sp_server_destroy", _ST, [_VP]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded libsp.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsp.so is not built (run python -m paper_2305_03317_amd._build); "
+                               "there is no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SpError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        self.status = status
+        detail = L.sp_last_error().decode()
+        super().__init__("%s: %s (%d)%s" % (where, L.sp_status_string(status).decode(), status,
+                                            (": " + detail) if detail else ""))
+
+
+def _check(status, where):
+    if status < 0:
+        raise SpError(status, where)
+    return status
+
+
+def sp_status_string(status: int) -> str:
+    return lib().sp_status_string(status).decode()
+
+
+def sp_last_error() -> str:
+    return lib().sp_last_error().decode()
+
+
+def sp_version() -> int:
+    return lib().sp_version()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _host_i32(a):
+    a = np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+    return a, a.ctypes.data_as(_I32P)
+
+
+class Graph:
+    """An uploaded graph (library-owned device CSR)."""
+
+    def __init__(self, handle, n, nnz):
+        self.handle = handle
+        self.n = n
+        self.nnz = nnz
+
+    def release(self):
+        if self.handle:
+            _check(lib().sp_graph_release(self.handle), "sp_graph_release")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def sp_graph_upload(row_ptr, col_idx, validate: bool = False, stream=None) -> Graph:
+    """Upload CSR arrays (numpy / host or CUDA torch tensors) to the device."""
+    torch = _torch()
+    flags = SP_VALIDATE if validate else 0
+    keep = []
+    if isinstance(row_ptr, torch.Tensor) and row_ptr.is_cuda:
+        rp = row_ptr.to(torch.int32).contiguous()
+        ci = col_idx.to(torch.int32).contiguous()
+        keep += [rp, ci]
+        rp_ptr, ci_ptr = rp.data_ptr(), ci.data_ptr()
+        n, nnz = rp.numel() - 1, ci.numel()
+        flags |= SP_PTR_DEVICE
+    else:
+        rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
+        ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
+        if ci.size == 0:
+            ci = np.zeros(1, np.int32)
+            nnz = 0
+        else:
+            nnz = ci.size
+        keep += [rp, ci]
+        rp_ptr, ci_ptr = rp.ctypes.data, ci.ctypes.data
+        n = rp.size - 1
+    h = ctypes.c_void_p()
+    _check(lib().sp_graph_upload(n, nnz, rp_ptr, ci_ptr, flags, _stream(stream), ctypes.byref(h)),
+           "sp_graph_upload")
+    return Graph(h, n, nnz)
+
+
+def sp_graph_release(g: Graph):
+    g.release()
+
+
+def sp_graph_info(g: Graph):
+    n = ctypes.c_int32()
+    nnz = ctypes.c_int64()
+    b = ctypes.c_size_t()
+    _check(lib().sp_graph_info(g.handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(b)),
+           "sp_graph_info")
+    return dict(n_vertices=n.value, nnz=nnz.value, device_bytes=b.value)
+
+
+def _out_f64(g, out):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(max(g.n, 1), dtype=torch.float64, device="cuda")
+    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() >= g.n
+    return out
+
+
+def _config(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, sp_batch_config):
+        return ctypes.byref(cfg)
+    c = sp_batch_config()
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    return ctypes.byref(c)
+
+
+def sp_bc(g: Graph, sources, out_bc=None, stream=None):
+    """Per-source path. Returns (out_bc[:V] tensor, status)."""
+    out_bc = _out_f64(g, out_bc)
+    src, p = _host_i32(sources)
+    st = _check(lib().sp_bc(g.handle, p, len(src), out_bc.data_ptr(), _stream(stream)), "sp_bc")
+    return out_bc[:g.n], st
+
+
+def sp_bc_batch(g: Graph, sources, out_bc=None, config=None, stream=None):
+    """Batched (multi-source bitmap) path. Returns (out_bc[:V] tensor, status)."""
+    out_bc = _out_f64(g, out_bc)
+    src, p = _host_i32(sources)
+    st = _check(lib().sp_bc_batch(g.handle, p, len(src), out_bc.data_ptr(), _config(config),
+                                  _stream(stream)), "sp_bc_batch")
+    return out_bc[:g.n], st
+
+
+def sp_get_last_stats() -> dict:
+    s = sp_stats()
+    _check(lib().sp_get_last_stats(ctypes.byref(s)), "sp_get_last_stats")
+    return _struct_dict(s)
+
+
+def sp_bfs_levels(g: Graph, source: int, with_sigma=True, with_delta=False, stream=None):
+    """(dist int32, sigma f64 or None, delta f64 or None, status) of one source."""
+    torch = _torch()
+    n = max(g.n, 1)
+    dist = torch.empty(n, dtype=torch.int32, device="cuda")
+    sigma = torch.empty(n, dtype=torch.float64, device="cuda") if with_sigma else None
+    delta = torch.empty(n, dtype=torch.float64, device="cuda") if with_delta else None
+    st = _check(lib().sp_bfs_levels(g.handle, int(source), dist.data_ptr(),
+                                    sigma.data_ptr() if sigma is not None else None,
+                                    delta.data_ptr() if delta is not None else None,
+                                    _stream(stream)), "sp_bfs_levels")
+    cut = lambda t: None if t is None else t[:g.n]
+    return dist[:g.n], cut(sigma), cut(delta), st
+
+
+def sp_batch_levels(g: Graph, sources, with_sigma=True, with_delta=True, config=None, stream=None):
+    """Per-source (dist, sigma, delta) of one multi-source pass, shape [len(sources), V]."""
+    torch = _torch()
+    src, p = _host_i32(sources)
+    k = len(src)
+    shape = (k, max(g.n, 1))
+    dist = torch.empty(shape, dtype=torch.int32, device="cuda")
+    sigma = torch.empty(shape, dtype=torch.float64, device="cuda") if with_sigma else None
+    delta = torch.empty(shape, dtype=torch.float64, device="cuda") if with_delta else None
+    st = _check(lib().sp_batch_levels(g.handle, p, k, dist.data_ptr(),
+                                      sigma.data_ptr() if sigma is not None else None,
+                                      delta.data_ptr() if delta is not None else None,
+                                      _config(config), _stream(stream)), "sp_batch_levels")
+    cut = lambda t: None if t is None else t[:, :g.n]
+    return dist[:, :g.n], cut(sigma), cut(delta), st
+
+
+def sp_bc_workspace_bytes(g: Graph, batch_width: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().sp_bc_workspace_bytes(g.handle, batch_width, ctypes.byref(b)), "sp_bc_workspace_bytes")
+    return b.value
+
+
+def sp_autotune(g: Graph, sources, stream=None) -> dict:
+    src, p = _host_i32(sources)
+    c = sp_batch_config()
+    _check(lib().sp_autotune(g.handle, p, len(src), ctypes.byref(c), _stream(stream)), "sp_autotune")
+    return _struct_dict(c)

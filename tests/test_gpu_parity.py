@@ -1,0 +1,246 @@
+"""GPU parity: both HIP paths against the CPU oracle, through the C ABI.
+
+Bar (Appendix Fig. "BC computation in StarPlat", DAG semantics of Section
+2.3.2): distances and level membership bit-exact; path counts bit-exact while
+below 2^53 (they are integers), else within 1e-12 relative; delta and BC
+within 1e-9 relative, and exactly zero where the oracle is zero.
+"""
+from __future__ import annotations
+
+import networkx as nx
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_03317_amd import graphs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+EXACT = 2.0 ** 53
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_03317_amd import sp as spmod
+    spmod.lib()
+    return spmod
+
+
+def assert_bc(got, ref, what=""):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape
+    zero = ref == 0
+    assert np.all(got[zero] == 0), "%s: nonzero where oracle is zero" % what
+    if np.any(~zero):
+        rel = np.abs(got[~zero] - ref[~zero]) / np.abs(ref[~zero])
+        assert rel.max() <= TOL, "%s: max rel err %g" % (what, rel.max())
+
+
+def assert_sigma(got, ref, what=""):
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    small = ref < EXACT
+    assert np.array_equal(got[small], ref[small]), what
+    if np.any(~small):
+        rel = np.abs(got[~small] - ref[~small]) / ref[~small]
+        assert rel.max() <= 1e-12, what
+
+
+def csr_of(G):
+    n = G.number_of_nodes()
+    e = np.array(list(G.edges()), dtype=np.int64).reshape(-1, 2)
+    return graphs.from_edges(n, e[:, 0], e[:, 1])
+
+
+def check_sources_detail(sp, g, rp, ci, srcs):
+    """Per-source dist/sigma/delta: per-source path and one batched pass."""
+    bd, bs, bdl, st = sp.sp_batch_levels(g, srcs)
+    bd, bs, bdl = bd.cpu().numpy(), bs.cpu().numpy(), bdl.cpu().numpy()
+    for i, s in enumerate(srcs):
+        d_ref, sig_ref, del_ref = oracle.source_detail(rp, ci, int(s))
+        d, sig, dl, _ = sp.sp_bfs_levels(g, int(s), with_sigma=True, with_delta=True)
+        assert np.array_equal(d.cpu().numpy(), d_ref), "per-source dist, source %d" % s
+        assert_sigma(sig.cpu().numpy(), sig_ref, "per-source sigma, source %d" % s)
+        dref = np.where(d_ref > 0, del_ref, 0.0)
+        assert_bc(dl.cpu().numpy(), dref, "per-source delta, source %d" % s)
+        assert np.array_equal(bd[i], d_ref), "batched dist, source %d (slot %d)" % (s, i)
+        assert_sigma(bs[i], sig_ref, "batched sigma, source %d" % s)
+        assert_bc(bdl[i], dref, "batched delta, source %d" % s)
+
+
+def both_paths(sp, g, srcs, config=None):
+    a, sa = sp.sp_bc(g, srcs)
+    b, sb = sp.sp_bc_batch(g, srcs, config=config)
+    return a.cpu().numpy(), b.cpu().numpy(), sa, sb
+
+
+# --------------------------------------------------------------------------
+
+def test_workload_uniform_4096_full(sp):
+    """Uniform random, 4,096 vertices, 32,768 edges, 16 sources: everything compared."""
+    rp, ci, src, _ = graphs.workload(1)
+    g = sp.sp_graph_upload(rp, ci, validate=True)
+    check_sources_detail(sp, g, rp, ci, src)
+    ref = oracle.bc(rp, ci, src)
+    a, b, sa, sb = both_paths(sp, g, src)
+    assert sa == sp.SP_OK and sb == sp.SP_OK
+    assert_bc(a, ref, "sp_bc")
+    assert_bc(b, ref, "sp_bc_batch")
+    g.release()
+
+
+@pytest.mark.parametrize("chunk", range(4))
+def test_small_graph_atlas(sp, chunk):
+    """Every 7th graph of the <= 7-vertex atlas, all sources, both paths."""
+    for G in nx.graph_atlas_g()[1 + chunk::28]:
+        rp, ci = csr_of(G)
+        n = len(rp) - 1
+        g = sp.sp_graph_upload(rp, ci, validate=True)
+        srcs = np.arange(n, dtype=np.int32)
+        ref = oracle.bc(rp, ci, srcs)
+        a, b, _, _ = both_paths(sp, g, srcs)
+        assert_bc(a, ref, "sp_bc atlas")
+        assert_bc(b, ref, "sp_bc_batch atlas")
+        check_sources_detail(sp, g, rp, ci, srcs)
+        g.release()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_random_disconnected_with_duplicates(sp, seed):
+    rng = np.random.default_rng(seed)
+    G = nx.disjoint_union(nx.gnm_random_graph(120, 300, seed=seed),
+                          nx.gnm_random_graph(60, 90, seed=seed + 100))
+    G.add_nodes_from(range(180, 185))  # isolated vertices
+    rp, ci = csr_of(G)
+    srcs = rng.integers(0, 185, 70).astype(np.int32)
+    srcs[5] = srcs[6] = 182               # isolated source, listed twice
+    srcs[10] = srcs[11] = srcs[12] = 7    # repeated source
+    g = sp.sp_graph_upload(rp, ci, validate=True)
+    ref = oracle.bc(rp, ci, srcs)
+    a, b, _, _ = both_paths(sp, g, srcs)
+    assert_bc(a, ref, "sp_bc")
+    assert_bc(b, ref, "sp_bc_batch")
+    check_sources_detail(sp, g, rp, ci, srcs[:64])
+    g.release()
+
+
+def test_single_vertex_and_empty_source_list(sp):
+    g = sp.sp_graph_upload(np.array([0, 0], np.int32), np.zeros(0, np.int32))
+    a, b, _, _ = both_paths(sp, g, [0, 0])
+    assert a.tolist() == [0.0] and b.tolist() == [0.0]
+    rp, ci = csr_of(nx.path_graph(9))
+    g2 = sp.sp_graph_upload(rp, ci)
+    a, b, _, _ = both_paths(sp, g2, [])
+    assert np.all(a == 0) and np.all(b == 0)
+    g.release()
+    g2.release()
+
+
+@pytest.mark.parametrize("width", [1, 7, 32, 64])
+def test_batch_widths_and_partial_batches(sp, width):
+    rp, ci = graphs.rmat(12, 16, graphs.RMAT_ABC, 77)
+    srcs = graphs.sources(rp, 100, 78, min_degree=1)
+    g = sp.sp_graph_upload(rp, ci)
+    ref = oracle.bc(rp, ci, srcs)
+    b, sb = sp.sp_bc_batch(g, srcs, config={"batch_width": width})
+    assert sb == sp.SP_OK
+    assert_bc(b.cpu().numpy(), ref, "width %d" % width)
+    g.release()
+
+
+def test_rmat_14_both_paths(sp):
+    rp, ci = graphs.rmat(14, 16, graphs.RMAT_ABC, 5)
+    srcs = graphs.sources(rp, 130, 6, min_degree=1)
+    g = sp.sp_graph_upload(rp, ci)
+    ref = oracle.bc(rp, ci, srcs)
+    a, b, _, _ = both_paths(sp, g, srcs)
+    assert_bc(a, ref, "sp_bc rmat14")
+    assert_bc(b, ref, "sp_bc_batch rmat14")
+    check_sources_detail(sp, g, rp, ci, srcs[:64])
+    g.release()
+
+
+def test_road_grid_128(sp):
+    """High diameter (hundreds of levels) and path counts beyond 2^53."""
+    rp, ci = graphs.road(128, 0.02, 9)
+    srcs = graphs.sources(rp, 20, 10)
+    g = sp.sp_graph_upload(rp, ci)
+    ref = oracle.bc(rp, ci, srcs)
+    a, b, _, _ = both_paths(sp, g, srcs)
+    assert_bc(a, ref, "sp_bc road")
+    assert_bc(b, ref, "sp_bc_batch road")
+    check_sources_detail(sp, g, rp, ci, srcs)
+    g.release()
+
+
+def test_full_grid_sigma_is_binomial(sp):
+    import math
+    W = 40
+    G = nx.convert_node_labels_to_integers(nx.grid_2d_graph(W, W), ordering="sorted")
+    rp, ci = csr_of(G)
+    g = sp.sp_graph_upload(rp, ci)
+    d, sig, _, _ = sp.sp_bfs_levels(g, 0)
+    _, bs, _, _ = sp.sp_batch_levels(g, [0, W * W - 1])
+    exp = np.array([float(math.comb(i + j, i)) for i in range(W) for j in range(W)])
+    assert np.array_equal(d.cpu().numpy(), np.add.outer(np.arange(W), np.arange(W)).ravel())
+    assert_sigma(sig.cpu().numpy(), exp, "per-source grid sigma")
+    assert_sigma(bs[0].cpu().numpy(), exp, "batched grid sigma")
+    g.release()
+
+
+@pytest.mark.parametrize("k,flag", [(996, False), (997, True), (1030, True)])
+def test_sigma_overflow_flag(sp, k, flag):
+    edges = []
+    for i in range(k):
+        a, b, c, d = 3 * i, 3 * i + 1, 3 * i + 2, 3 * i + 3
+        edges += [(a, b), (a, c), (b, d), (c, d)]
+    e = np.array(edges)
+    n = 3 * k + 1
+    rp, ci = graphs.from_edges(n, e[:, 0], e[:, 1])
+    g = sp.sp_graph_upload(rp, ci)
+    want = sp.SP_WARN_SIGMA_LARGE if flag else sp.SP_OK
+    _, sa = sp.sp_bc(g, [0])
+    _, sb = sp.sp_bc_batch(g, [0, n - 1])
+    assert sa == want and sb == want
+    if not flag:
+        ref = oracle.bc(rp, ci, [0, n - 1])
+        assert_bc(sp.sp_bc(g, [0, n - 1])[0].cpu().numpy(), ref)
+        assert_bc(sp.sp_bc_batch(g, [0, n - 1])[0].cpu().numpy(), ref)
+    g.release()
+
+
+def test_runs_are_bit_identical(sp):
+    rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 12)
+    srcs = graphs.sources(rp, 70, 13, min_degree=1)
+    g = sp.sp_graph_upload(rp, ci)
+    a1, b1, _, _ = both_paths(sp, g, srcs)
+    a2, b2, _, _ = both_paths(sp, g, srcs)
+    assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    g.release()
+
+
+def test_invalid_source_leaves_output_untouched(sp):
+    import torch
+    rp, ci = csr_of(nx.path_graph(10))
+    g = sp.sp_graph_upload(rp, ci)
+    out = torch.full((10,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(sp.SpError) as ei:
+        sp.sp_bc(g, [0, 10], out_bc=out)
+    assert ei.value.status == sp.SP_ERR_INVALID_ARGUMENT
+    with pytest.raises(sp.SpError):
+        sp.sp_bc_batch(g, [-1], out_bc=out)
+    assert torch.all(out == 7.0)
+    g.release()
+
+
+def test_upload_validation(sp):
+    rp = np.array([0, 1, 1], np.int32)
+    ci = np.array([1], np.int32)          # 0->1 without 1->0
+    with pytest.raises(sp.SpError):
+        sp.sp_graph_upload(rp, ci, validate=True)
+    with pytest.raises(sp.SpError):       # id out of range: caught on the device
+        sp.sp_graph_upload(np.array([0, 1, 2], np.int32), np.array([1, 5], np.int32))
