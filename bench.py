@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Benchmark: batched betweenness centrality on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: sp_bc_batch
+on the workload's full source list (per-batch init, level-synchronous
+multi-source forward pass, reverse pass, BC accumulation, sigma overflow
+check), with the graph already resident in HBM.  The graph is built and
+uploaded once before timing; upload time is reported separately.
+
+Default workload: RMAT scale 22 (4,194,304 vertices, edge factor 16,
+a/b/c = 0.57/0.19/0.19, deduplicated, relabelled), 1,024 seeded sources among
+vertices of degree >= 1, batches of 64.  TEPS = sources x undirected edges /
+step time.  Also reported: the per-source GPU path on a sample of the same
+sources (the "batched vs per-source" ratio), the dominant kernel's achieved
+algorithmic bandwidth against the HBM peak, and the CPU oracle on a bounded
+sample of the same sources (which doubles as a parity check of this run).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "BC TEPS (sources×edges/s) batched vs per-source at 1e-9 rel err; p99 latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {"uniform-4096": 1, "rmat-20": 2, "rmat-22": 3, "road-4096": 4}
+
+# Algorithmic bytes per unit of work, per kernel family (units counted on the
+# device while timing): items = vertices (per-source) or (vertex, level)
+# entries (batched); edges = adjacency entries scanned; pairs = DAG edges
+# (per-source) or (slot, DAG edge) pairs (batched); item_slots = slots over
+# entries (batched).
+BYTE_MODEL = {
+    "ms_sigma": dict(items=68, edges=20, pairs=8, item_slots=8),
+    "ms_delta": dict(items=36, edges=20, pairs=16, item_slots=16),
+    "ms_topdown": dict(items=20, edges=20),
+    "ms_bottomup": dict(items=16, edges=20),
+    "ms_bc": dict(items=24, item_slots=8),
+    "src_topdown": dict(items=12, edges=8),
+    "src_bottomup": dict(items=12, edges=8),
+    "src_sigma": dict(items=20, edges=8, pairs=8),
+    "src_delta": dict(items=44, edges=8, pairs=16),
+}
+
+
+def algorithmic_bytes(name, prof):
+    model = BYTE_MODEL.get(name, {})
+    return sum(coef * prof.get(unit, 0) for unit, coef in model.items())
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat-22", choices=sorted(WORKLOADS))
+    ap.add_argument("--sources", type=int, default=None, help="override the workload's source count")
+    ap.add_argument("--batch-width", type=int, default=0)
+    ap.add_argument("--per-source-sample", type=int, default=32,
+                    help="sources timed through the per-source path (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=4,
+                    help="sources timed through the CPU oracle (0 = skip)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(BC over a source set would shard sources across GPUs and all-reduce BC; "
+              "not implemented here).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_03317_amd import graphs, sp
+    if not os.path.exists(sp.LIB_PATH):
+        from paper_2305_03317_amd import _build
+        _build.build_all()
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    k = WORKLOADS[args.workload]
+
+    t0 = time.perf_counter()
+    rp, ci, src, spec = graphs.workload(k, args.sources)
+    gen_s = time.perf_counter() - t0
+    n = len(rp) - 1
+    m = len(ci) // 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sp.sp_graph_upload(rp, ci)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t0) * 1e3
+    cfg = {"batch_width": args.batch_width} if args.batch_width else None
+
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
+    torch.cuda.synchronize()
+
+    sp.sp_profile_enable(True)
+    sp.sp_profile_read()  # discard warmup counts
+    times, dev_ms, statuses = [], [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        dev_ms.append(sp.sp_get_last_stats()["device_ms"])
+        statuses.append(st)
+        print("step %d: %.1f ms" % (len(times), times[-1] * 1e3), file=sys.stderr, flush=True)
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    stats = sp.sp_get_last_stats()
+    step_s = float(np.mean(times))
+    value = len(src) * m / step_s
+
+    # dominant kernel: most time inside the timed region
+    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"]) if prof else None
+    roofline = None
+    if dom:
+        name, p = dom
+        achieved = algorithmic_bytes(name, p) / (p["total_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "launches": p["launches"],
+                    "avg_launch_ms": round(p["total_ms"] / max(p["launches"], 1), 4),
+                    "algorithmic_bytes_per_launch": int(algorithmic_bytes(name, p) / max(p["launches"], 1))}
+    kernels = {kname: {"launches": p["launches"], "total_ms": round(p["total_ms"], 3),
+                       "GBps_algorithmic": round(algorithmic_bytes(kname, p) / max(p["total_ms"], 1e-9) / 1e6, 1)}
+               for kname, p in prof.items()}
+
+    # per-source GPU path on a sample of the same sources
+    per_source = None
+    if args.per_source_sample > 0:
+        ps_src = src[:args.per_source_sample]
+        sp.sp_bc(g, ps_src[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp.sp_bc(g, ps_src)
+        torch.cuda.synchronize()
+        ps_s = time.perf_counter() - t0
+        per_source = {"sources": len(ps_src), "teps": len(ps_src) * m / ps_s,
+                      "ms_per_source": ps_s * 1e3 / len(ps_src)}
+
+    # CPU oracle on a bounded sample (also a parity check at full size)
+    cpu = None
+    parity = None
+    if args.cpu_sample > 0:
+        import oracle
+        oracle.build()
+        cs = src[:args.cpu_sample]
+        t0 = time.perf_counter()
+        ref = oracle.bc(rp, ci, cs)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+               "sample": "first %d of the %d sources, single-threaded C oracle, %.1f s"
+                         % (len(cs), len(src), cpu_s)}
+        got, _ = sp.sp_bc_batch(g, cs, config=cfg)
+        got = got.cpu().numpy()
+        nz = ref != 0
+        rel = float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
+        parity = {"sources": len(cs), "max_rel_err": rel, "zero_exact": bool(np.all(got[~nz] == 0)),
+                  "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s batched BC" % spec["name"], "vertices": n, "undirected_edges": m,
+                   "nnz": len(ci), "sources": len(src), "batch_width": stats["batch_width"],
+                   "graph_seed": spec["graph_seed"], "source_seed": spec["source_seed"],
+                   "levels_max": stats["max_levels"], "topdown_levels": stats["topdown_levels"],
+                   "bottomup_levels": stats["bottomup_levels"]},
+        "device_ms_per_step": float(np.mean(dev_ms)),
+        "status": max(statuses),
+        "upload_ms": upload_ms,
+        "graph_build_s": gen_s,
+        "per_source_path": per_source,
+        "batched_over_per_source": (value / per_source["teps"]) if per_source else None,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    g.release()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -192,6 +192,30 @@ sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_sources,
                       sp_batch_config *out, sp_stream s);
 
 /* ------------------------------------------------------------------------
+ * Kernel timing (measurement support)
+ * ------------------------------------------------------------------------ */
+
+/* Per kernel family: launches, HIP-event time, and the work it did. */
+typedef struct sp_kernel_profile {
+    char name[32];      /* kernel family, e.g. "ms_delta" */
+    int64_t launches;
+    double total_ms;    /* sum over launches of the time between HIP events recorded
+                           on the launch stream immediately before and after it */
+    int64_t items;      /* vertices (per-source path) or (vertex, level) entries (batched) */
+    int64_t edges;      /* adjacency entries scanned */
+    int64_t pairs;      /* DAG edges accumulated (per-source) or (slot, DAG edge) pairs (batched) */
+    int64_t item_slots; /* batched: sum over entries of their slot count; per-source: = items */
+} sp_kernel_profile;
+
+/* Turn timing on or off for all later launches of this process (off by
+ * default; on adds two event records per launch). */
+sp_status sp_profile_enable(int32_t on);
+
+/* Synchronise every stream used, write up to `cap` families with at least one
+ * launch into out[], their count into *n_out, and reset the totals. */
+sp_status sp_profile_read(sp_kernel_profile *out, int32_t cap, int32_t *n_out);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching over several resident graphs
  * ------------------------------------------------------------------------ */
 

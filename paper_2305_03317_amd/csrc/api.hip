@@ -418,7 +418,14 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     dev_free(bad);
     bad = nullptr;
     int32_t md = 0;
-    for (int32_t v = 0; v < n_vertices; ++v) md = std::max(md, deg_rp[v + 1] - deg_rp[v]);
+    for (int32_t v = 0; v < n_vertices; ++v) {
+        const int32_t d = deg_rp[v + 1] - deg_rp[v];
+        md = std::max(md, d);
+        if (d > kHubDeg) {
+            g->n_hubs++;
+            g->hub_chunks += (d + kHubChunk - 1) / kHubChunk;
+        }
+    }
     g->max_degree = md;
     g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
     *out = g;
@@ -664,7 +671,7 @@ sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes) 
         set_error("sp_bc_workspace_bytes: bad arguments");
         return SP_ERR_INVALID_ARGUMENT;
     }
-    *bytes = batch_ws_bytes(g->n, initial_qcap(g->n, batch_width), std::max(g->n, 1) + 2);
+    *bytes = batch_ws_bytes(g, initial_qcap(g->n, batch_width));
     return SP_OK;
 }
 

@@ -62,6 +62,8 @@ struct sp_graph_s {
     int32_t *row_ptr = nullptr;  // device, n + 1
     int32_t *col_idx = nullptr;  // device, nnz (>= 1 element allocated)
     int32_t max_degree = 0;
+    int32_t n_hubs = 0;          // vertices of degree > kHubDeg
+    int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
     size_t bytes = 0;
     std::mutex mu;               // guards `tuned` and the workspace pools
     sp::TuneEntry tuned;
@@ -80,6 +82,23 @@ sp_stats &tls_stats();
 // it, and the host reads it back once per chunk of levels.
 // ---------------------------------------------------------------------------
 enum : int32_t { MODE_TOPDOWN = 0, MODE_BOTTOMUP = 1 };
+
+// Vertices with more than kHubDeg neighbours ("hubs") are not reduced by one
+// wave: their adjacency is cut into chunks of kHubChunk entries, each chunk is
+// reduced by its own wave into a partial, and the last chunk to finish sums
+// the partials in chunk order.  The result depends only on the degree, not on
+// scheduling.
+constexpr int32_t kHubDeg = 1024;
+constexpr int32_t kHubChunk = 1024;
+
+// One hub occurrence on a level: vertex, its queue entry, and the range of
+// level-local chunk ids [chunk_base, chunk_base + nchunks).
+struct HubEntry {
+    int32_t v;
+    int32_t entry;
+    int32_t chunk_base;
+    int32_t nchunks;
+};
 
 struct LevelCtl {
     int32_t level;      // level of the current frontier
@@ -102,9 +121,32 @@ struct LevelCtl {
     int32_t n_vertices;
     int32_t topdown_levels, bottomup_levels;
     int32_t pad1;
+    // Hubs: entries of the level being built are appended at hub_next, with
+    // hub_pack = (count << 40) | chunks accumulating; `advance` turns them into
+    // the current level's segment [hub_lo, hub_hi) with hub_nchunks chunks.
+    unsigned long long hub_pack;
+    int32_t hub_lo, hub_hi, hub_nchunks, hub_next;
 };
 
-constexpr int kMaxLevelsHost = 1 << 22;  // sanity bound on BFS depth (V < 2^31)
+// Measurement: kernel families timed with HIP events when profiling is on,
+// each with device counters of the work it did.
+enum ProfKind : int {
+    P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_DELTA,
+    P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_DELTA, P_MS_BC, P_COUNT
+};
+constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
+extern const char *const kProfNames[P_COUNT];
+bool prof_enabled();
+unsigned long long *prof_counters(int kind);  // device u64[kProfCounters], null when off
+class ProfScope {
+  public:
+    ProfScope(int kind, hipStream_t s);
+    ~ProfScope();
+  private:
+    int kind_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr;
+};
 
 // Launch shape helpers.
 int device_cu_count();
@@ -122,6 +164,11 @@ struct SourceWorkspace {
     int32_t *queue = nullptr;
     int32_t *level_off = nullptr;  // device, levels + 2
     int32_t level_cap = 0;
+    HubEntry *hub_list = nullptr;  // device, n_hubs + 1 (a hub occurs once per source)
+    int32_t *hub_off = nullptr;    // device, levels + 2: hub segment of each level
+    int32_t *hub_lvl_chunks = nullptr;  // device, levels + 1: chunk count of each level
+    unsigned int *hub_cnt = nullptr;    // device, n_hubs + 1: finished chunks per hub
+    double *partial = nullptr;     // device, hub_chunks + 1
     LevelCtl *ctl = nullptr;       // device
     LevelCtl *ctl_host = nullptr;  // pinned mirror
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -164,6 +211,12 @@ struct BatchWorkspace {
     int32_t *level_off = nullptr;        // device, level_cap + 2
     int32_t level_cap = 0;
     int32_t *slot_src = nullptr;         // device, 64: source vertex of each slot (-1 = empty)
+    HubEntry *hub_list = nullptr;        // device, hub_cap entries
+    int64_t hub_cap = 0;
+    int32_t *hub_off = nullptr;          // device, level_cap: hub segment of each level
+    int32_t *hub_lvl_chunks = nullptr;   // device, level_cap
+    unsigned int *hub_cnt = nullptr;     // device, n_hubs + 1
+    double *partial = nullptr;           // device, (hub_chunks + 1) x 64
     LevelCtl *ctl = nullptr;
     LevelCtl *ctl_host = nullptr;
     void *staging = nullptr;             // pinned: level-0 entries and slot sources
@@ -171,7 +224,7 @@ struct BatchWorkspace {
     size_t bytes = 0;
     std::vector<int32_t> kept_off;       // level offsets of the last pass (host copy)
 };
-size_t batch_ws_bytes(int32_t n, int64_t qcap, int32_t level_cap);
+size_t batch_ws_bytes(sp_graph g, int64_t qcap);
 sp_status batch_ws_create(sp_graph g, int64_t qcap, BatchWorkspace &ws);
 void batch_ws_destroy(BatchWorkspace &ws);
 

@@ -162,3 +162,119 @@ __device__ __forceinline__ void block_add_u64(unsigned long long x, unsigned lon
 }
 
 }  // namespace sp
+
+namespace sp {
+
+// Per-wave LDS scratch for the chunked reductions below (64 entries each).
+struct WaveScratch {
+    int32_t *coff;  // first chunk index of each lane's vertex
+    int32_t *beg;   // adjacency start
+    int32_t *deg;   // adjacency length (0 = nothing to do)
+    double *acc;    // running sum of each lane's vertex
+    double *val;    // per-vertex operand the term may read (e.g. sigma[v])
+};
+
+// Wave-level sum over the adjacency of up to 64 vertices, one per lane.
+// Every vertex's adjacency is cut into chunks of 8 entries aligned at its row
+// start.  A step gives 8 chunks to 8 groups of 8 lanes (one entry per lane),
+// folds each chunk with a fixed xor tree, and adds the chunk sums to the
+// vertex's running sum in chunk order.  The result therefore depends only on
+// the vertex's own adjacency, not on the lane or wave that handled it, and the
+// lanes stay busy whatever the degree mix.  term(e, owner) is the
+// contribution of adjacency entry e of the vertex held by lane `owner`.
+template <class Term>
+__device__ __forceinline__ double wave_chunk_sum(int32_t beg, int32_t deg, const WaveScratch &ws,
+                                                 Term term) {
+    const int lane = lane_id();
+    const int32_t nch = (deg + 7) >> 3;
+    const int32_t incl = wave_incl_scan(nch);
+    const int32_t total = __shfl(incl, kWave - 1, kWave);
+    ws.coff[lane] = incl - nch;
+    ws.beg[lane] = beg;
+    ws.deg[lane] = deg;
+    ws.acc[lane] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    const int g = lane >> 3, j = lane & 7;
+    for (int32_t t0 = 0; t0 < total; t0 += 8) {
+        const int32_t k = t0 + g;
+        int32_t a = -1;
+        double x = 0.0;
+        if (k < total) {
+            int32_t lo = 0, hi = kWave - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (ws.coff[mid] <= k) lo = mid; else hi = mid - 1;
+            }
+            a = lo;
+            const int32_t off = (k - ws.coff[a]) * 8 + j;
+            if (off < ws.deg[a]) x = term(ws.beg[a] + off, a);
+        }
+        x += __shfl_xor(x, 1, kWave);
+        x += __shfl_xor(x, 2, kWave);
+        x += __shfl_xor(x, 4, kWave);
+        int32_t ag[8];
+        double xg[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ag[q] = __shfl(a, q * 8, kWave);
+            xg[q] = __shfl(x, q * 8, kWave);
+        }
+        const int32_t a_prev = __shfl(a, ((g + 7) & 7) * 8, kWave);
+        if (j == 0 && a >= 0 && (g == 0 || a_prev != a)) {
+            double s = ws.acc[a];
+            bool run = true;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q >= g) {
+                    if (run && ag[q] == a) s += xg[q];
+                    else run = false;
+                }
+            ws.acc[a] = s;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_wave_barrier();
+    return ws.acc[lane];
+}
+
+// Wave-level "any": does some adjacency entry of each lane's vertex satisfy
+// pred?  Same chunking as wave_chunk_sum; a vertex stops loading entries in
+// the step after one is found.
+template <class Pred>
+__device__ __forceinline__ bool wave_chunk_any(int32_t beg, int32_t deg, const WaveScratch &ws,
+                                               Pred pred) {
+    const int lane = lane_id();
+    const int32_t nch = (deg + 7) >> 3;
+    const int32_t incl = wave_incl_scan(nch);
+    const int32_t total = __shfl(incl, kWave - 1, kWave);
+    ws.coff[lane] = incl - nch;
+    ws.beg[lane] = beg;
+    ws.deg[lane] = deg;
+    ws.acc[lane] = 0.0;  // 1.0 once found
+    __builtin_amdgcn_wave_barrier();
+    const int g = lane >> 3, j = lane & 7;
+    for (int32_t t0 = 0; t0 < total; t0 += 8) {
+        const int32_t k = t0 + g;
+        int32_t a = -1;
+        bool hit = false;
+        if (k < total) {
+            int32_t lo = 0, hi = kWave - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (ws.coff[mid] <= k) lo = mid; else hi = mid - 1;
+            }
+            a = lo;
+            const int32_t off = (k - ws.coff[a]) * 8 + j;
+            if (off < ws.deg[a] && ws.acc[a] == 0.0) hit = pred(ws.beg[a] + off, a);
+        }
+        if (hit) ws.acc[a] = 1.0;  // several lanes may store the same value
+        __builtin_amdgcn_wave_barrier();
+        // stop once every vertex with work is found
+        const bool open = nch > 0 && ws.acc[lane] == 0.0;
+        if (!__ballot(open)) break;
+    }
+    __builtin_amdgcn_wave_barrier();
+    return ws.acc[lane] != 0.0;
+}
+
+}  // namespace sp

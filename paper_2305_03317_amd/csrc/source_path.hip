@@ -5,26 +5,29 @@
 //   discover: the next frontier F_{l+1} = unreached vertices adjacent to F_l,
 //             either top-down (scan the adjacency of F_l, claim with a CAS on
 //             dist) or bottom-up (every unreached vertex scans its own
-//             adjacency and stops at the first neighbour in F_l);
+//             adjacency and stops once it finds a neighbour in F_l);
 //   sigma:    every w in F_{l+1} sums sigma over its DAG parents (neighbours
-//             at level l) -- a pull, so no floating-point atomics and a fixed
-//             summation order;
+//             at level l) -- a pull, so no floating-point atomics;
 //   advance:  one thread moves the frontier window and picks the direction of
 //             the next level from the frontier's and the unreached vertices'
-//             adjacency sizes.
+//             adjacency sizes;
+//   sigma_hub: path counts of the new level's hubs (see kHubDeg), chunk by
+//             chunk.
 // The queue holds the vertices in level order; level_off[l] is where level l
 // starts, so the reverse pass replays the levels without a second BFS.
 //
 // Reverse ("iterateInReverse"): for l = L-1 down to 1 each v in F_l sums
-// (sigma[v] / sigma[w]) * (1 + delta[w]) over its DAG children w (level l+1),
-// in CSR order for vertices handled by one lane, and adds delta[v] to BC[v].
-// The source (level 0) is skipped.
+// (sigma[v] / sigma[w]) * (1 + delta[w]) over its DAG children w (level l+1)
+// and adds delta[v] to BC[v]; the source (level 0) is skipped.  Sums are
+// formed chunk by chunk in a fixed order (wave_chunk_sum), so every vertex's
+// value is independent of where it sits in the queue.
 //
 // Level loops run on the device: the host enqueues a chunk of levels, whose
 // kernels return at once after the control block says `done`, and reads the
 // control block back once per chunk.
 #include "common.h"
 #include "devutil.h"
+#include "levels.h"
 
 namespace sp {
 
@@ -61,7 +64,8 @@ sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
 // Kernels
 // ---------------------------------------------------------------------------
 __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *queue,
-                           int32_t *level_off, const int32_t *rp, int32_t src, int32_t n,
+                           int32_t *level_off, HubEntry *hub_list, int32_t *hub_off,
+                           int32_t *hub_lvl_chunks, const int32_t *rp, int32_t src, int32_t n,
                            long long nnz, double alpha, double beta) {
     const int32_t deg = rp[src + 1] - rp[src];
     c->level = 0;
@@ -74,13 +78,26 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     c->front_deg = (unsigned long long)deg;
     c->next_deg = 0;
     c->unset_deg = (unsigned long long)(nnz - deg);
+    c->reached_pairs = 1;
     c->sigma_max_bits = (unsigned long long)__double_as_longlong(1.0);
     c->flagged_slots = 0;
+    c->settled_deg = 0;
     c->alpha = alpha;
     c->beta = beta;
     c->n_vertices = n;
     c->topdown_levels = 0;
     c->bottomup_levels = 0;
+    const bool hub = deg > kHubDeg;
+    const int32_t nch = hub ? (deg + kHubChunk - 1) / kHubChunk : 0;
+    if (hub) hub_list[0] = HubEntry{src, 0, 0, nch};
+    c->hub_pack = 0;
+    c->hub_lo = 0;
+    c->hub_hi = hub ? 1 : 0;
+    c->hub_nchunks = nch;
+    c->hub_next = c->hub_hi;
+    hub_off[0] = 0;
+    hub_off[1] = c->hub_hi;
+    hub_lvl_chunks[0] = nch;
     dist[src] = 0;
     sigma[src] = 1.0;
     queue[0] = src;
@@ -88,138 +105,174 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     level_off[1] = 1;
 }
 
-// Top-down discovery: the block takes BS frontier vertices, scans their
-// degrees, and walks the concatenated adjacency BS entries at a time, so
-// every lane has one edge regardless of the degree mix.
+// Top-down discovery.  blockIdx.y == 0: the block takes BS frontier vertices
+// (hubs excluded), scans their degrees, and walks the concatenated adjacency BS
+// entries at a time, one entry per lane.  blockIdx.y == 1: blocks walk the
+// chunks of the frontier's hubs.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_src_topdown(LevelCtl *c, const int32_t *__restrict__ rp,
                                                     const int32_t *__restrict__ ci, int32_t *dist,
-                                                    int32_t *queue) {
+                                                    int32_t *queue,
+                                                    const HubEntry *__restrict__ hub_list,
+                                                    unsigned long long *prof) {
     if (c->done || c->mode != MODE_TOPDOWN) return;
     __shared__ int32_t s_beg[BS], s_off[BS], s_scan[BS / kWave + 1];
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
+    __shared__ unsigned long long s_red[1];
     StagedQueue<BS, 4 * BS> q;
     q.init(s_qbuf, s_meta);
     const int32_t lo = c->lo, hi = c->hi, nl = c->level + 1, n = c->n_vertices;
-    for (int32_t b = lo + blockIdx.x * BS; b < hi; b += gridDim.x * BS) {
-        const int32_t i = b + threadIdx.x;
-        int32_t beg = 0, deg = 0;
-        if (i < hi) {
-            const int32_t v = queue[i];
-            beg = rp[v];
-            deg = rp[v + 1] - beg;
-        }
-        int32_t total;
-        const int32_t off = block_excl_scan<BS>(deg, s_scan, &total);
-        s_beg[threadIdx.x] = beg;
-        s_off[threadIdx.x] = off;
-        __syncthreads();
-        for (int32_t k0 = 0; k0 < total; k0 += BS) {
-            const int32_t k = k0 + threadIdx.x;
-            bool claim = false;
-            int32_t w = 0;
-            if (k < total) {
-                int32_t a = 0, z = BS - 1;  // last j with s_off[j] <= k
-                while (a < z) {
-                    const int32_t mid = (a + z + 1) >> 1;
-                    if (s_off[mid] <= k) a = mid; else z = mid - 1;
-                }
-                w = ci[s_beg[a] + (k - s_off[a])];
-                if (dist[w] < 0) claim = atomicCAS(&dist[w], -1, nl) == -1;
+    unsigned long long my_items = 0, my_edges = 0;
+    if (blockIdx.y == 0) {
+        for (int32_t b = lo + blockIdx.x * BS; b < hi; b += gridDim.x * BS) {
+            const int32_t i = b + threadIdx.x;
+            int32_t beg = 0, deg = 0;
+            if (i < hi) {
+                const int32_t v = queue[i];
+                beg = rp[v];
+                deg = rp[v + 1] - beg;
+                if (deg > kHubDeg) deg = 0;  // chunks handled by blockIdx.y == 1
+                ++my_items;
+                my_edges += deg;
             }
-            q.stage(claim, w, &c->tail, queue, n, &c->overflow);
+            int32_t total;
+            const int32_t off = block_excl_scan<BS>(deg, s_scan, &total);
+            s_beg[threadIdx.x] = beg;
+            s_off[threadIdx.x] = off;
+            __syncthreads();
+            for (int32_t k0 = 0; k0 < total; k0 += BS) {
+                const int32_t k = k0 + threadIdx.x;
+                bool claim = false;
+                int32_t w = 0;
+                if (k < total) {
+                    int32_t a = 0, z = BS - 1;  // last j with s_off[j] <= k
+                    while (a < z) {
+                        const int32_t mid = (a + z + 1) >> 1;
+                        if (s_off[mid] <= k) a = mid; else z = mid - 1;
+                    }
+                    w = ci[s_beg[a] + (k - s_off[a])];
+                    if (dist[w] < 0) claim = atomicCAS(&dist[w], -1, nl) == -1;
+                }
+                q.stage(claim, w, &c->tail, queue, n, &c->overflow);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        const int32_t hlo = c->hub_lo, hhi = c->hub_hi, nch = c->hub_nchunks;
+        for (int32_t k = blockIdx.x; k < nch; k += gridDim.x) {
+            const HubEntry h = hub_list[hub_find(hub_list, hlo, hhi, k)];
+            const int32_t beg = rp[h.v] + (k - h.chunk_base) * kHubChunk;
+            const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+            my_edges += (threadIdx.x == 0) ? (unsigned long long)(end - beg) : 0ull;
+            for (int32_t e0 = beg; e0 < end; e0 += BS) {
+                const int32_t e = e0 + threadIdx.x;
+                bool claim = false;
+                int32_t w = 0;
+                if (e < end) {
+                    w = ci[e];
+                    if (dist[w] < 0) claim = atomicCAS(&dist[w], -1, nl) == -1;
+                }
+                q.stage(claim, w, &c->tail, queue, n, &c->overflow);
+            }
+        }
     }
     q.finish(&c->tail, queue, n, &c->overflow);
+    flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
-// Bottom-up discovery: each unreached vertex looks for any neighbour on the
-// current level and stops at the first one.
+// Bottom-up discovery: every unreached vertex looks for a neighbour on the
+// current level, 8 entries per lane group, and stops once it finds one.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_src_bottomup(LevelCtl *c, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, int32_t *dist,
-                                                     int32_t *queue) {
+                                                     int32_t *queue, unsigned long long *prof) {
     if (c->done || c->mode != MODE_BOTTOMUP) return;
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
+    __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
+    __shared__ double s_acc[BS];
+    __shared__ unsigned long long s_red[1];
     StagedQueue<BS, 4 * BS> q;
     q.init(s_qbuf, s_meta);
+    const int wbase = threadIdx.x & ~(kWave - 1);
+    const WaveScratch ws{s_coff + wbase, s_beg + wbase, s_deg + wbase, s_acc + wbase, nullptr};
     const int32_t lvl = c->level, n = c->n_vertices;
+    unsigned long long my_items = 0, my_edges = 0;
     for (int32_t b = blockIdx.x * BS; b < n; b += gridDim.x * BS) {
         const int32_t v = b + threadIdx.x;
-        bool found = false;
+        int32_t beg = 0, deg = 0;
         if (v < n && dist[v] < 0) {
-            const int32_t end = rp[v + 1];
-            for (int32_t e = rp[v]; e < end; ++e)
-                if (dist[ci[e]] == lvl) {
-                    found = true;
-                    break;
-                }
+            beg = rp[v];
+            deg = rp[v + 1] - beg;
+            ++my_items;
         }
+        const bool found = wave_chunk_any(beg, deg, ws, [&](int32_t e, int32_t) {
+            return dist[ci[e]] == lvl;
+        });
+        my_edges += deg;
         if (found) dist[v] = lvl + 1;
         q.stage(found, v, &c->tail, queue, n, &c->overflow);
     }
     q.finish(&c->tail, queue, n, &c->overflow);
+    flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
 // Path counts of the new frontier: sigma[w] = sum of sigma[u] over neighbours
-// u on the current level.  A lane owns a vertex of small degree and sums in
-// CSR order; larger vertices are summed by the whole wave.
+// u on the current level.  Hubs are registered for k_src_sigma_hub.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci,
                                                   const int32_t *__restrict__ queue,
-                                                  const int32_t *__restrict__ dist, double *sigma) {
+                                                  const int32_t *__restrict__ dist, double *sigma,
+                                                  HubEntry *hub_list, long long hub_cap,
+                                                  unsigned long long *prof) {
     if (c->done) return;
+    __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
+    __shared__ double s_acc[BS];
     __shared__ unsigned long long s_red[1];
-    const int32_t lvl = c->level, hi = c->hi, tail = c->tail;
+    const int wbase = threadIdx.x & ~(kWave - 1);
+    const WaveScratch ws{s_coff + wbase, s_beg + wbase, s_deg + wbase, s_acc + wbase, nullptr};
+    const int32_t lvl = c->level, hi = c->hi, tail = min(c->tail, c->n_vertices);
     const int lane = lane_id();
-    unsigned long long my_deg = 0;
+    unsigned long long my_deg = 0, my_items = 0, my_pairs = 0;
     double my_max = 0.0;
     bool large = false;
     for (int32_t b = hi + (int32_t)(blockIdx.x * BS + threadIdx.x) - lane; b < tail;
          b += gridDim.x * BS) {
         const int32_t i = b + lane;
-        int32_t w = -1, beg = 0, end = 0;
+        int32_t w = -1, beg = 0, deg = 0;
         if (i < tail) {
             w = queue[i];
             beg = rp[w];
-            end = rp[w + 1];
+            deg = rp[w + 1] - beg;
         }
-        const bool big = (end - beg) > kWave;
-        double s = 0.0;
-        if (w >= 0 && !big)
-            for (int32_t e = beg; e < end; ++e) {
-                const int32_t u = ci[e];
-                if (dist[u] == lvl) s += sigma[u];
-            }
-        unsigned long long bm = __ballot(w >= 0 && big);
-        while (bm) {
-            const int j = __ffsll((long long)bm) - 1;
-            bm &= bm - 1;
-            const int32_t bj = shfl_i32(beg, j), ej = shfl_i32(end, j);
-            double part = 0.0;
-            for (int32_t e = bj + lane; e < ej; e += kWave) {
-                const int32_t u = ci[e];
-                if (dist[u] == lvl) part += sigma[u];
-            }
-            part = wave_sum_f64(part);
-            if (lane == j) s = part;
-        }
+        const bool hub = deg > kHubDeg;
+        const double s = wave_chunk_sum(beg, hub ? 0 : deg, ws, [&](int32_t e, int32_t) {
+            const int32_t u = ci[e];
+            if (dist[u] != lvl) return 0.0;
+            ++my_pairs;
+            return sigma[u];
+        });
         if (w >= 0) {
-            sigma[w] = s;
-            my_deg += (unsigned long long)(end - beg);
-            my_max = fmax(my_max, s);
-            large |= sigma_is_large(s);
+            my_deg += (unsigned long long)deg;
+            ++my_items;
+            if (hub) {
+                hub_register(c, hub_list, hub_cap, w, i, deg);
+            } else {
+                sigma[w] = s;
+                my_max = fmax(my_max, s);
+                large |= sigma_is_large(s);
+            }
         }
     }
     my_max = wave_max_f64(my_max);
     if (lane == 0) atomic_max_nonneg_f64(&c->sigma_max_bits, my_max);
     if (__ballot(large) && lane == 0) atomicOr(&c->flagged_slots, 1ull);
     block_add_u64<BS>(my_deg, s_red, &c->next_deg);
+    flush_counters<BS>(prof, my_items, my_deg, my_pairs, s_red);
 }
 
-__global__ void k_src_advance(LevelCtl *c, int32_t *level_off) {
+__global__ void k_src_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
+                              int32_t *hub_lvl_chunks) {
     if (c->done) return;
     if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
     const int32_t nf = c->tail - c->hi;
@@ -227,13 +280,23 @@ __global__ void k_src_advance(LevelCtl *c, int32_t *level_off) {
         c->done = 1;
         return;
     }
-    level_off[c->level + 2] = c->tail;
+    const int32_t nl = c->level + 1;
+    level_off[nl + 1] = c->tail;
+    const unsigned long long hp = c->hub_pack;
+    c->hub_lo = c->hub_next;
+    c->hub_hi = c->hub_next + (int32_t)(hp >> 40);
+    c->hub_nchunks = (int32_t)(hp & ((1ull << 40) - 1));
+    c->hub_next = c->hub_hi;
+    c->hub_pack = 0;
+    hub_off[nl + 1] = c->hub_hi;
+    hub_lvl_chunks[nl] = c->hub_nchunks;
     c->front_deg = c->next_deg;
     c->unset_deg -= c->next_deg;
     c->next_deg = 0;
+    c->reached_pairs += (unsigned long long)nf;
     c->lo = c->hi;
     c->hi = c->tail;
-    c->level += 1;
+    c->level = nl;
     if (c->mode == MODE_TOPDOWN) {
         if ((double)c->front_deg * c->alpha > (double)c->unset_deg) c->mode = MODE_BOTTOMUP;
     } else {
@@ -241,7 +304,67 @@ __global__ void k_src_advance(LevelCtl *c, int32_t *level_off) {
     }
 }
 
-// Reverse sweep over one level.
+// One chunk of a hub: lanes stride over its entries, each summing in order,
+// then a fixed xor tree.  The last chunk of the hub to finish adds the
+// partials in chunk order.  Returns true in the wave that finalised.
+template <class Term, class Final>
+__device__ __forceinline__ void hub_chunk(const HubEntry &h, int32_t k, int32_t beg, int32_t end,
+                                          double *partial, unsigned int *cnt, Term term, Final fin) {
+    const int lane = lane_id();
+    double x = 0.0;
+    for (int32_t e = beg + lane; e < end; e += kWave) x += term(e);
+    x = wave_sum_f64(x);
+    unsigned int old = 0;
+    if (lane == 0) {
+        partial[k] = x;
+        __threadfence();
+        old = atomicAdd(cnt, 1u);
+    }
+    old = __shfl(old, 0, kWave);
+    if (old == (unsigned int)h.nchunks - 1) {
+        __threadfence();
+        if (lane == 0) {
+            double s = 0.0;
+            const volatile double *vp = partial;
+            for (int32_t q = 0; q < h.nchunks; ++q) s += vp[h.chunk_base + q];
+            *cnt = 0;
+            fin(s);
+        }
+    }
+}
+
+// Path counts of the current level's hubs (parents one level up).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const int32_t *__restrict__ dist,
+                                                      double *sigma, const HubEntry *hub_list,
+                                                      unsigned int *hub_cnt, double *partial,
+                                                      unsigned long long *prof) {
+    if (c->done) return;
+    const int32_t hlo = c->hub_lo, hhi = c->hub_hi, nch = c->hub_nchunks, pl = c->level - 1;
+    const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
+    for (int64_t k = wave0; k < nch; k += nwaves) {
+        const int32_t j = hub_find(hub_list, hlo, hhi, (int32_t)k);
+        const HubEntry h = hub_list[j];
+        const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
+        const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+        hub_chunk(h, (int32_t)k, beg, end, partial, hub_cnt + (j - hlo),
+                  [&](int32_t e) {
+                      const int32_t u = ci[e];
+                      return dist[u] == pl ? sigma[u] : 0.0;
+                  },
+                  [&](double s) {
+                      sigma[h.v] = s;
+                      atomic_max_nonneg_f64(&c->sigma_max_bits, s);
+                      if (sigma_is_large(s)) atomicOr(&c->flagged_slots, 1ull);
+                  });
+    }
+    (void)prof;
+}
+
+// Reverse sweep over one level (hubs excluded; see k_src_delta_hub).
 template <int BS>
 __global__ __launch_bounds__(BS) void k_src_delta(const int32_t *__restrict__ level_off, int32_t lvl,
                                                   const int32_t *__restrict__ rp,
@@ -249,45 +372,69 @@ __global__ __launch_bounds__(BS) void k_src_delta(const int32_t *__restrict__ le
                                                   const int32_t *__restrict__ queue,
                                                   const int32_t *__restrict__ dist,
                                                   const double *__restrict__ sigma, double *delta,
-                                                  double *bc) {
+                                                  double *bc, unsigned long long *prof) {
+    __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
+    __shared__ double s_acc[BS], s_val[BS];
+    __shared__ unsigned long long s_red[1];
+    const int wbase = threadIdx.x & ~(kWave - 1);
+    const WaveScratch ws{s_coff + wbase, s_beg + wbase, s_deg + wbase, s_acc + wbase, s_val + wbase};
     const int32_t lo = level_off[lvl], hi = level_off[lvl + 1], nl = lvl + 1;
     const int lane = lane_id();
+    unsigned long long my_items = 0, my_edges = 0, my_pairs = 0;
     for (int32_t b = lo + (int32_t)(blockIdx.x * BS + threadIdx.x) - lane; b < hi;
          b += gridDim.x * BS) {
         const int32_t i = b + lane;
-        int32_t v = -1, beg = 0, end = 0;
+        int32_t v = -1, beg = 0, deg = 0;
         double sv = 0.0;
         if (i < hi) {
             v = queue[i];
             beg = rp[v];
-            end = rp[v + 1];
+            deg = rp[v + 1] - beg;
             sv = sigma[v];
         }
-        const bool big = (end - beg) > kWave;
-        double acc = 0.0;
-        if (v >= 0 && !big)
-            for (int32_t e = beg; e < end; ++e) {
-                const int32_t w = ci[e];
-                if (dist[w] == nl) acc += (sv / sigma[w]) * (1.0 + delta[w]);
-            }
-        unsigned long long bm = __ballot(v >= 0 && big);
-        while (bm) {
-            const int j = __ffsll((long long)bm) - 1;
-            bm &= bm - 1;
-            const int32_t bj = shfl_i32(beg, j), ej = shfl_i32(end, j);
-            const double svj = shfl_f64(sv, j);
-            double part = 0.0;
-            for (int32_t e = bj + lane; e < ej; e += kWave) {
-                const int32_t w = ci[e];
-                if (dist[w] == nl) part += (svj / sigma[w]) * (1.0 + delta[w]);
-            }
-            part = wave_sum_f64(part);
-            if (lane == j) acc = part;
-        }
-        if (v >= 0) {
+        const bool hub = deg > kHubDeg;
+        ws.val[lane] = sv;
+        const double acc = wave_chunk_sum(beg, hub ? 0 : deg, ws, [&](int32_t e, int32_t a) {
+            const int32_t w = ci[e];
+            if (dist[w] != nl) return 0.0;
+            ++my_pairs;
+            return (ws.val[a] / sigma[w]) * (1.0 + delta[w]);
+        });
+        if (v >= 0 && !hub) {
             delta[v] = acc;
             if (bc) bc[v] += acc;
+            ++my_items;
+            my_edges += deg;
         }
+    }
+    flush_counters<BS>(prof, my_items, my_edges, my_pairs, s_red);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_src_delta_hub(
+    const int32_t *__restrict__ hub_off, const int32_t *__restrict__ hub_lvl_chunks, int32_t lvl,
+    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const int32_t *__restrict__ dist,
+    const double *__restrict__ sigma, double *delta, double *bc, const HubEntry *hub_list,
+    unsigned int *hub_cnt, double *partial) {
+    const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1], nch = hub_lvl_chunks[lvl];
+    const int32_t nl = lvl + 1;
+    const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
+    for (int64_t k = wave0; k < nch; k += nwaves) {
+        const int32_t j = hub_find(hub_list, hlo, hhi, (int32_t)k);
+        const HubEntry h = hub_list[j];
+        const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
+        const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+        const double sv = sigma[h.v];
+        hub_chunk(h, (int32_t)k, beg, end, partial, hub_cnt + (j - hlo),
+                  [&](int32_t e) {
+                      const int32_t w = ci[e];
+                      return dist[w] == nl ? (sv / sigma[w]) * (1.0 + delta[w]) : 0.0;
+                  },
+                  [&](double s) {
+                      delta[h.v] = s;
+                      if (bc) bc[h.v] += s;
+                  });
     }
 }
 
@@ -304,6 +451,12 @@ sp_status source_ws_create(sp_graph g, SourceWorkspace &ws) {
     SP_TRY(dev_alloc((void **)&ws.queue, n * sizeof(int32_t)));
     ws.level_cap = (int32_t)n + 2;
     SP_TRY(dev_alloc((void **)&ws.level_off, (size_t)ws.level_cap * sizeof(int32_t)));
+    SP_TRY(dev_alloc((void **)&ws.hub_off, (size_t)ws.level_cap * sizeof(int32_t)));
+    SP_TRY(dev_alloc((void **)&ws.hub_lvl_chunks, (size_t)ws.level_cap * sizeof(int32_t)));
+    SP_TRY(dev_alloc((void **)&ws.hub_list, ((size_t)g->n_hubs + 1) * sizeof(HubEntry)));
+    SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
+    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->hub_chunks + 1) * sizeof(double)));
+    SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
     SP_HIP(hipHostMalloc((void **)&ws.ctl_host, sizeof(LevelCtl), hipHostMallocDefault));
     SP_HIP(hipEventCreate(&ws.ev0));
@@ -317,6 +470,11 @@ void source_ws_destroy(SourceWorkspace &ws) {
     dev_free(ws.delta);
     dev_free(ws.queue);
     dev_free(ws.level_off);
+    dev_free(ws.hub_off);
+    dev_free(ws.hub_lvl_chunks);
+    dev_free(ws.hub_list);
+    dev_free(ws.hub_cnt);
+    dev_free(ws.partial);
     dev_free(ws.ctl);
     if (ws.ctl_host) (void)hipHostFree(ws.ctl_host);
     if (ws.ev0) (void)hipEventDestroy(ws.ev0);
@@ -329,23 +487,44 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                                bool with_backward, const SourceRunOpts &o, hipStream_t s,
                                SourceResult *res) {
     const int32_t n = g->n;
-    const int grid_frontier = grid_for((int64_t)n, BS, device_cu_count() * 8);
+    const int maxb = device_cu_count() * 8;
+    const int grid = grid_for((int64_t)n, BS, maxb);
+    const bool hubs = g->n_hubs > 0;
+    const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
     SP_TRY(launch_fill_i32(ws.dist, n, -1, s));
     hipLaunchKernelGGL(k_src_init, dim3(1), dim3(1), 0, s, ws.ctl, ws.dist, ws.sigma, ws.queue,
-                       ws.level_off, (const int32_t *)g->row_ptr, src, n, (long long)g->nnz, o.alpha,
-                       o.beta);
+                       ws.level_off, ws.hub_list, ws.hub_off, ws.hub_lvl_chunks,
+                       (const int32_t *)g->row_ptr, src, n, (long long)g->nnz,
+                       may_pull ? o.alpha : 0.0, o.beta);  // alpha 0: never switch to bottom-up
     SP_HIP(hipGetLastError());
     int32_t enqueued = 0;
     for (;;) {
         const int chunk = std::max(1, o.chunk_levels);
         for (int k = 0; k < chunk; ++k) {
-            hipLaunchKernelGGL(k_src_topdown<BS>, dim3(grid_frontier), dim3(BS), 0, s, ws.ctl,
-                               g->row_ptr, g->col_idx, ws.dist, ws.queue);
-            hipLaunchKernelGGL(k_src_bottomup<BS>, dim3(grid_frontier), dim3(BS), 0, s, ws.ctl,
-                               g->row_ptr, g->col_idx, ws.dist, ws.queue);
-            hipLaunchKernelGGL(k_src_sigma<BS>, dim3(grid_frontier), dim3(BS), 0, s, ws.ctl,
-                               g->row_ptr, g->col_idx, ws.queue, ws.dist, ws.sigma);
-            hipLaunchKernelGGL(k_src_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off);
+            {
+                ProfScope ps(P_SRC_TOPDOWN, s);
+                hipLaunchKernelGGL(k_src_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s,
+                                   ws.ctl, g->row_ptr, g->col_idx, ws.dist, ws.queue,
+                                   (const HubEntry *)ws.hub_list, prof_counters(P_SRC_TOPDOWN));
+            }
+            if (may_pull) {
+                ProfScope ps(P_SRC_BOTTOMUP, s);
+                hipLaunchKernelGGL(k_src_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
+                                   g->col_idx, ws.dist, ws.queue, prof_counters(P_SRC_BOTTOMUP));
+            }
+            {
+                ProfScope ps(P_SRC_SIGMA, s);
+                hipLaunchKernelGGL(k_src_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
+                                   g->col_idx, ws.queue, ws.dist, ws.sigma, ws.hub_list,
+                                   (long long)g->n_hubs + 1, prof_counters(P_SRC_SIGMA));
+            }
+            hipLaunchKernelGGL(k_src_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
+                               ws.hub_off, ws.hub_lvl_chunks);
+            if (hubs)
+                hipLaunchKernelGGL(k_src_sigma_hub<BS>, dim3(grid_for((int64_t)g->hub_chunks * kWave, BS, maxb)),
+                                   dim3(BS), 0, s, ws.ctl, g->row_ptr, g->col_idx, ws.dist, ws.sigma,
+                                   (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
+                                   prof_counters(P_SRC_SIGMA));
         }
         SP_HIP(hipGetLastError());
         enqueued += chunk;
@@ -360,15 +539,26 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
     const LevelCtl &c = *ws.ctl_host;
     const int32_t levels = c.level + 1;
     if (with_backward && levels > 1) {
-        std::vector<int32_t> off(levels + 1);
+        std::vector<int32_t> off(levels + 1), hchunks(levels);
         SP_HIP(hipMemcpyAsync(off.data(), ws.level_off, sizeof(int32_t) * (levels + 1),
+                              hipMemcpyDeviceToHost, s));
+        SP_HIP(hipMemcpyAsync(hchunks.data(), ws.hub_lvl_chunks, sizeof(int32_t) * levels,
                               hipMemcpyDeviceToHost, s));
         SP_HIP(hipStreamSynchronize(s));
         for (int32_t l = levels - 1; l >= 1; --l) {
             const int32_t cnt = off[l + 1] - off[l];
-            const int grid = grid_for((int64_t)cnt, BS, device_cu_count() * 8);
-            hipLaunchKernelGGL(k_src_delta<BS>, dim3(grid), dim3(BS), 0, s, ws.level_off, l,
-                               g->row_ptr, g->col_idx, ws.queue, ws.dist, ws.sigma, ws.delta, bc);
+            {
+                ProfScope ps(P_SRC_DELTA, s);
+                hipLaunchKernelGGL(k_src_delta<BS>, dim3(grid_for((int64_t)cnt, BS, maxb)), dim3(BS), 0, s,
+                                   ws.level_off, l, g->row_ptr, g->col_idx, ws.queue, ws.dist,
+                                   ws.sigma, ws.delta, bc, prof_counters(P_SRC_DELTA));
+            }
+            if (hubs && hchunks[l] > 0)
+                hipLaunchKernelGGL(k_src_delta_hub<BS>, dim3(grid_for((int64_t)hchunks[l] * kWave, BS, maxb)),
+                                   dim3(BS), 0, s, (const int32_t *)ws.hub_off,
+                                   (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
+                                   ws.dist, ws.sigma, ws.delta, bc, (const HubEntry *)ws.hub_list,
+                                   ws.hub_cnt, ws.partial);
         }
         SP_HIP(hipGetLastError());
     }

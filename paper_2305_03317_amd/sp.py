@@ -60,6 +60,13 @@ class sp_server_stats(ctypes.Structure):
                 ("queue_depth", ctypes.c_int32), ("in_flight", ctypes.c_int32)]
 
 
+class sp_kernel_profile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("items", ctypes.c_int64),
+                ("edges", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("item_slots", ctypes.c_int64)]
+
+
 def _struct_dict(s):
     return {k: (list(getattr(s, k)) if k == "reserved" else getattr(s, k)) for k, _ in s._fields_}
 
@@ -85,6 +92,8 @@ SIGNATURES = [
                               ctypes.POINTER(sp_batch_config), _VP]),
     ("sp_bc_workspace_bytes", _ST, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("sp_autotune", _ST, [_VP, _I32P, ctypes.c_int32, ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_profile_enable", _ST, [ctypes.c_int32]),
+    ("sp_profile_read", _ST, [ctypes.POINTER(sp_kernel_profile), ctypes.c_int32, _I32P]),
     ("sp_server_create", _ST, [ctypes.POINTER(sp_server_config), ctypes.POINTER(_VP)]),
     ("sp_server_add_graph", _ST, [_VP, _VP, _I32P]),
     ("sp_stream_submit", _ST, [_VP, ctypes.c_int32, _I32P, ctypes.c_int32, _VP, ctypes.POINTER(_VP)]),
@@ -300,6 +309,22 @@ def sp_bc_workspace_bytes(g: Graph, batch_width: int) -> int:
     b = ctypes.c_size_t()
     _check(lib().sp_bc_workspace_bytes(g.handle, batch_width, ctypes.byref(b)), "sp_bc_workspace_bytes")
     return b.value
+
+
+def sp_profile_enable(on: bool = True):
+    _check(lib().sp_profile_enable(1 if on else 0), "sp_profile_enable")
+
+
+def sp_profile_read() -> dict:
+    """{family: dict(launches, total_ms, items, edges, pairs, item_slots)}; resets."""
+    buf = (sp_kernel_profile * 32)()
+    n = ctypes.c_int32()
+    _check(lib().sp_profile_read(buf, 32, ctypes.byref(n)), "sp_profile_read")
+    out = {}
+    for i in range(n.value):
+        d = _struct_dict(buf[i])
+        out[d.pop("name").decode()] = d
+    return out
 
 
 def sp_autotune(g: Graph, sources, stream=None) -> dict:

@@ -49,7 +49,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     """ctypes mirrors of the header's structs have the C sizes and offsets."""
     import subprocess
     structs = {"sp_batch_config": sp.sp_batch_config, "sp_stats": sp.sp_stats,
-               "sp_server_config": sp.sp_server_config, "sp_server_stats": sp.sp_server_stats}
+               "sp_server_config": sp.sp_server_config, "sp_server_stats": sp.sp_server_stats,
+               "sp_kernel_profile": sp.sp_kernel_profile}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))

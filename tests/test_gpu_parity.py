@@ -244,3 +244,34 @@ def test_upload_validation(sp):
         sp.sp_graph_upload(rp, ci, validate=True)
     with pytest.raises(sp.SpError):       # id out of range: caught on the device
         sp.sp_graph_upload(np.array([0, 1, 2], np.int32), np.array([1, 5], np.int32))
+
+
+@pytest.mark.parametrize("alpha,beta", [(1e-9, 24.0), (1e9, 1e-9), (1e9, 1e9)])
+def test_direction_extremes(sp, alpha, beta):
+    """Top-down only, bottom-up as early as possible, and bottom-up to the end."""
+    rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 21)
+    srcs = graphs.sources(rp, 40, 22, min_degree=1)
+    g = sp.sp_graph_upload(rp, ci)
+    ref = oracle.bc(rp, ci, srcs)
+    b, _ = sp.sp_bc_batch(g, srcs, config={"alpha": alpha, "beta": beta})
+    assert_bc(b.cpu().numpy(), ref, "alpha %g beta %g" % (alpha, beta))
+    st = sp.sp_get_last_stats()
+    if alpha > 1:
+        assert st["bottomup_levels"] > 0
+    else:
+        assert st["bottomup_levels"] == 0
+    g.release()
+
+
+def test_star_and_meshes_never_switch_direction(sp):
+    """Low-degree graphs run top-down only; the switch must not strand a level."""
+    for G in (nx.star_graph(6), nx.grid_2d_graph(9, 9), nx.path_graph(50)):
+        rp, ci = csr_of(nx.convert_node_labels_to_integers(G))
+        n = len(rp) - 1
+        g = sp.sp_graph_upload(rp, ci)
+        srcs = np.arange(n)
+        ref = oracle.bc(rp, ci, srcs)
+        a, b, _, _ = both_paths(sp, g, srcs)
+        assert_bc(a, ref, "sp_bc")
+        assert_bc(b, ref, "sp_bc_batch")
+        g.release()
