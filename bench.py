@@ -39,8 +39,8 @@ WORKLOADS = {"uniform-4096": 1, "rmat-20": 2, "rmat-22": 3, "road-4096": 4}
 # (per-source) or (slot, DAG edge) pairs (batched); item_slots = slots over
 # entries (batched).
 BYTE_MODEL = {
-    "ms_sigma": dict(items=68, edges=20, pairs=8, item_slots=8),
-    "ms_delta": dict(items=36, edges=20, pairs=16, item_slots=16),
+    "ms_sigma": dict(items=72, edges=20, pairs=8, item_slots=8),
+    "ms_delta": dict(items=40, edges=20, pairs=8, item_slots=24),
     "ms_topdown": dict(items=20, edges=20),
     "ms_bottomup": dict(items=16, edges=20),
     "ms_bc": dict(items=24, item_slots=8),
@@ -68,6 +68,9 @@ def main():
                     help="sources timed through the per-source path (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="sources timed through the CPU oracle (0 = skip)")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="run one device-to-device copy of this many GiB first (a known-size "
+                         "kernel that calibrates hardware byte counters in a profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -86,6 +89,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_gib > 0:
+        nbytes = int(args.copy_gib * (1 << 30))
+        a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     k = WORKLOADS[args.workload]
 
     t0 = time.perf_counter()

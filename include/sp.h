@@ -84,8 +84,9 @@ const char *sp_last_error(void);
 int32_t sp_version(void);
 
 /* ------------------------------------------------------------------------
- * Graphs (paper Section 2.3.1 "Data Types": CSR offsets + neighbour lists;
- * Section 3 "Backend graph library": the CSR is copied to the device once)
+ * Graphs (paper Section 2.3.1 "Data Types" and Section 3.1 "Graph
+ * Representation and Storage": CSR offsets + neighbour lists, copied to the
+ * device once; the graph is static)
  * ------------------------------------------------------------------------ */
 
 /* Copy a CSR graph into library-owned device memory on the current device.
@@ -99,8 +100,11 @@ int32_t sp_version(void);
  *               device arrays back first) before uploading.
  *   s           stream used for the copies; the call synchronises it.
  *   out         receives the handle (unchanged on error).
- * Without SP_VALIDATE the CSR is trusted; a malformed one gives undefined
- * results (never out-of-bounds access: ids are masked into range). */
+ * Every upload checks on the device that offsets are monotone within
+ * [0, nnz] and ids lie in [0, V) (SP_ERR_INVALID_ARGUMENT otherwise), so no
+ * kernel can index outside the arrays.  Without SP_VALIDATE the remaining
+ * properties (sorted, duplicate-free, loop-free, symmetric rows) are trusted;
+ * a CSR that breaks them gives BC of the directed multigraph it encodes. */
 sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
                           const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out);
 

@@ -214,15 +214,16 @@ int64_t initial_qcap(int32_t n, int32_t width) {
 sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out) {
     {
         std::lock_guard<std::mutex> lk(g->mu);
-        if (!g->batch_pool.empty()) {
-            *out = g->batch_pool.back();
-            g->batch_pool.pop_back();
-            return SP_OK;
-        }
+        for (size_t i = 0; i < g->batch_pool.size(); ++i)
+            if (g->batch_pool[i]->width >= width) {
+                *out = g->batch_pool[i];
+                g->batch_pool.erase(g->batch_pool.begin() + i);
+                return SP_OK;
+            }
     }
     auto *ws = new (std::nothrow) BatchWorkspace;
     if (!ws) return SP_ERR_OUT_OF_MEMORY;
-    sp_status st = batch_ws_create(g, initial_qcap(g->n, width), *ws);
+    sp_status st = batch_ws_create(g, initial_qcap(g->n, width), width, *ws);
     if (st < 0) {
         batch_ws_destroy(*ws);
         delete ws;
@@ -583,7 +584,7 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
     for (int32_t b = 0; b < n_sources; b += width) {
         const int32_t nb = std::min(width, n_sources - b);
         BatchResult r;
-        SP_TRY(batch_run(g, *ws, sources + b, nb, slots, o, st, &r, false));
+        SP_TRY(batch_run(g, *ws, sources + b, nb, slots, o, st, &r));
         stats.n_passes++;
         stats.max_levels = std::max(stats.max_levels, r.levels);
         stats.levels_total += r.levels;
@@ -659,8 +660,11 @@ sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources,
         ~Rel() { release_batch_ws(g, ws); }
     } rel{g, ws};
     BatchResult r;
-    SP_TRY(batch_run(g, *ws, sources, n_sources, nullptr, o, st, &r, true));
-    SP_TRY(batch_extract(g, *ws, n_sources, out_dist, out_sigma, out_delta, st));
+    BatchExtract ex;
+    ex.dist = out_dist;
+    ex.sigma = out_sigma;
+    ex.delta = out_delta;
+    SP_TRY(batch_run(g, *ws, sources, n_sources, nullptr, o, st, &r, &ex));
     SP_HIP(hipStreamSynchronize(st));
     return r.flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
     SP_GUARD_END
@@ -671,7 +675,7 @@ sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes) 
         set_error("sp_bc_workspace_bytes: bad arguments");
         return SP_ERR_INVALID_ARGUMENT;
     }
-    *bytes = batch_ws_bytes(g, initial_qcap(g->n, batch_width));
+    *bytes = batch_ws_bytes(g, initial_qcap(g->n, batch_width), batch_width);
     return SP_OK;
 }
 

@@ -1,0 +1,118 @@
+// Autotuner for the batched path: times candidate configurations on a sample
+// of the caller's sources and keeps the fastest per graph.
+//
+// Search: coordinate descent from the defaults over block size
+// {128, 256, 512}, batch width {32, 48, 64}, the top-down -> bottom-up
+// threshold alpha {4, 15, 60} and the bottom-up -> top-down threshold beta
+// {8, 24, 96}; each candidate runs the same sample twice (warm, then timed
+// with HIP events) and is scored by device time per source.  The winner is
+// cached on the graph (sp_graph_s::tuned) and used for every zero field of a
+// later configuration.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+using namespace sp;
+
+namespace {
+
+sp_status time_config(sp_graph g, BatchWorkspace &ws, const int32_t *src, int32_t n,
+                      int32_t width, const BatchRunOpts &o, hipStream_t s, double *ms_per_source) {
+    hipEvent_t e0, e1;
+    SP_HIP(hipEventCreate(&e0));
+    SP_HIP(hipEventCreate(&e1));
+    struct Rel {
+        hipEvent_t a, b;
+        ~Rel() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } rel{e0, e1};
+    for (int rep = 0; rep < 2; ++rep) {
+        SP_HIP(hipEventRecord(e0, s));
+        for (int32_t b = 0; b < n; b += width) {
+            BatchResult r;
+            SP_TRY(batch_run(g, ws, src + b, std::min(width, n - b), nullptr, o, s, &r));
+        }
+        SP_HIP(hipEventRecord(e1, s));
+        SP_HIP(hipEventSynchronize(e1));
+    }
+    float ms = 0.f;
+    SP_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *ms_per_source = ms / std::max(n, 1);
+    return SP_OK;
+}
+
+}  // namespace
+
+extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_sources,
+                                 sp_batch_config *out, sp_stream s) {
+    try {
+        clear_error();
+        if (!g || !out || n_sources < 1 || !sources) {
+            set_error("sp_autotune: need a graph, an output and at least one source");
+            return SP_ERR_INVALID_ARGUMENT;
+        }
+        for (int32_t i = 0; i < n_sources; ++i)
+            if (sources[i] < 0 || sources[i] >= g->n) {
+                set_error("sources[%d] out of range", i);
+                return SP_ERR_INVALID_ARGUMENT;
+            }
+        hipStream_t st = (hipStream_t)s;
+        const int32_t n = std::min(n_sources, 2 * kSlots);
+        BatchWorkspace *ws = nullptr;
+        SP_TRY(acquire_batch_ws(g, kSlots, &ws));
+        struct Rel {
+            sp_graph g;
+            BatchWorkspace *ws;
+            ~Rel() { release_batch_ws(g, ws); }
+        } rel{g, ws};
+
+        sp_batch_config best{};
+        best.batch_width = 64;
+        best.block_size = 256;
+        best.alpha = 15.0;
+        best.beta = 24.0;
+        best.chunk_levels = 8;
+        auto opts = [](const sp_batch_config &c) {
+            BatchRunOpts o;
+            o.block = c.block_size;
+            o.alpha = c.alpha;
+            o.beta = c.beta;
+            o.chunk_levels = c.chunk_levels;
+            return o;
+        };
+        double best_ms = 0;
+        SP_TRY(time_config(g, *ws, sources, n, best.batch_width, opts(best), st, &best_ms));
+        auto try_field = [&](auto setter, const std::vector<double> &values) -> sp_status {
+            for (double v : values) {
+                sp_batch_config c = best;
+                setter(c, v);
+                double ms = 0;
+                SP_TRY(time_config(g, *ws, sources, n, c.batch_width, opts(c), st, &ms));
+                if (ms < best_ms * 0.98) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+            return SP_OK;
+        };
+        SP_TRY(try_field([](sp_batch_config &c, double v) { c.block_size = (int32_t)v; }, {128, 512}));
+        SP_TRY(try_field([](sp_batch_config &c, double v) { c.batch_width = (int32_t)v; }, {32, 48}));
+        if (g->max_degree > 8) {
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.alpha = v; }, {4, 60}));
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.beta = v; }, {8, 96}));
+        }
+        {
+            std::lock_guard<std::mutex> lk(g->mu);
+            g->tuned.valid = true;
+            g->tuned.cfg = best;
+        }
+        *out = best;
+        return SP_OK;
+    } catch (...) {
+        set_error("sp_autotune: unexpected failure");
+        return SP_ERR_DEVICE;
+    }
+}

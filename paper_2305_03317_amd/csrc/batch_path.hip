@@ -6,12 +6,17 @@
 // A (vertex, mask) pair per level is an "entry"; entries of one level are
 // contiguous in `queue`/`qmask`, and level_off[l] is where level l starts.
 //
-// Per-source arithmetic is exactly the per-source path's (paper Appendix,
-// Fig. "BC computation in StarPlat"; DAG semantics of Section 2.3.2): for
-// slot s, sigma[w][s] sums sigma[u][s] over neighbours u with s in
-// front(l)[u], and delta[v][s] sums (sigma[v][s] / sigma[w][s]) *
-// (1 + delta[w][s]) over neighbours w with s in front(l+1)[w], both in CSR
-// order.  sigma and delta rows are vertex-major (64 doubles per vertex).
+// Per slot s the arithmetic is Brandes' (paper Appendix, Fig. "BC computation
+// in StarPlat"; DAG semantics of Section 2.3.2): sigma_s(w) sums sigma_s(u)
+// over neighbours u whose level-l entry holds s, in CSR order.  The reverse
+// sum is regrouped: with rho_s(w) = (1 + delta_s(w)) / sigma_s(w),
+//   delta_s(v) = sum_w (sigma_s(v) / sigma_s(w)) (1 + delta_s(w))
+//              = sigma_s(v) * sum_w rho_s(w),
+// so a child contributes one stored value instead of two (same sum, a few
+// ulps apart).  Values are stored per entry, compactly: slot s of entry
+// (v, level, m) lives at val[vb + rank_m(s)] and the front record carries vb,
+// so a neighbour's values for the slots it shares are one short contiguous
+// read.  delta also goes to vertex-major rows dlt[v][64] for the BC sums.
 //
 // An entry is reduced one of three ways:
 //   dense  (many slots): one wave, lane = slot; the wave reads the neighbours'
@@ -51,8 +56,9 @@ __device__ __forceinline__ unsigned long long mask_of(uint4 f) {
     return (unsigned long long)f.x | ((unsigned long long)f.y << 32);
 }
 
-__device__ __forceinline__ uint4 make_front(unsigned long long m, uint32_t tag) {
-    return make_uint4((uint32_t)m, (uint32_t)(m >> 32), tag, 0u);
+// {mask lo, mask hi, level tag, value base}
+__device__ __forceinline__ uint4 make_front(unsigned long long m, uint32_t tag, uint32_t vb) {
+    return make_uint4((uint32_t)m, (uint32_t)(m >> 32), tag, vb);
 }
 
 __device__ __forceinline__ int32_t rl_i32(int32_t v, int j) { return __builtin_amdgcn_readlane(v, j); }
@@ -63,104 +69,95 @@ __device__ __forceinline__ unsigned long long rl_u64(unsigned long long v, int j
     return (unsigned long long)lo | ((unsigned long long)hi << 32);
 }
 
-// lane = slot: sum over adjacency entries [beg, end) of sigma[u][lane] for
-// neighbours u whose level-`tag` mask (restricted to m) holds the lane.
-__device__ __forceinline__ double dense_sigma(int32_t beg, int32_t end, unsigned long long m,
-                                              uint32_t tag, const int32_t *__restrict__ ci,
-                                              const uint4 *__restrict__ front,
-                                              const double *__restrict__ sigma,
-                                              unsigned long long &pairs) {
+__device__ __forceinline__ int rank_in(unsigned long long m, int s) {
+    return __popcll(m & ((1ull << s) - 1ull));
+}
+
+// lane = slot: sum over adjacency entries [beg, end) of the value of slot
+// `lane` of each neighbour's level-`tag` entry, for neighbours whose entry
+// holds the lane and m holds it too.  The sum runs in CSR order; up to 8
+// neighbour values are loaded at once.  Forward: parents' sigma.  Reverse:
+// children's rho.
+__device__ __forceinline__ double dense_sum(int32_t beg, int32_t end, unsigned long long m,
+                                            uint32_t tag, const int32_t *__restrict__ ci,
+                                            const uint4 *__restrict__ front,
+                                            const double *__restrict__ val,
+                                            unsigned long long &pairs) {
     const int lane = lane_id();
     double acc = 0.0;
     for (int32_t e0 = beg; e0 < end; e0 += kWave) {
         const int32_t e = e0 + lane;
-        int32_t u = 0;
-        unsigned long long f = 0;
+        unsigned long long mu = 0;
+        uint32_t vb = 0;
         if (e < end) {
-            u = ci[e];
-            const uint4 fu = front[u];
-            if (fu.z == tag) f = mask_of(fu) & m;
+            const uint4 fu = front[ci[e]];
+            if (fu.z == tag) {
+                mu = mask_of(fu);
+                vb = fu.w;
+            }
         }
-        unsigned long long nz = __ballot(f != 0ull);
+        unsigned long long nz = __ballot((mu & m) != 0ull);
         while (nz) {
-            int32_t uj[8];
-            unsigned long long fj[8];
+            unsigned long long mj[8];
+            uint32_t vj[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 if (nz) {
                     const int j = __ffsll((long long)nz) - 1;
                     nz &= nz - 1;
-                    uj[t] = rl_i32(u, j);
-                    fj[t] = rl_u64(f, j);
+                    mj[t] = rl_u64(mu, j);
+                    vj[t] = (uint32_t)rl_i32((int32_t)vb, j);
                 } else {
-                    uj[t] = 0;
-                    fj[t] = 0;
+                    mj[t] = 0;
+                    vj[t] = 0;
                 }
             }
             double x[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
-                x[t] = ((fj[t] >> lane) & 1ull) ? sigma[(int64_t)uj[t] * kSlots + lane] : 0.0;
+            for (int t = 0; t < 8; ++t) {
+                const bool on = ((mj[t] & m) >> lane) & 1ull;
+                x[t] = on ? val[(int64_t)vj[t] + rank_in(mj[t], lane)] : 0.0;
+            }
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                if ((fj[t] >> lane) & 1ull) acc += x[t];
-                pairs += (unsigned long long)__popcll(fj[t]);
+                if (((mj[t] & m) >> lane) & 1ull) acc += x[t];
+                pairs += (unsigned long long)__popcll(mj[t] & m);
             }
         }
     }
     return acc;
 }
 
-// lane = slot: sum over [beg, end) of (sv / sigma[w][lane]) * (1 + delta[w][lane])
-// for neighbours w whose level-`tag` mask (restricted to m) holds the lane.
-__device__ __forceinline__ double dense_delta(int32_t beg, int32_t end, unsigned long long m,
-                                              uint32_t tag, double sv,
-                                              const int32_t *__restrict__ ci,
-                                              const uint4 *__restrict__ front,
-                                              const double *__restrict__ sigma,
-                                              const double *__restrict__ delta,
-                                              unsigned long long &pairs) {
-    const int lane = lane_id();
+// One lane, one slot s: the same sum as dense_sum for slot s alone.  Four
+// adjacency entries are in flight at a time (their column ids, then their
+// front records, then the values), and added in CSR order.
+__device__ __forceinline__ double sparse_sum(int32_t beg, int32_t end, int s, uint32_t tag,
+                                             const int32_t *__restrict__ ci,
+                                             const uint4 *__restrict__ front,
+                                             const double *__restrict__ val,
+                                             unsigned long long &pairs) {
     double acc = 0.0;
-    for (int32_t e0 = beg; e0 < end; e0 += kWave) {
-        const int32_t e = e0 + lane;
-        int32_t w = 0;
-        unsigned long long g = 0;
-        if (e < end) {
-            w = ci[e];
-            const uint4 fw = front[w];
-            if (fw.z == tag) g = mask_of(fw) & m;
+    for (int32_t e0 = beg; e0 < end; e0 += 4) {
+        int32_t u[4];
+        uint4 f[4];
+        double x[4];
+        bool hit[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) u[t] = e0 + t < end ? ci[e0 + t] : -1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f[t] = u[t] >= 0 ? front[u[t]] : make_uint4(0u, 0u, kNoTag, 0u);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const unsigned long long mu = mask_of(f[t]);
+            hit[t] = f[t].z == tag && ((mu >> s) & 1ull);
+            x[t] = hit[t] ? val[(int64_t)f[t].w + rank_in(mu, s)] : 0.0;
         }
-        unsigned long long nz = __ballot(g != 0ull);
-        while (nz) {
-            int32_t wj[8];
-            unsigned long long gj[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (nz) {
-                    const int j = __ffsll((long long)nz) - 1;
-                    nz &= nz - 1;
-                    wj[t] = rl_i32(w, j);
-                    gj[t] = rl_u64(g, j);
-                } else {
-                    wj[t] = 0;
-                    gj[t] = 0;
-                }
+        for (int t = 0; t < 4; ++t)
+            if (hit[t]) {
+                acc += x[t];
+                ++pairs;
             }
-            double sg[8], dl[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const bool on = (gj[t] >> lane) & 1ull;
-                const int64_t o = (int64_t)wj[t] * kSlots + lane;
-                sg[t] = on ? sigma[o] : 1.0;
-                dl[t] = on ? delta[o] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if ((gj[t] >> lane) & 1ull) acc += (sv / sg[t]) * (1.0 + dl[t]);
-                pairs += (unsigned long long)__popcll(gj[t]);
-            }
-        }
     }
     return acc;
 }
@@ -169,7 +166,7 @@ __global__ void k_ms_clear(unsigned long long *seen, unsigned long long *nxt, ui
                            int32_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const uint4 z = make_front(0, kNoTag);
+    const uint4 z = make_front(0, kNoTag, 0u);
     for (; i < n; i += stride) {
         seen[i] = 0;
         nxt[i] = 0;
@@ -180,19 +177,31 @@ __global__ void k_ms_clear(unsigned long long *seen, unsigned long long *nxt, ui
 
 // Level 0: entries [0, n0) hold the distinct source vertices and their slots.
 __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int32_t *queue,
-                          const unsigned long long *qmask, int32_t n0, unsigned long long *seen,
-                          uint4 *front0, double *sigma, int32_t *level_off, HubEntry *hub_list,
-                          int32_t *hub_off, int32_t *hub_lvl_chunks, int32_t n, long long nnz,
-                          unsigned long long active, double alpha, double beta) {
+                          const unsigned long long *qmask, uint32_t *qvb, int32_t n0,
+                          unsigned long long *seen, uint4 *front0, double *val, int32_t *level_off,
+                          HubEntry *hub_list, int32_t *hub_off, int32_t *hub_lvl_chunks, int32_t n,
+                          long long nnz, unsigned long long active, double alpha, double beta) {
+    __shared__ uint32_t s_vb[kSlots + 1];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int32_t i = 0; i < n0; ++i) {
+            s_vb[i] = run;
+            run += (uint32_t)__popcll(qmask[i]);
+        }
+        s_vb[n0] = run;
+    }
+    __syncthreads();
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
     for (int32_t i = wv; i < n0; i += blockDim.x / kWave) {
         const int32_t v = queue[i];
         const unsigned long long m = qmask[i];
-        if ((m >> lane) & 1ull) sigma[(int64_t)v * kSlots + lane] = 1.0;
+        const uint32_t vb = s_vb[i];
+        if ((m >> lane) & 1ull) val[vb + rank_in(m, lane)] = 1.0;
         if (lane == 0) {
             seen[v] = m;
-            front0[v] = make_front(m, 0u);
+            front0[v] = make_front(m, 0u, vb);
+            qvb[i] = vb;
         }
     }
     if (threadIdx.x == 0) {
@@ -221,6 +230,7 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->next_deg = 0;
         c->settled_deg = 0;
         c->reached_pairs = pairs;
+        c->vtail = s_vb[n0];
         c->unset_deg = (unsigned long long)nnz - settled;
         c->sigma_max_bits = (unsigned long long)__double_as_longlong(1.0);
         c->flagged_slots = 0;
@@ -411,23 +421,25 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
-// Path counts of the new entries [hi, tail).  Wave takes 64 entries; sparse
-// ones are reduced by their own lane, dense ones by the whole wave in turn,
-// hubs are registered for k_ms_sigma_hub.  Every entry's bookkeeping (qmask,
-// nxt reset, seen, front of the new level) is done here.
+// Path counts of the new entries [hi, tail).  Wave takes 64 entries, gives
+// each its value range, then: sparse entries are reduced by their own lane,
+// dense ones by the whole wave in turn, hubs are registered for
+// k_ms_sigma_hub.  Every entry's bookkeeping (qmask, value base, nxt reset,
+// seen, front of the new level) is done here.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
                                                  const int32_t *__restrict__ queue,
-                                                 unsigned long long *qmask, unsigned long long *seen,
-                                                 unsigned long long *nxt,
+                                                 unsigned long long *qmask, uint32_t *qvb,
+                                                 unsigned long long *seen, unsigned long long *nxt,
                                                  const uint4 *__restrict__ front_cur,
-                                                 uint4 *front_nxt, double *sigma,
+                                                 uint4 *front_nxt, double *val, long long vcap,
                                                  HubEntry *hub_list, long long hub_cap,
                                                  unsigned long long active, long long qcap,
                                                  unsigned long long *prof) {
     if (c->done) return;
-    __shared__ unsigned long long s_red[1];
+    __shared__ unsigned long long s_red[1], s_base[1];
+    __shared__ int32_t s_scan[BS / kWave + 1];
     const uint32_t lvl = (uint32_t)c->level;
     const int32_t hi = c->hi;
     const int32_t tail = (int32_t)min((long long)c->tail, qcap);
@@ -435,12 +447,12 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
     unsigned long long my_deg = 0, my_settled = 0, my_flag = 0, my_pairs = 0, my_items = 0,
                        my_dag = 0;
     double my_max = 0.0;
-    for (int32_t b = hi + (int32_t)(blockIdx.x * BS + threadIdx.x) - lane; b < tail;
-         b += gridDim.x * BS) {
-        const int32_t i = b + lane;
+    for (int32_t b = hi + (int32_t)(blockIdx.x * BS); b < tail; b += gridDim.x * BS) {
+        const int32_t i = b + (int32_t)threadIdx.x;
+        const bool valid = i < tail;
         int32_t w = 0, beg = 0, end = 0;
         unsigned long long m = 0;
-        if (i < tail) {
+        if (valid) {
             w = queue[i];
             m = nxt[w];
             beg = rp[w];
@@ -448,25 +460,26 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
         }
         const int32_t deg = end - beg;
         const int pc = __popcll(m);
-        const bool valid = i < tail;
-        const bool hub = valid && deg > kHubDeg;
-        const bool sparse = valid && !hub && pc <= kSparseSlots && deg <= kSparseDeg;
-        const bool dense = valid && !hub && !sparse;
+        // value range of this entry: block scan + one atomic per block
+        int32_t btotal;
+        const int32_t excl = block_excl_scan<BS>(pc, s_scan, &btotal);
+        if (threadIdx.x == 0) s_base[0] = btotal ? atomicAdd(&c->vtail, (unsigned long long)btotal) : 0ull;
+        __syncthreads();
+        const unsigned long long vb64 = s_base[0] + (unsigned long long)excl;
+        __syncthreads();
+        const bool fits = vb64 + (unsigned long long)pc <= (unsigned long long)vcap;
+        const uint32_t vb = (uint32_t)vb64;
+        if (valid && !fits) atomicOr(&c->overflow, 1);
+        const bool hub = valid && fits && deg > kHubDeg;
+        const bool sparse = valid && fits && !hub && pc <= kSparseSlots && deg <= kSparseDeg;
+        const bool dense = valid && fits && !hub && !sparse;
         if (sparse) {
             unsigned long long bits = m;
             while (bits) {
                 const int s = __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                double acc = 0.0;
-                for (int32_t e = beg; e < end; ++e) {
-                    const int32_t u = ci[e];
-                    const uint4 fu = front_cur[u];
-                    if (fu.z == lvl && ((mask_of(fu) >> s) & 1ull)) {
-                        acc += sigma[(int64_t)u * kSlots + s];
-                        ++my_dag;
-                    }
-                }
-                sigma[(int64_t)w * kSlots + s] = acc;
+                const double acc = sparse_sum(beg, end, s, lvl, ci, front_cur, val, my_dag);
+                val[vb + rank_in(m, s)] = acc;
                 my_max = fmax(my_max, acc);
                 if (sigma_is_large(acc)) my_flag |= 1ull << s;
             }
@@ -475,24 +488,27 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
         while (dm) {
             const int jl = __ffsll((long long)dm) - 1;
             dm &= dm - 1;
-            const int32_t wj = rl_i32(w, jl), bj = rl_i32(beg, jl), ej = rl_i32(end, jl);
+            const int32_t bj = rl_i32(beg, jl), ej = rl_i32(end, jl);
+            const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
             const unsigned long long mj = rl_u64(m, jl);
             unsigned long long pr = 0;
-            const double acc = dense_sigma(bj, ej, mj, lvl, ci, front_cur, sigma, pr);
+            const double acc = dense_sum(bj, ej, mj, lvl, ci, front_cur, val, pr);
             if (lane == 0) my_dag += pr;
-            if ((mj >> lane) & 1ull) {
-                sigma[(int64_t)wj * kSlots + lane] = acc;
+            const bool mine = (mj >> lane) & 1ull;
+            if (mine) {
+                val[vbj + rank_in(mj, lane)] = acc;
                 my_max = fmax(my_max, acc);
             }
-            my_flag |= __ballot(((mj >> lane) & 1ull) && sigma_is_large(acc));
+            my_flag |= __ballot(mine && sigma_is_large(acc));
         }
         if (hub) hub_register(c, hub_list, hub_cap, w, i, deg);
         if (valid) {
             qmask[i] = m;
+            qvb[i] = vb;
             nxt[w] = 0;
             const unsigned long long now = seen[w] | m;
             seen[w] = now;
-            front_nxt[w] = make_front(m, lvl + 1);
+            front_nxt[w] = make_front(m, lvl + 1, vb);
             my_deg += (unsigned long long)deg;
             my_pairs += (unsigned long long)pc;
             ++my_items;
@@ -589,8 +605,9 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci,
                                                      const unsigned long long *__restrict__ qmask,
+                                                     const uint32_t *__restrict__ qvb,
                                                      const uint4 *__restrict__ front_par,
-                                                     double *sigma, const HubEntry *hub_list,
+                                                     double *val, const HubEntry *hub_list,
                                                      unsigned int *hub_cnt, double *partial,
                                                      unsigned long long *prof) {
     if (c->done) return;
@@ -611,13 +628,14 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
         ms_hub_chunk(h, (int32_t)k, partial, hub_cnt + (jh - hlo),
-                     [&] { return dense_sigma(beg, end, m, pl, ci, front_par, sigma, pr); },
+                     [&] { return dense_sum(beg, end, m, pl, ci, front_par, val, pr); },
                      [&](double s) {
-                         if ((m >> lane) & 1ull) {
-                             sigma[(int64_t)h.v * kSlots + lane] = s;
+                         const bool mine = (m >> lane) & 1ull;
+                         if (mine) {
+                             val[qvb[h.entry] + rank_in(m, lane)] = s;
                              my_max = fmax(my_max, s);
                          }
-                         my_flag |= __ballot(((m >> lane) & 1ull) && sigma_is_large(s));
+                         my_flag |= __ballot(mine && sigma_is_large(s));
                      });
         if (lane == 0) my_dag += pr;
     }
@@ -633,17 +651,29 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
     }
 }
 
-// Reverse sweep of one level.  Every entry re-publishes {mask, level} in
-// front(l); dense and sparse entries get delta here, hubs in k_ms_delta_hub.
+// Finish slot `s` of an entry in the reverse pass: acc = sum of the
+// children's rho; delta = sigma * acc goes to the BC rows, and the entry's
+// value becomes rho = (1 + delta) / sigma for its parents.
+__device__ __forceinline__ void finish_slot(double acc, double *vp, double *drow) {
+    const double sg = *vp;
+    const double d = sg * acc;
+    *drow = d;
+    *vp = (1.0 + d) / sg;
+}
+
+// Reverse sweep of one level.  Every entry re-publishes {mask, level, value
+// base} in front(l); dense and sparse entries are finished here, hubs in
+// k_ms_delta_hub.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ level_off, int32_t lvl,
                                                  int32_t deepest, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
                                                  const int32_t *__restrict__ queue,
                                                  const unsigned long long *__restrict__ qmask,
+                                                 const uint32_t *__restrict__ qvb,
                                                  const uint4 *__restrict__ front_rd,
-                                                 uint4 *front_wr, const double *__restrict__ sigma,
-                                                 double *delta, unsigned long long *prof) {
+                                                 uint4 *front_wr, double *val, double *dlt,
+                                                 unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
     const int32_t lo = level_off[lvl], hi = level_off[lvl + 1];
     const uint32_t nl = (uint32_t)lvl + 1;
@@ -655,22 +685,24 @@ __global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ lev
         const bool valid = i < hi;
         int32_t v = 0, beg = 0, end = 0;
         unsigned long long m = 0;
+        uint32_t vb = 0;
         if (valid) {
             v = queue[i];
             m = qmask[i];
+            vb = qvb[i];
             beg = rp[v];
             end = rp[v + 1];
-            front_wr[v] = make_front(m, (uint32_t)lvl);
+            front_wr[v] = make_front(m, (uint32_t)lvl, vb);
             ++my_items;
             my_slots += (unsigned long long)__popcll(m);
         }
         const int32_t deg = end - beg;
-        if (deepest) {  // no children: delta is zero
+        if (deepest) {  // no children: delta = 0, rho = 1 / sigma
             unsigned long long bits = m;
             while (bits) {
                 const int s = __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                delta[(int64_t)v * kSlots + s] = 0.0;
+                finish_slot(0.0, val + vb + rank_in(m, s), dlt + (int64_t)v * kSlots + s);
             }
             continue;
         }
@@ -683,18 +715,8 @@ __global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ lev
             while (bits) {
                 const int s = __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                const double sv = sigma[(int64_t)v * kSlots + s];
-                double acc = 0.0;
-                for (int32_t e = beg; e < end; ++e) {
-                    const int32_t w = ci[e];
-                    const uint4 fw = front_rd[w];
-                    if (fw.z == nl && ((mask_of(fw) >> s) & 1ull)) {
-                        const int64_t o = (int64_t)w * kSlots + s;
-                        acc += (sv / sigma[o]) * (1.0 + delta[o]);
-                        ++my_pairs;
-                    }
-                }
-                delta[(int64_t)v * kSlots + s] = acc;
+                const double acc = sparse_sum(beg, end, s, nl, ci, front_rd, val, my_pairs);
+                finish_slot(acc, val + vb + rank_in(m, s), dlt + (int64_t)v * kSlots + s);
             }
         }
         unsigned long long dm = __ballot(dense);
@@ -702,16 +724,16 @@ __global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ lev
             const int jl = __ffsll((long long)dm) - 1;
             dm &= dm - 1;
             const int32_t vj = rl_i32(v, jl), bj = rl_i32(beg, jl), ej = rl_i32(end, jl);
+            const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
             const unsigned long long mj = rl_u64(m, jl);
-            const bool mine = (mj >> lane) & 1ull;
-            const double sv = mine ? sigma[(int64_t)vj * kSlots + lane] : 0.0;
             unsigned long long pr = 0;
-            const double acc = dense_delta(bj, ej, mj, nl, sv, ci, front_rd, sigma, delta, pr);
+            const double acc = dense_sum(bj, ej, mj, nl, ci, front_rd, val, pr);
             if (lane == 0) {
                 my_pairs += pr;
                 my_edges += (unsigned long long)(ej - bj);
             }
-            if (mine) delta[(int64_t)vj * kSlots + lane] = acc;
+            if ((mj >> lane) & 1ull)
+                finish_slot(acc, val + vbj + rank_in(mj, lane), dlt + (int64_t)vj * kSlots + lane);
         }
     }
     if (prof) {
@@ -729,8 +751,8 @@ template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_delta_hub(
     const int32_t *__restrict__ hub_off, const int32_t *__restrict__ hub_lvl_chunks, int32_t lvl,
     const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const unsigned long long *__restrict__ qmask, const uint4 *__restrict__ front_rd,
-    const double *__restrict__ sigma, double *delta, const HubEntry *hub_list,
+    const unsigned long long *__restrict__ qmask, const uint32_t *__restrict__ qvb,
+    const uint4 *__restrict__ front_rd, double *val, double *dlt, const HubEntry *hub_list,
     unsigned int *hub_cnt, double *partial, unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
     const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1], nch = hub_lvl_chunks[lvl];
@@ -745,14 +767,14 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
         const unsigned long long m = qmask[h.entry];
         const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
-        const bool mine = (m >> lane) & 1ull;
-        const double sv = mine ? sigma[(int64_t)h.v * kSlots + lane] : 0.0;
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
         ms_hub_chunk(h, (int32_t)k, partial, hub_cnt + (jh - hlo),
-                     [&] { return dense_delta(beg, end, m, nl, sv, ci, front_rd, sigma, delta, pr); },
+                     [&] { return dense_sum(beg, end, m, nl, ci, front_rd, val, pr); },
                      [&](double s) {
-                         if (mine) delta[(int64_t)h.v * kSlots + lane] = s;
+                         if ((m >> lane) & 1ull)
+                             finish_slot(s, val + qvb[h.entry] + rank_in(m, lane),
+                                         dlt + (int64_t)h.v * kSlots + lane);
                      });
         if (lane == 0) my_pairs += pr;
     }
@@ -802,22 +824,26 @@ __global__ __launch_bounds__(BS) void k_ms_bc(int32_t n, const unsigned long lon
     }
 }
 
-// Per-slot results of one level into source-major arrays (for checks).
+// Per-slot results of one level into source-major arrays (for checks):
+// distance and sigma after the forward pass (values still hold sigma),
+// delta after the reverse pass.
 __global__ void k_ms_extract(const int32_t *__restrict__ queue,
-                             const unsigned long long *__restrict__ qmask, int32_t lo, int32_t hi,
-                             int32_t lvl, int32_t n, const double *__restrict__ sigma,
-                             const double *__restrict__ delta, int32_t *out_dist,
-                             double *out_sigma, double *out_delta) {
+                             const unsigned long long *__restrict__ qmask,
+                             const uint32_t *__restrict__ qvb, int32_t lo, int32_t hi, int32_t lvl,
+                             int32_t n, const double *__restrict__ val,
+                             const double *__restrict__ dlt, int32_t *out_dist, double *out_sigma,
+                             double *out_delta) {
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
     for (int64_t i = lo + wave0; i < hi; i += nwaves) {
         const int32_t v = queue[i];
-        if (!((qmask[i] >> lane) & 1ull)) continue;
-        const int64_t o = (int64_t)lane * n + v, r = (int64_t)v * kSlots + lane;
-        out_dist[o] = lvl;
-        if (out_sigma) out_sigma[o] = sigma[r];
-        if (out_delta) out_delta[o] = lvl > 0 ? delta[r] : 0.0;
+        const unsigned long long m = qmask[i];
+        if (!((m >> lane) & 1ull)) continue;
+        const int64_t o = (int64_t)lane * n + v;
+        if (out_dist) out_dist[o] = lvl;
+        if (out_sigma) out_sigma[o] = val[qvb[i] + rank_in(m, lane)];
+        if (out_delta) out_delta[o] = lvl > 0 ? dlt[(int64_t)v * kSlots + lane] : 0.0;
     }
 }
 
@@ -826,28 +852,40 @@ __global__ void k_ms_extract(const int32_t *__restrict__ queue,
 // ---------------------------------------------------------------------------
 static int64_t hub_capacity(sp_graph g) { return (int64_t)g->n_hubs * kSlots + kSlots; }
 
-size_t batch_ws_bytes(sp_graph g, int64_t qcap) {
+static int64_t value_capacity(sp_graph g, int32_t width) {
+    return (int64_t)std::max(g->n, 1) * width + kSlots;
+}
+
+size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
     const size_t V = (size_t)std::max(g->n, 1);
-    return V * (8 + 8 + 16 + 16) + V * kSlots * 16 + (size_t)qcap * 12 + (V + 2) * 12 +
-           kSlots * 4 + (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
+    return V * (8 + 8 + 16 + 16) + V * kSlots * 8 + (size_t)value_capacity(g, width) * 8 +
+           (size_t)qcap * 16 + (V + 2) * 12 + kSlots * 4 +
+           (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
            ((size_t)g->hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
 }
 
-sp_status batch_ws_create(sp_graph g, int64_t qcap, BatchWorkspace &ws) {
+sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws) {
     ws.device = g->device;
     ws.n = g->n;
+    ws.width = width;
     const size_t V = (size_t)std::max(g->n, 1);
     ws.qcap = qcap;
+    ws.vcap = value_capacity(g, width);
+    if (ws.vcap > (int64_t)UINT32_MAX) {
+        set_error("graph too large for %d-slot passes (value bases are 32-bit)", width);
+        return SP_ERR_NOT_SUPPORTED;
+    }
     ws.level_cap = (int32_t)std::min<int64_t>((int64_t)V + 2, (int64_t)INT32_MAX);
     ws.hub_cap = hub_capacity(g);
     SP_TRY(dev_alloc((void **)&ws.seen, V * 8));
     SP_TRY(dev_alloc((void **)&ws.nxt, V * 8));
     SP_TRY(dev_alloc((void **)&ws.front[0], V * 16));
     SP_TRY(dev_alloc((void **)&ws.front[1], V * 16));
-    SP_TRY(dev_alloc((void **)&ws.sigma, V * kSlots * 8));
-    SP_TRY(dev_alloc((void **)&ws.delta, V * kSlots * 8));
+    SP_TRY(dev_alloc((void **)&ws.val, (size_t)ws.vcap * 8));
+    SP_TRY(dev_alloc((void **)&ws.dlt, V * kSlots * 8));
     SP_TRY(dev_alloc((void **)&ws.queue, (size_t)qcap * 4));
     SP_TRY(dev_alloc((void **)&ws.qmask, (size_t)qcap * 8));
+    SP_TRY(dev_alloc((void **)&ws.qvb, (size_t)qcap * 4));
     SP_TRY(dev_alloc((void **)&ws.level_off, (size_t)ws.level_cap * 4));
     SP_TRY(dev_alloc((void **)&ws.hub_off, (size_t)ws.level_cap * 4));
     SP_TRY(dev_alloc((void **)&ws.hub_lvl_chunks, (size_t)ws.level_cap * 4));
@@ -861,7 +899,7 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, BatchWorkspace &ws) {
     SP_HIP(hipHostMalloc((void **)&ws.staging, kSlots * (4 + 8 + 4), hipHostMallocDefault));
     SP_HIP(hipEventCreate(&ws.ev0));
     SP_HIP(hipEventCreate(&ws.ev1));
-    ws.bytes = batch_ws_bytes(g, qcap);
+    ws.bytes = batch_ws_bytes(g, qcap, width);
     return SP_OK;
 }
 
@@ -870,10 +908,11 @@ void batch_ws_destroy(BatchWorkspace &ws) {
     dev_free(ws.nxt);
     dev_free(ws.front[0]);
     dev_free(ws.front[1]);
-    dev_free(ws.sigma);
-    dev_free(ws.delta);
+    dev_free(ws.val);
+    dev_free(ws.dlt);
     dev_free(ws.queue);
     dev_free(ws.qmask);
+    dev_free(ws.qvb);
     dev_free(ws.level_off);
     dev_free(ws.hub_off);
     dev_free(ws.hub_lvl_chunks);
@@ -892,12 +931,15 @@ void batch_ws_destroy(BatchWorkspace &ws) {
 static sp_status grow_queue(sp_graph g, BatchWorkspace &ws, int64_t qcap) {
     dev_free(ws.queue);
     dev_free(ws.qmask);
+    dev_free(ws.qvb);
     ws.queue = nullptr;
     ws.qmask = nullptr;
+    ws.qvb = nullptr;
     SP_TRY(dev_alloc((void **)&ws.queue, (size_t)qcap * 4));
     SP_TRY(dev_alloc((void **)&ws.qmask, (size_t)qcap * 8));
+    SP_TRY(dev_alloc((void **)&ws.qvb, (size_t)qcap * 4));
     ws.qcap = qcap;
-    ws.bytes = batch_ws_bytes(g, qcap);
+    ws.bytes = batch_ws_bytes(g, qcap, ws.width);
     return SP_OK;
 }
 
@@ -913,8 +955,8 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
     hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.seen, ws.nxt,
                        ws.front[0], ws.front[1], n);
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, s, ws.ctl, (const int32_t *)g->row_ptr,
-                       (const int32_t *)ws.queue, (const unsigned long long *)ws.qmask, n0, ws.seen,
-                       ws.front[0], ws.sigma, ws.level_off, ws.hub_list, ws.hub_off,
+                       (const int32_t *)ws.queue, (const unsigned long long *)ws.qmask, ws.qvb, n0,
+                       ws.seen, ws.front[0], ws.val, ws.level_off, ws.hub_list, ws.hub_off,
                        ws.hub_lvl_chunks, n, (long long)g->nnz, active,
                        may_pull ? o.alpha : 0.0, o.beta);  // alpha 0: never switch to bottom-up
     SP_HIP(hipGetLastError());
@@ -940,9 +982,9 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
             {
                 ProfScope ps(P_MS_SIGMA, s);
                 hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                                   g->col_idx, ws.queue, ws.qmask, ws.seen, ws.nxt, fcur, fnxt,
-                                   ws.sigma, ws.hub_list, (long long)ws.hub_cap, active,
-                                   (long long)ws.qcap, prof_counters(P_MS_SIGMA));
+                                   g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
+                                   ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
+                                   active, (long long)ws.qcap, prof_counters(P_MS_SIGMA));
             }
             hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks, (long long)ws.qcap,
@@ -951,8 +993,9 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
                 ProfScope ps(P_MS_SIGMA, s);
                 hipLaunchKernelGGL(k_ms_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s, ws.ctl,
                                    g->row_ptr, g->col_idx, (const unsigned long long *)ws.qmask,
-                                   (const uint4 *)fcur, ws.sigma, (const HubEntry *)ws.hub_list,
-                                   ws.hub_cnt, ws.partial, prof_counters(P_MS_SIGMA));
+                                   (const uint32_t *)ws.qvb, (const uint4 *)fcur, ws.val,
+                                   (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
+                                   prof_counters(P_MS_SIGMA));
             }
         }
         SP_HIP(hipGetLastError());
@@ -968,10 +1011,23 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
     return SP_OK;
 }
 
+static sp_status launch_extract(sp_graph g, BatchWorkspace &ws, const std::vector<int32_t> &off,
+                                int32_t *dist, double *sigma, double *delta, hipStream_t s) {
+    for (size_t l = 0; l + 1 < off.size(); ++l) {
+        const int64_t cnt = off[l + 1] - off[l];
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL(k_ms_extract, dim3(grid_for(cnt * kWave, 256, 4096)), dim3(256), 0, s,
+                           ws.queue, ws.qmask, ws.qvb, off[l], off[l + 1], (int32_t)l, g->n, ws.val,
+                           ws.dlt, dist, sigma, delta);
+    }
+    SP_HIP(hipGetLastError());
+    return SP_OK;
+}
+
 template <int BS>
 static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
                               double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
-                              BatchResult *res, bool keep_levels) {
+                              BatchResult *res, const BatchExtract *ex) {
     const int32_t n = g->n;
     const unsigned long long active = nslots >= 64 ? ~0ull : ((1ull << nslots) - 1ull);
     // Level 0: distinct source vertices with the mask of their slots.
@@ -1011,6 +1067,8 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
     SP_HIP(hipMemcpyAsync(hch.data(), ws.hub_lvl_chunks, sizeof(int32_t) * levels,
                           hipMemcpyDeviceToHost, s));
     SP_HIP(hipStreamSynchronize(s));
+    if (ex && (ex->dist || ex->sigma))
+        SP_TRY(launch_extract(g, ws, off, ex->dist, ex->sigma, nullptr, s));
     const int maxb = device_cu_count() * 8;
     for (int32_t l = levels - 1; l >= 1; --l) {
         const int64_t cnt = off[l + 1] - off[l];
@@ -1020,20 +1078,21 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
             ProfScope ps(P_MS_DELTA, s);
             hipLaunchKernelGGL(k_ms_delta<BS>, dim3(grid_for(cnt, BS, maxb)), dim3(BS), 0, s,
                                ws.level_off, l, (int32_t)deepest, g->row_ptr, g->col_idx, ws.queue,
-                               ws.qmask, (const uint4 *)frd, fwr, ws.sigma, ws.delta,
-                               prof_counters(P_MS_DELTA));
+                               ws.qmask, (const uint32_t *)ws.qvb, (const uint4 *)frd, fwr, ws.val,
+                               ws.dlt, prof_counters(P_MS_DELTA));
         }
         if (!deepest && hch[l] > 0) {
             ProfScope ps(P_MS_DELTA, s);
             hipLaunchKernelGGL(k_ms_delta_hub<BS>, dim3(grid_for((int64_t)hch[l] * kWave, BS, maxb)),
                                dim3(BS), 0, s, (const int32_t *)ws.hub_off,
                                (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
-                               (const unsigned long long *)ws.qmask, (const uint4 *)frd, ws.sigma,
-                               ws.delta, (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
-                               prof_counters(P_MS_DELTA));
+                               (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
+                               (const uint4 *)frd, ws.val, ws.dlt, (const HubEntry *)ws.hub_list,
+                               ws.hub_cnt, ws.partial, prof_counters(P_MS_DELTA));
         }
     }
     SP_HIP(hipGetLastError());
+    if (ex && ex->delta) SP_TRY(launch_extract(g, ws, off, nullptr, nullptr, ex->delta, s));
     bool any_out = false;
     SlotTable tbl{};
     for (int32_t i = 0; i < kSlots; ++i) {
@@ -1043,7 +1102,7 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
     if (any_out) {
         ProfScope ps(P_MS_BC, s);
         hipLaunchKernelGGL(k_ms_bc<BS>, dim3(grid_for(n, BS, maxb)), dim3(BS), 0, s, n, ws.seen,
-                           ws.delta, ws.slot_src, nslots, tbl, prof_counters(P_MS_BC));
+                           ws.dlt, ws.slot_src, nslots, tbl, prof_counters(P_MS_BC));
         SP_HIP(hipGetLastError());
     }
     if (res) {
@@ -1055,40 +1114,27 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         res->bu = c.bottomup_levels;
         res->entries = off[levels];
     }
-    if (keep_levels) ws.kept_off = std::move(off);
     return SP_OK;
 }
 
 sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
                     double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
-                    BatchResult *res, bool keep_levels) {
-    if (nslots < 1 || nslots > kSlots) {
-        set_error("batch of %d sources (1..64 allowed)", nslots);
+                    BatchResult *res, const BatchExtract *ex) {
+    if (nslots < 1 || nslots > ws.width) {
+        set_error("batch of %d sources (1..%d allowed)", nslots, ws.width);
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (ex) {
+        const int64_t total = (int64_t)nslots * g->n;
+        if (ex->dist) SP_TRY(launch_fill_i32(ex->dist, total, -1, s));
+        if (ex->sigma) SP_TRY(launch_fill_f64(ex->sigma, total, 0.0, s));
+        if (ex->delta) SP_TRY(launch_fill_f64(ex->delta, total, 0.0, s));
+    }
     switch (o.block) {
-        case 128: return batch_run_bs<128>(g, ws, srcs, nslots, bc_of_slot, o, s, res, keep_levels);
-        case 512: return batch_run_bs<512>(g, ws, srcs, nslots, bc_of_slot, o, s, res, keep_levels);
-        default: return batch_run_bs<256>(g, ws, srcs, nslots, bc_of_slot, o, s, res, keep_levels);
+        case 128: return batch_run_bs<128>(g, ws, srcs, nslots, bc_of_slot, o, s, res, ex);
+        case 512: return batch_run_bs<512>(g, ws, srcs, nslots, bc_of_slot, o, s, res, ex);
+        default: return batch_run_bs<256>(g, ws, srcs, nslots, bc_of_slot, o, s, res, ex);
     }
-}
-
-sp_status batch_extract(sp_graph g, BatchWorkspace &ws, int32_t nslots, int32_t *out_dist,
-                        double *out_sigma, double *out_delta, hipStream_t s) {
-    const int64_t total = (int64_t)nslots * g->n;
-    SP_TRY(launch_fill_i32(out_dist, total, -1, s));
-    if (out_sigma) SP_TRY(launch_fill_f64(out_sigma, total, 0.0, s));
-    if (out_delta) SP_TRY(launch_fill_f64(out_delta, total, 0.0, s));
-    const std::vector<int32_t> &off = ws.kept_off;
-    for (size_t l = 0; l + 1 < off.size(); ++l) {
-        const int64_t cnt = off[l + 1] - off[l];
-        if (cnt <= 0) continue;
-        hipLaunchKernelGGL(k_ms_extract, dim3(grid_for(cnt * kWave, 256, 4096)), dim3(256), 0, s,
-                           ws.queue, ws.qmask, off[l], off[l + 1], (int32_t)l, g->n, ws.sigma,
-                           ws.delta, out_dist, out_sigma, out_delta);
-    }
-    SP_HIP(hipGetLastError());
-    return SP_OK;
 }
 
 }  // namespace sp

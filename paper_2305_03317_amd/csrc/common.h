@@ -112,6 +112,7 @@ struct LevelCtl {
     unsigned long long next_deg;   // adjacency entries of the next frontier (accumulating)
     unsigned long long unset_deg;  // adjacency entries of vertices not yet reached
     unsigned long long reached_pairs;   // batched path: (slot, vertex) pairs reached
+    unsigned long long vtail;           // batched path: next free value (compact storage)
     unsigned long long sigma_max_bits;  // bit pattern of the largest sigma (>= 0, so
                                         // integer order = value order; NaN sorts above inf)
     unsigned long long flagged_slots;   // batched path: slots with sigma > 1e300 / non-finite
@@ -203,10 +204,16 @@ struct BatchWorkspace {
     unsigned long long *seen = nullptr;  // V: slots that reached v at any level so far
     unsigned long long *nxt = nullptr;   // V: slots discovering v at the level being built
     uint4 *front[2] = {nullptr, nullptr};  // V: {mask lo, mask hi, level tag, pad} by level parity
-    double *sigma = nullptr;             // V x 64, vertex-major: sigma[v * 64 + slot]
-    double *delta = nullptr;             // V x 64
+    // Values of an entry (v, level, mask m) are stored compactly: slot s of m
+    // lives at val[vb + rank_m(s)], rank_m(s) = set bits of m below s, where vb
+    // is the entry's value base.  val holds sigma after the forward pass and
+    // rho = (1 + delta) / sigma once the reverse pass has visited the entry.
+    double *val = nullptr;               // vcap values
+    int64_t vcap = 0;
+    double *dlt = nullptr;               // V x 64, vertex-major: delta[v * 64 + slot] (for BC)
     int32_t *queue = nullptr;            // entries: vertex ids, levels concatenated
     unsigned long long *qmask = nullptr; // entries: slot mask of the vertex at that level
+    uint32_t *qvb = nullptr;             // entries: value base
     int64_t qcap = 0;
     int32_t *level_off = nullptr;        // device, level_cap + 2
     int32_t level_cap = 0;
@@ -222,16 +229,23 @@ struct BatchWorkspace {
     void *staging = nullptr;             // pinned: level-0 entries and slot sources
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t bytes = 0;
-    std::vector<int32_t> kept_off;       // level offsets of the last pass (host copy)
+    int32_t width = 0;                   // slots the value store is sized for
 };
-size_t batch_ws_bytes(sp_graph g, int64_t qcap);
-sp_status batch_ws_create(sp_graph g, int64_t qcap, BatchWorkspace &ws);
+size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width);
+sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws);
 void batch_ws_destroy(BatchWorkspace &ws);
 
 struct BatchRunOpts {
     double alpha = 15.0, beta = 24.0;
     int block = 256;
     int chunk_levels = 8;
+};
+
+// Per-slot results of a pass, source-major ([slot * V + v]); any may be null.
+struct BatchExtract {
+    int32_t *dist = nullptr;
+    double *sigma = nullptr;
+    double *delta = nullptr;
 };
 
 // One multi-source pass over up to 64 sources (slot i <- srcs[i]).
@@ -248,10 +262,7 @@ struct BatchResult {
 };
 sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
                     double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
-                    BatchResult *res, bool keep_levels = false);
-// After batch_run(keep_levels = true): per-slot dist/sigma/delta, source-major.
-sp_status batch_extract(sp_graph g, BatchWorkspace &ws, int32_t nslots, int32_t *out_dist,
-                        double *out_sigma, double *out_delta, hipStream_t s);
+                    BatchResult *res, const BatchExtract *ex = nullptr);
 
 // Workspace pools and configuration shared by the entry points and the server.
 int64_t initial_qcap(int32_t n, int32_t width);

@@ -332,3 +332,92 @@ def sp_autotune(g: Graph, sources, stream=None) -> dict:
     c = sp_batch_config()
     _check(lib().sp_autotune(g.handle, p, len(src), ctypes.byref(c), _stream(stream)), "sp_autotune")
     return _struct_dict(c)
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+
+class Request:
+    """A submitted BC request; `out_bc` is filled when it completes."""
+
+    def __init__(self, handle, out_bc):
+        self.handle = handle
+        self.out_bc = out_bc
+
+    def wait(self, timeout_us: int = -1) -> int:
+        st = ctypes.c_int32()
+        rc = lib().sp_request_wait(self.handle, timeout_us, ctypes.byref(st))
+        if rc == SP_ERR_TIMEOUT:
+            raise TimeoutError("request still running")
+        _check(rc, "sp_request_wait")
+        return st.value
+
+    def poll(self):
+        done = ctypes.c_int32()
+        st = ctypes.c_int32()
+        _check(lib().sp_request_poll(self.handle, ctypes.byref(done), ctypes.byref(st)), "sp_request_poll")
+        return bool(done.value), st.value
+
+    def cancel(self) -> int:
+        return lib().sp_request_cancel(self.handle)
+
+    def latency_us(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().sp_request_latency_us(self.handle, ctypes.byref(v)), "sp_request_latency_us")
+        return v.value
+
+    def release(self):
+        if self.handle:
+            _check(lib().sp_request_release(self.handle), "sp_request_release")
+            self.handle = None
+
+
+class Server:
+    """Continuous-batching BC server over resident graphs (sp_server_*)."""
+
+    def __init__(self, memory_budget: int = 0, max_batch: int = 0, n_streams: int = 0):
+        c = sp_server_config()
+        c.memory_budget = memory_budget
+        c.max_batch = max_batch
+        c.n_streams = n_streams
+        h = ctypes.c_void_p()
+        _check(lib().sp_server_create(ctypes.byref(c), ctypes.byref(h)), "sp_server_create")
+        self.handle = h
+        self.graphs = {}
+
+    def add_graph(self, g: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(lib().sp_server_add_graph(self.handle, g.handle, ctypes.byref(gid)), "sp_server_add_graph")
+        self.graphs[gid.value] = g
+        return gid.value
+
+    def submit(self, graph_id: int, sources, out_bc=None) -> Request:
+        torch = _torch()
+        g = self.graphs.get(graph_id)
+        if out_bc is None:
+            n = g.n if g is not None else 1
+            out_bc = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        src, p = _host_i32(sources)
+        h = ctypes.c_void_p()
+        _check(lib().sp_stream_submit(self.handle, graph_id, p, len(src), out_bc.data_ptr(),
+                                      ctypes.byref(h)), "sp_stream_submit")
+        return Request(h, out_bc)
+
+    def stats(self) -> dict:
+        s = sp_server_stats()
+        _check(lib().sp_server_get_stats(self.handle, ctypes.byref(s)), "sp_server_get_stats")
+        return _struct_dict(s)
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().sp_server_destroy(self.handle), "sp_server_destroy")
+            self.handle = None
+
+
+def sp_server_create(memory_budget: int = 0, max_batch: int = 0, n_streams: int = 0) -> Server:
+    return Server(memory_budget, max_batch, n_streams)
+
+
+def sp_stream_submit(server: Server, graph_id: int, sources, out_bc=None) -> Request:
+    return server.submit(graph_id, sources, out_bc)

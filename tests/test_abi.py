@@ -97,3 +97,26 @@ def test_no_device_is_reported_not_crashed():
     h = ctypes.c_void_p()
     st = L.sp_graph_upload(2, 2, rp.ctypes.data, ci.ctypes.data, 0, None, ctypes.byref(h))
     assert st in (sp.SP_ERR_NOT_SUPPORTED, sp.SP_ERR_DEVICE)
+
+
+def test_server_calls_reject_bad_arguments_on_the_host():
+    L = sp.lib()
+    assert L.sp_server_create(None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    bad = sp.sp_server_config()
+    bad.max_batch = 65
+    h = ctypes.c_void_p()
+    assert L.sp_server_create(ctypes.byref(bad), ctypes.byref(h)) == sp.SP_ERR_INVALID_ARGUMENT
+    bad.max_batch = 0
+    bad.reserved[1] = 3
+    assert L.sp_server_create(ctypes.byref(bad), ctypes.byref(h)) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_server_add_graph(None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_stream_submit(None, 0, None, 0, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_request_wait(None, 0, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_request_poll(None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_request_cancel(None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_request_release(None) == sp.SP_OK
+    assert L.sp_server_destroy(None) == sp.SP_OK
+    assert L.sp_autotune(None, None, 0, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    n = ctypes.c_int32()
+    assert L.sp_profile_read(None, 4, ctypes.byref(n)) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_profile_enable(0) == sp.SP_OK

@@ -1,0 +1,126 @@
+"""Serving loop on the GPU: continuous batching over several resident graphs.
+
+Each request's BC must match the oracle, and be bit-identical whether the
+request runs alone or mixed with others (its sources may share passes with
+other requests and be split differently across passes)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_03317_amd import graphs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2305_03317_amd import sp as spmod
+    spmod.lib()
+    return spmod
+
+
+@pytest.fixture(scope="module")
+def resident(sp):
+    specs = [graphs.uniform(4096, 32768, 1001), graphs.rmat(12, 16, graphs.RMAT_ABC, 31),
+             graphs.road(48, 0.02, 32)]
+    gs = [sp.sp_graph_upload(rp, ci) for rp, ci in specs]
+    yield specs, gs
+    for g in gs:
+        g.release()
+
+
+def requests_for(specs, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(9):
+        gi = k % 3
+        rp, _ = specs[gi]
+        n = len(rp) - 1
+        size = int(rng.integers(1, 100))
+        reqs.append((gi, rng.integers(0, n, size).astype(np.int32)))
+    return reqs
+
+
+def test_alone_equals_mixed_and_oracle(sp, resident):
+    specs, gs = resident
+    reqs = requests_for(specs, 5)
+    srv = sp.Server(n_streams=2)
+    ids = [srv.add_graph(g) for g in gs]
+    alone = []
+    for gi, src in reqs:
+        r = srv.submit(ids[gi], src)
+        assert r.wait() == sp.SP_OK
+        alone.append(r.out_bc[:gs[gi].n].cpu().numpy().copy())
+        r.release()
+    live = [srv.submit(ids[gi], src) for gi, src in reqs]
+    for (gi, src), r, a in zip(reqs, live, alone):
+        assert r.wait() == sp.SP_OK
+        got = r.out_bc[:gs[gi].n].cpu().numpy()
+        assert np.array_equal(got, a), "mixed result differs from the same request alone"
+        rp, ci = specs[gi]
+        ref = oracle.bc(rp, ci, src)
+        nz = ref != 0
+        assert np.all(got[~nz] == 0)
+        assert np.max(np.abs(got[nz] - ref[nz]) / ref[nz]) <= 1e-9
+        assert r.latency_us() > 0
+        r.release()
+    st = srv.stats()
+    assert st["completed"] == 2 * len(reqs) and st["failed"] == 0
+    assert st["slots_used"] == 2 * sum(len(s) for _, s in reqs)
+    srv.destroy()
+
+
+def test_memory_budget_admission_and_rejection(sp, resident):
+    specs, gs = resident
+    need = max(sp.sp_bc_workspace_bytes(g, 64) for g in gs)
+    srv = sp.Server(memory_budget=need + 1024, n_streams=2)
+    ids = [srv.add_graph(g) for g in gs]
+    reqs = requests_for(specs, 6)
+    live = [(gi, src, srv.submit(ids[gi], src)) for gi, src in reqs]
+    for gi, src, r in live:
+        assert r.wait() == sp.SP_OK
+        rp, ci = specs[gi]
+        ref = oracle.bc(rp, ci, src)
+        got = r.out_bc[:gs[gi].n].cpu().numpy()
+        nz = ref != 0
+        assert np.max(np.abs(got[nz] - ref[nz]) / ref[nz]) <= 1e-9
+        r.release()
+    st = srv.stats()
+    assert st["peak_admitted_bytes"] <= need + 1024
+    srv.destroy()
+    tiny = sp.Server(memory_budget=4096, n_streams=1)
+    gid = tiny.add_graph(gs[0])
+    with pytest.raises(sp.SpError) as ei:
+        tiny.submit(gid, [1, 2, 3])
+    assert ei.value.status == sp.SP_ERR_REJECTED
+    assert tiny.stats()["rejected"] == 1
+    tiny.destroy()
+
+
+def test_cancel_invalid_and_empty(sp, resident):
+    specs, gs = resident
+    srv = sp.Server(n_streams=1, max_batch=8)
+    gid = srv.add_graph(gs[1])
+    first = srv.submit(gid, np.arange(1, 400, dtype=np.int32) % gs[1].n)
+    last = srv.submit(gid, [5, 6, 7])
+    rc = last.cancel()
+    if rc == sp.SP_OK:
+        assert last.wait() == sp.SP_ERR_CANCELLED
+        assert srv.stats()["cancelled"] == 1
+    else:  # already started: it completes normally
+        assert last.wait() == sp.SP_OK
+    assert first.wait() == sp.SP_OK
+    with pytest.raises(sp.SpError):
+        srv.submit(gid, [gs[1].n])          # source out of range
+    with pytest.raises(sp.SpError):
+        srv.submit(gid + 7, [0])            # unknown graph
+    empty = srv.submit(gid, [])
+    assert empty.wait() == sp.SP_OK
+    assert np.all(empty.out_bc[:gs[1].n].cpu().numpy() == 0)
+    for r in (first, last, empty):
+        r.release()
+    srv.destroy()
