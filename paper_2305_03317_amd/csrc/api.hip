@@ -346,7 +346,8 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     SP_GUARD_BEGIN
     clear_error();
     if (!out || n_vertices < 0 || n_vertices == INT32_MAX || nnz < 0 || nnz >= INT32_MAX ||
-        !row_ptr || (nnz > 0 && !col_idx) || (flags & ~(SP_PTR_DEVICE | SP_VALIDATE))) {
+        !row_ptr || (nnz > 0 && !col_idx) ||
+        (flags & ~(SP_PTR_DEVICE | SP_VALIDATE))) {
         set_error("sp_graph_upload: bad arguments");
         return SP_ERR_INVALID_ARGUMENT;
     }

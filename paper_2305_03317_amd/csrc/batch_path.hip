@@ -222,24 +222,26 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->level = 0;
         c->lo = 0;
         c->hi = n0;
-        c->tail = n0;
+        c->tail_.v = n0;
         c->done = 0;
         c->mode = MODE_TOPDOWN;
-        c->overflow = 0;
+        c->overflow_.v = 0;
         c->front_deg = fdeg;
-        c->next_deg = 0;
-        c->settled_deg = 0;
-        c->reached_pairs = pairs;
-        c->vtail = s_vb[n0];
+        c->next_deg_.v = 0;
+        c->settled_deg_.v = 0;
+        c->reached_pairs = pairs;  // = s_vb[n0]
+        c->vtail_.v = s_vb[n0];
         c->unset_deg = (unsigned long long)nnz - settled;
-        c->sigma_max_bits = (unsigned long long)__double_as_longlong(1.0);
-        c->flagged_slots = 0;
+        c->sigma_max_bits_.v = (unsigned long long)__double_as_longlong(1.0);
+        c->flagged_slots_.v = 0;
+        c->live = active;  // every slot's level-0 frontier holds its source
+        c->nlive_.v = 0;
         c->alpha = alpha;
         c->beta = beta;
         c->n_vertices = n;
         c->topdown_levels = 0;
         c->bottomup_levels = 0;
-        c->hub_pack = 0;
+        c->hub_pack_.v = 0;
         c->hub_lo = 0;
         c->hub_hi = nh;
         c->hub_nchunks = nch;
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
                     w = ci[s_beg[a] + (k - s_off[a])];
                     claim = visit(w, s_mask[a]);
                 }
-                q.stage(claim, w, &c->tail, queue, qcap, &c->overflow);
+                q.stage(claim, w, &c->tail_.v, queue, qcap, &c->overflow_.v);
             }
             __syncthreads();
         }
@@ -330,11 +332,11 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
                     w = ci[e];
                     claim = visit(w, fm);
                 }
-                q.stage(claim, w, &c->tail, queue, qcap, &c->overflow);
+                q.stage(claim, w, &c->tail_.v, queue, qcap, &c->overflow_.v);
             }
         }
     }
-    q.finish(&c->tail, queue, qcap, &c->overflow);
+    q.finish(&c->tail_.v, queue, qcap, &c->overflow_.v);
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
         int32_t beg = 0, deg = 0;
         unsigned long long u_s = 0;
         if (v < n) {
-            u_s = active & ~seen[v];
+            u_s = active & c->live & ~seen[v];
             if (u_s) {
                 beg = rp[v];
                 deg = rp[v + 1] - beg;
@@ -415,9 +417,9 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
         __builtin_amdgcn_wave_barrier();
         const unsigned long long found = acc[lane];
         if (found) nxt[v] = found;
-        q.stage(found != 0ull, v, &c->tail, queue, qcap, &c->overflow);
+        q.stage(found != 0ull, v, &c->tail_.v, queue, qcap, &c->overflow_.v);
     }
-    q.finish(&c->tail, queue, qcap, &c->overflow);
+    q.finish(&c->tail_.v, queue, qcap, &c->overflow_.v);
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
@@ -436,16 +438,18 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
                                                  uint4 *front_nxt, double *val, long long vcap,
                                                  HubEntry *hub_list, long long hub_cap,
                                                  unsigned long long active, long long qcap,
-                                                 unsigned long long *prof) {
+                                                 int32_t track_deg, unsigned long long *prof) {
     if (c->done) return;
-    __shared__ unsigned long long s_red[1], s_base[1];
+    __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
     __shared__ int32_t s_scan[BS / kWave + 1];
     const uint32_t lvl = (uint32_t)c->level;
     const int32_t hi = c->hi;
-    const int32_t tail = (int32_t)min((long long)c->tail, qcap);
+    const int32_t tail = (int32_t)min((long long)c->tail_.v, qcap);
     const int lane = lane_id();
+    if (threadIdx.x == 0) s_or[0] = 0;
+    __syncthreads();
     unsigned long long my_deg = 0, my_settled = 0, my_flag = 0, my_pairs = 0, my_items = 0,
-                       my_dag = 0;
+                       my_dag = 0, my_or = 0;
     double my_max = 0.0;
     for (int32_t b = hi + (int32_t)(blockIdx.x * BS); b < tail; b += gridDim.x * BS) {
         const int32_t i = b + (int32_t)threadIdx.x;
@@ -463,13 +467,13 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
         // value range of this entry: block scan + one atomic per block
         int32_t btotal;
         const int32_t excl = block_excl_scan<BS>(pc, s_scan, &btotal);
-        if (threadIdx.x == 0) s_base[0] = btotal ? atomicAdd(&c->vtail, (unsigned long long)btotal) : 0ull;
+        if (threadIdx.x == 0) s_base[0] = btotal ? atomicAdd(&c->vtail_.v, (unsigned long long)btotal) : 0ull;
         __syncthreads();
         const unsigned long long vb64 = s_base[0] + (unsigned long long)excl;
         __syncthreads();
         const bool fits = vb64 + (unsigned long long)pc <= (unsigned long long)vcap;
         const uint32_t vb = (uint32_t)vb64;
-        if (valid && !fits) atomicOr(&c->overflow, 1);
+        if (valid && !fits) atomicOr(&c->overflow_.v, 1);
         const bool hub = valid && fits && deg > kHubDeg;
         const bool sparse = valid && fits && !hub && pc <= kSparseSlots && deg <= kSparseDeg;
         const bool dense = valid && fits && !hub && !sparse;
@@ -511,21 +515,33 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
             front_nxt[w] = make_front(m, lvl + 1, vb);
             my_deg += (unsigned long long)deg;
             my_pairs += (unsigned long long)pc;
+            my_or |= m;
             ++my_items;
             if (now == active) my_settled += (unsigned long long)deg;
         }
     }
     my_max = wave_max_f64(my_max);
-    for (int o = 32; o > 0; o >>= 1) my_flag |= __shfl_xor(my_flag, o, kWave);
-    if (lane == 0) {
-        atomic_max_nonneg_f64(&c->sigma_max_bits, my_max);
-        if (my_flag) atomicOr(&c->flagged_slots, my_flag);
+    for (int o = 32; o > 0; o >>= 1) {
+        my_flag |= __shfl_xor(my_flag, o, kWave);
+        my_or |= __shfl_xor(my_or, o, kWave);
     }
-    block_add_u64<BS>(my_deg, s_red, &c->next_deg);
+    if (lane == 0) {
+        atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
+        if (my_flag) atomicOr(&c->flagged_slots_.v, my_flag);
+        if (my_or) atomicOr(&s_or[0], my_or);  // LDS
+    }
     __syncthreads();
-    block_add_u64<BS>(my_settled, s_red, &c->settled_deg);
-    __syncthreads();
-    block_add_u64<BS>(my_pairs, s_red, &c->reached_pairs);
+    if (threadIdx.x == 0 && s_or[0]) {
+        // bits are only added during a level: a stale read is a subset of the
+        // current value, so skipping when it already holds our bits is safe
+        const unsigned long long cur = *(volatile unsigned long long *)&c->nlive_.v;
+        if ((cur | s_or[0]) != cur) atomicOr(&c->nlive_.v, s_or[0]);
+    }
+    if (track_deg) {  // only the direction switch needs these sums
+        block_add_u64<BS>(my_deg, s_red, &c->next_deg_.v);
+        __syncthreads();
+        block_add_u64<BS>(my_settled, s_red, &c->settled_deg_.v);
+    }
     if (prof) {
         __syncthreads();
         block_add_u64<BS>(my_items, s_red, prof + 0);
@@ -542,33 +558,36 @@ __global__ void k_ms_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
                              int32_t *hub_lvl_chunks, long long qcap, long long hub_cap) {
     if (c->done) return;
     if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
-    const unsigned long long hp = c->hub_pack;
-    if ((long long)c->tail > qcap || c->overflow ||
+    const unsigned long long hp = c->hub_pack_.v;
+    if ((long long)c->tail_.v > qcap || c->overflow_.v ||
         (long long)c->hub_next + (long long)(hp >> 40) > hub_cap) {
-        c->overflow = 1;
+        c->overflow_.v = 1;
         c->done = 1;
         return;
     }
-    const int32_t nf = c->tail - c->hi;
+    const int32_t nf = c->tail_.v - c->hi;
     if (nf <= 0) {
         c->done = 1;
         return;
     }
     const int32_t nl = c->level + 1;
-    level_off[nl + 1] = c->tail;
+    level_off[nl + 1] = c->tail_.v;
     c->hub_lo = c->hub_next;
     c->hub_hi = c->hub_next + (int32_t)(hp >> 40);
     c->hub_nchunks = (int32_t)(hp & ((1ull << 40) - 1));
     c->hub_next = c->hub_hi;
-    c->hub_pack = 0;
+    c->hub_pack_.v = 0;
     hub_off[nl + 1] = c->hub_hi;
     hub_lvl_chunks[nl] = c->hub_nchunks;
-    c->front_deg = c->next_deg;
-    c->unset_deg -= c->settled_deg;
-    c->next_deg = 0;
-    c->settled_deg = 0;
+    c->front_deg = c->next_deg_.v;
+    c->unset_deg -= c->settled_deg_.v;
+    c->next_deg_.v = 0;
+    c->settled_deg_.v = 0;
+    c->reached_pairs = c->vtail_.v;  // every reached (slot, vertex) pair owns one value
+    c->live = c->nlive_.v;
+    c->nlive_.v = 0;
     c->lo = c->hi;
-    c->hi = c->tail;
+    c->hi = c->tail_.v;
     c->level = nl;
     if (c->mode == MODE_TOPDOWN) {
         if ((double)c->front_deg * c->alpha > (double)c->unset_deg) c->mode = MODE_BOTTOMUP;
@@ -641,8 +660,8 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
     }
     my_max = wave_max_f64(my_max);
     if (lane == 0) {
-        atomic_max_nonneg_f64(&c->sigma_max_bits, my_max);
-        if (my_flag) atomicOr(&c->flagged_slots, my_flag);
+        atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
+        if (my_flag) atomicOr(&c->flagged_slots_.v, my_flag);
     }
     if (prof) {
         block_add_u64<BS>(my_edges, s_red, prof + 1);
@@ -984,7 +1003,8 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
                 hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
                                    g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
                                    ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
-                                   active, (long long)ws.qcap, prof_counters(P_MS_SIGMA));
+                                   active, (long long)ws.qcap, (int32_t)may_pull,
+                                   prof_counters(P_MS_SIGMA));
             }
             hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks, (long long)ws.qcap,
@@ -1051,7 +1071,7 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         SP_HIP(hipMemcpyAsync(ws.qmask, h_m, n0 * 8, hipMemcpyHostToDevice, s));
         SP_HIP(hipMemcpyAsync(ws.slot_src, h_src, kSlots * 4, hipMemcpyHostToDevice, s));
         SP_TRY(batch_forward<BS>(g, ws, n0, active, o, s));
-        if (!ws.ctl_host->overflow) break;
+        if (!ws.ctl_host->overflow_.v) break;
         if (attempt == 1) {
             set_error("multi-source queue overflow at capacity %lld", (long long)ws.qcap);
             return SP_ERR_DEVICE;
@@ -1108,8 +1128,8 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
     if (res) {
         res->levels = levels;
         res->reached = (int64_t)c.reached_pairs;
-        std::memcpy(&res->sigma_max, &c.sigma_max_bits, sizeof(double));
-        res->flagged = __builtin_popcountll(c.flagged_slots);
+        std::memcpy(&res->sigma_max, &c.sigma_max_bits_.v, sizeof(double));
+        res->flagged = __builtin_popcountll(c.flagged_slots_.v);
         res->td = c.topdown_levels;
         res->bu = c.bottomup_levels;
         res->entries = off[levels];

@@ -100,34 +100,47 @@ struct HubEntry {
     int32_t nchunks;
 };
 
+// Counters that many workgroups update with atomics each sit on their own
+// 128-byte line, so updates of one do not queue behind another's.
+struct alignas(128) HotU64 {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
+struct alignas(128) HotI32 {
+    int32_t v;
+    int32_t pad[31];
+};
+
 struct LevelCtl {
+    // read-mostly part (written by init/advance)
     int32_t level;      // level of the current frontier
     int32_t lo, hi;     // current frontier = queue[lo, hi)
-    int32_t tail;       // append position for the next frontier (starts at hi)
     int32_t done;       // 1 once a level produced no new vertex
     int32_t mode;       // MODE_* chosen for expanding the current frontier
-    int32_t overflow;   // batched path: queue capacity exceeded
-    int32_t pad0;
-    unsigned long long front_deg;  // adjacency entries of the current frontier
-    unsigned long long next_deg;   // adjacency entries of the next frontier (accumulating)
-    unsigned long long unset_deg;  // adjacency entries of vertices not yet reached
-    unsigned long long reached_pairs;   // batched path: (slot, vertex) pairs reached
-    unsigned long long vtail;           // batched path: next free value (compact storage)
-    unsigned long long sigma_max_bits;  // bit pattern of the largest sigma (>= 0, so
-                                        // integer order = value order; NaN sorts above inf)
-    unsigned long long flagged_slots;   // batched path: slots with sigma > 1e300 / non-finite
-    unsigned long long settled_deg;     // batched path: adjacency entries of vertices that
-                                        // became reached by every slot at this level
-    double alpha, beta;                 // direction thresholds
     int32_t n_vertices;
     int32_t topdown_levels, bottomup_levels;
-    int32_t pad1;
+    unsigned long long front_deg;  // adjacency entries of the current frontier
+    unsigned long long unset_deg;  // adjacency entries of vertices not yet reached
+    unsigned long long reached_pairs;  // (slot, vertex) pairs reached (per-source: vertices)
+    double alpha, beta;                // direction thresholds
+    unsigned long long live;           // batched: slots with a nonempty current frontier
     // Hubs: entries of the level being built are appended at hub_next, with
     // hub_pack = (count << 40) | chunks accumulating; `advance` turns them into
     // the current level's segment [hub_lo, hub_hi) with hub_nchunks chunks.
-    unsigned long long hub_pack;
     int32_t hub_lo, hub_hi, hub_nchunks, hub_next;
+    // contended counters
+    HotI32 tail_;       // append position for the next frontier (starts at hi)
+    HotI32 overflow_;   // capacity of the queue, hub list or value store exceeded
+    HotU64 next_deg_;   // adjacency entries of the next frontier (accumulating)
+    HotU64 settled_deg_;  // batched: adjacency entries of vertices every slot has reached
+    HotU64 vtail_;      // batched: next free value (compact storage)
+    HotU64 hub_pack_;
+    HotU64 sigma_max_bits_;  // bit pattern of the largest sigma (>= 0, so integer order =
+                             // value order; NaN sorts above inf)
+    HotU64 flagged_slots_;   // slots with sigma > 1e300 / non-finite
+    HotU64 nlive_;           // batched: slots of the next frontier (accumulating)
 };
+
 
 // Measurement: kernel families timed with HIP events when profiling is on,
 // each with device counters of the work it did.
@@ -263,6 +276,7 @@ struct BatchResult {
 sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
                     double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
                     BatchResult *res, const BatchExtract *ex = nullptr);
+
 
 // Workspace pools and configuration shared by the entry points and the server.
 int64_t initial_qcap(int32_t n, int32_t width);

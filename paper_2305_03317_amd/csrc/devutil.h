@@ -238,40 +238,51 @@ __device__ __forceinline__ double wave_chunk_sum(int32_t beg, int32_t deg, const
 }
 
 // Wave-level "any": does some adjacency entry of each lane's vertex satisfy
-// pred?  Same chunking as wave_chunk_sum; a vertex stops loading entries in
-// the step after one is found.
+// pred?  The lanes with entries are compacted; group g of 8 lanes takes them
+// g, g+8, ... one at a time, 16 entries per step, and leaves a vertex in the
+// step where an entry is found, so heavy vertices that are found early cost
+// one or two steps however long their rows are.
 template <class Pred>
 __device__ __forceinline__ bool wave_chunk_any(int32_t beg, int32_t deg, const WaveScratch &ws,
                                                Pred pred) {
     const int lane = lane_id();
-    const int32_t nch = (deg + 7) >> 3;
-    const int32_t incl = wave_incl_scan(nch);
-    const int32_t total = __shfl(incl, kWave - 1, kWave);
-    ws.coff[lane] = incl - nch;
+    const unsigned long long cm = __ballot(deg > 0);
+    const int ncand = __popcll(cm);
+    if (deg > 0) ws.coff[lanes_below(cm)] = lane;  // coff holds the candidate list here
     ws.beg[lane] = beg;
     ws.deg[lane] = deg;
     ws.acc[lane] = 0.0;  // 1.0 once found
     __builtin_amdgcn_wave_barrier();
     const int g = lane >> 3, j = lane & 7;
-    for (int32_t t0 = 0; t0 < total; t0 += 8) {
-        const int32_t k = t0 + g;
-        int32_t a = -1;
-        bool hit = false;
-        if (k < total) {
-            int32_t lo = 0, hi = kWave - 1;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (ws.coff[mid] <= k) lo = mid; else hi = mid - 1;
-            }
-            a = lo;
-            const int32_t off = (k - ws.coff[a]) * 8 + j;
-            if (off < ws.deg[a] && ws.acc[a] == 0.0) hit = pred(ws.beg[a] + off, a);
+    int k = g;
+    int a = k < ncand ? ws.coff[k] : -1;
+    int32_t abeg = 0, adeg = 0, off = 0;
+    if (a >= 0) {
+        abeg = ws.beg[a];
+        adeg = ws.deg[a];
+    }
+    while (__ballot(a >= 0)) {
+        bool h0 = false, h1 = false;
+        if (a >= 0) {
+            const int32_t e0 = off + j, e1 = off + 8 + j;
+            if (e0 < adeg) h0 = pred(abeg + e0, a);
+            if (e1 < adeg) h1 = pred(abeg + e1, a);
         }
-        if (hit) ws.acc[a] = 1.0;  // several lanes may store the same value
-        __builtin_amdgcn_wave_barrier();
-        // stop once every vertex with work is found
-        const bool open = nch > 0 && ws.acc[lane] == 0.0;
-        if (!__ballot(open)) break;
+        const unsigned long long hb = __ballot(h0 || h1);
+        const bool ghit = ((hb >> (g * 8)) & 0xffull) != 0ull;
+        if (a >= 0) {
+            off += 16;
+            if (ghit || off >= adeg) {
+                if (j == 0 && ghit) ws.acc[a] = 1.0;
+                k += 8;
+                off = 0;
+                a = k < ncand ? ws.coff[k] : -1;
+                if (a >= 0) {
+                    abeg = ws.beg[a];
+                    adeg = ws.deg[a];
+                }
+            }
+        }
     }
     __builtin_amdgcn_wave_barrier();
     return ws.acc[lane] != 0.0;

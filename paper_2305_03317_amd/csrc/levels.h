@@ -14,7 +14,7 @@ namespace sp {
 __device__ __forceinline__ void hub_register(LevelCtl *c, HubEntry *list, long long cap, int32_t v,
                                              int32_t entry, int32_t deg) {
     const int32_t nch = (deg + kHubChunk - 1) / kHubChunk;
-    const unsigned long long old = atomicAdd(&c->hub_pack, (1ull << 40) | (unsigned long long)nch);
+    const unsigned long long old = atomicAdd(&c->hub_pack_.v, (1ull << 40) | (unsigned long long)nch);
     const int32_t idx = (int32_t)(old >> 40);
     const int32_t base = (int32_t)(old & ((1ull << 40) - 1));
     if ((long long)c->hub_next + idx < cap) list[c->hub_next + idx] = HubEntry{v, entry, base, nch};

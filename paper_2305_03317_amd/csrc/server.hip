@@ -66,6 +66,7 @@ struct sp_server_s {
     std::vector<std::thread> workers;
     bool stopping = false;
     size_t admitted = 0;  // bytes of workspaces held (idle + in use)
+    int held = 0;         // workspaces taken by workers (being created or running)
     sp_server_stats stats{};
 };
 
@@ -143,14 +144,15 @@ static void worker_main(sp_server_s *srv) {
         if (!gs.idle.empty()) {
             ws = gs.idle.back();
             gs.idle.pop_back();
+            srv->held++;
         } else {
             const size_t need = batch_ws_bytes(g, initial_qcap(g->n, kSlots), kSlots);
             if (!admit(srv, need, gi)) {
-                // Memory is held by passes in flight: wait for one to finish.
-                // With nothing in flight every held workspace is idle and
-                // freeable, so admission only fails if one pass exceeds the
-                // budget, which submit already rejects; fail defensively.
-                if (srv->stats.in_flight == 0) {
+                // Memory is held by other workers: wait for one to return it.
+                // With none held every workspace is idle and freeable, so
+                // admission only fails if one pass exceeds the budget, which
+                // submit already rejects; fail defensively.
+                if (srv->held == 0) {
                     while (!gs.waiting.empty() && !gs.waiting.front()->in_flight) {
                         sp_request r = gs.waiting.front();
                         gs.waiting.pop_front();
@@ -162,6 +164,7 @@ static void worker_main(sp_server_s *srv) {
                 continue;
             }
             srv->admitted += need;
+            srv->held++;
             srv->stats.admitted_bytes = srv->admitted;
             srv->stats.peak_admitted_bytes = std::max(srv->stats.peak_admitted_bytes, srv->admitted);
             lk.unlock();
@@ -175,11 +178,13 @@ static void worker_main(sp_server_s *srv) {
                     delete ws;
                 }
                 srv->admitted -= need;
+                srv->held--;
                 while (!gs.waiting.empty() && !gs.waiting.front()->in_flight) {
                     sp_request r = gs.waiting.front();
                     gs.waiting.pop_front();
                     finish_request(srv, r, st);
                 }
+                srv->work_cv.notify_all();
                 continue;
             }
             ws->bytes = need;
@@ -210,6 +215,8 @@ static void worker_main(sp_server_s *srv) {
         }
         if (srcs.empty()) {  // another worker took these sources while we allocated
             gs.idle.push_back(ws);
+            srv->held--;
+            srv->work_cv.notify_all();
             continue;
         }
         // Requests whose every source is now assigned leave the waiting list.
@@ -232,6 +239,7 @@ static void worker_main(sp_server_s *srv) {
 
         lk.lock();
         srv->stats.in_flight--;
+        srv->held--;
         if (ws->bytes != batch_ws_bytes(g, ws->qcap, ws->width)) {  // the queue grew
             const size_t now = batch_ws_bytes(g, ws->qcap, ws->width);
             srv->admitted = srv->admitted - ws->bytes + now;

@@ -71,17 +71,17 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     c->level = 0;
     c->lo = 0;
     c->hi = 1;
-    c->tail = 1;
+    c->tail_.v = 1;
     c->done = 0;
     c->mode = MODE_TOPDOWN;
-    c->overflow = 0;
+    c->overflow_.v = 0;
     c->front_deg = (unsigned long long)deg;
-    c->next_deg = 0;
+    c->next_deg_.v = 0;
     c->unset_deg = (unsigned long long)(nnz - deg);
     c->reached_pairs = 1;
-    c->sigma_max_bits = (unsigned long long)__double_as_longlong(1.0);
-    c->flagged_slots = 0;
-    c->settled_deg = 0;
+    c->sigma_max_bits_.v = (unsigned long long)__double_as_longlong(1.0);
+    c->flagged_slots_.v = 0;
+    c->settled_deg_.v = 0;
     c->alpha = alpha;
     c->beta = beta;
     c->n_vertices = n;
@@ -90,7 +90,7 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     const bool hub = deg > kHubDeg;
     const int32_t nch = hub ? (deg + kHubChunk - 1) / kHubChunk : 0;
     if (hub) hub_list[0] = HubEntry{src, 0, 0, nch};
-    c->hub_pack = 0;
+    c->hub_pack_.v = 0;
     c->hub_lo = 0;
     c->hub_hi = hub ? 1 : 0;
     c->hub_nchunks = nch;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(BS) void k_src_topdown(LevelCtl *c, const int32_t *
                     w = ci[s_beg[a] + (k - s_off[a])];
                     if (dist[w] < 0) claim = atomicCAS(&dist[w], -1, nl) == -1;
                 }
-                q.stage(claim, w, &c->tail, queue, n, &c->overflow);
+                q.stage(claim, w, &c->tail_.v, queue, n, &c->overflow_.v);
             }
             __syncthreads();
         }
@@ -172,11 +172,11 @@ __global__ __launch_bounds__(BS) void k_src_topdown(LevelCtl *c, const int32_t *
                     w = ci[e];
                     if (dist[w] < 0) claim = atomicCAS(&dist[w], -1, nl) == -1;
                 }
-                q.stage(claim, w, &c->tail, queue, n, &c->overflow);
+                q.stage(claim, w, &c->tail_.v, queue, n, &c->overflow_.v);
             }
         }
     }
-    q.finish(&c->tail, queue, n, &c->overflow);
+    q.finish(&c->tail_.v, queue, n, &c->overflow_.v);
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
@@ -206,13 +206,13 @@ __global__ __launch_bounds__(BS) void k_src_bottomup(LevelCtl *c, const int32_t 
             ++my_items;
         }
         const bool found = wave_chunk_any(beg, deg, ws, [&](int32_t e, int32_t) {
+            ++my_edges;
             return dist[ci[e]] == lvl;
         });
-        my_edges += deg;
         if (found) dist[v] = lvl + 1;
-        q.stage(found, v, &c->tail, queue, n, &c->overflow);
+        q.stage(found, v, &c->tail_.v, queue, n, &c->overflow_.v);
     }
-    q.finish(&c->tail, queue, n, &c->overflow);
+    q.finish(&c->tail_.v, queue, n, &c->overflow_.v);
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
     __shared__ unsigned long long s_red[1];
     const int wbase = threadIdx.x & ~(kWave - 1);
     const WaveScratch ws{s_coff + wbase, s_beg + wbase, s_deg + wbase, s_acc + wbase, nullptr};
-    const int32_t lvl = c->level, hi = c->hi, tail = min(c->tail, c->n_vertices);
+    const int32_t lvl = c->level, hi = c->hi, tail = min(c->tail_.v, c->n_vertices);
     const int lane = lane_id();
     unsigned long long my_deg = 0, my_items = 0, my_pairs = 0;
     double my_max = 0.0;
@@ -265,9 +265,9 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
         }
     }
     my_max = wave_max_f64(my_max);
-    if (lane == 0) atomic_max_nonneg_f64(&c->sigma_max_bits, my_max);
-    if (__ballot(large) && lane == 0) atomicOr(&c->flagged_slots, 1ull);
-    block_add_u64<BS>(my_deg, s_red, &c->next_deg);
+    if (lane == 0) atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
+    if (__ballot(large) && lane == 0) atomicOr(&c->flagged_slots_.v, 1ull);
+    block_add_u64<BS>(my_deg, s_red, &c->next_deg_.v);
     flush_counters<BS>(prof, my_items, my_deg, my_pairs, s_red);
 }
 
@@ -275,27 +275,27 @@ __global__ void k_src_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
                               int32_t *hub_lvl_chunks) {
     if (c->done) return;
     if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
-    const int32_t nf = c->tail - c->hi;
+    const int32_t nf = c->tail_.v - c->hi;
     if (nf <= 0) {
         c->done = 1;
         return;
     }
     const int32_t nl = c->level + 1;
-    level_off[nl + 1] = c->tail;
-    const unsigned long long hp = c->hub_pack;
+    level_off[nl + 1] = c->tail_.v;
+    const unsigned long long hp = c->hub_pack_.v;
     c->hub_lo = c->hub_next;
     c->hub_hi = c->hub_next + (int32_t)(hp >> 40);
     c->hub_nchunks = (int32_t)(hp & ((1ull << 40) - 1));
     c->hub_next = c->hub_hi;
-    c->hub_pack = 0;
+    c->hub_pack_.v = 0;
     hub_off[nl + 1] = c->hub_hi;
     hub_lvl_chunks[nl] = c->hub_nchunks;
-    c->front_deg = c->next_deg;
-    c->unset_deg -= c->next_deg;
-    c->next_deg = 0;
+    c->front_deg = c->next_deg_.v;
+    c->unset_deg -= c->next_deg_.v;
+    c->next_deg_.v = 0;
     c->reached_pairs += (unsigned long long)nf;
     c->lo = c->hi;
-    c->hi = c->tail;
+    c->hi = c->tail_.v;
     c->level = nl;
     if (c->mode == MODE_TOPDOWN) {
         if ((double)c->front_deg * c->alpha > (double)c->unset_deg) c->mode = MODE_BOTTOMUP;
@@ -357,8 +357,8 @@ __global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t
                   },
                   [&](double s) {
                       sigma[h.v] = s;
-                      atomic_max_nonneg_f64(&c->sigma_max_bits, s);
-                      if (sigma_is_large(s)) atomicOr(&c->flagged_slots, 1ull);
+                      atomic_max_nonneg_f64(&c->sigma_max_bits_.v, s);
+                      if (sigma_is_large(s)) atomicOr(&c->flagged_slots_.v, 1ull);
                   });
     }
     (void)prof;
@@ -565,8 +565,8 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
     if (res) {
         res->levels = levels;
         res->reached = c.hi;
-        std::memcpy(&res->sigma_max, &c.sigma_max_bits, sizeof(double));
-        res->flagged = c.flagged_slots != 0;
+        std::memcpy(&res->sigma_max, &c.sigma_max_bits_.v, sizeof(double));
+        res->flagged = c.flagged_slots_.v != 0;
         res->td = c.topdown_levels;
         res->bu = c.bottomup_levels;
     }
