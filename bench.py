@@ -40,20 +40,40 @@ WORKLOADS = {"uniform-4096": 1, "rmat-20": 2, "rmat-22": 3, "road-4096": 4}
 # entries (batched).
 BYTE_MODEL = {
     "ms_sigma": dict(items=72, edges=20, pairs=8, item_slots=8),
+    "ms_sigma_hub": dict(edges=20, pairs=8),
     "ms_delta": dict(items=40, edges=20, pairs=8, item_slots=24),
+    "ms_delta_hub": dict(edges=20, pairs=8),
     "ms_topdown": dict(items=20, edges=20),
     "ms_bottomup": dict(items=16, edges=20),
     "ms_bc": dict(items=24, item_slots=8),
     "src_topdown": dict(items=12, edges=8),
     "src_bottomup": dict(items=12, edges=8),
     "src_sigma": dict(items=20, edges=8, pairs=8),
+    "src_sigma_hub": dict(edges=8, pairs=8),
     "src_delta": dict(items=44, edges=8, pairs=16),
 }
+FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub")
 
 
 def algorithmic_bytes(name, prof):
     model = BYTE_MODEL.get(name, {})
     return sum(coef * prof.get(unit, 0) for unit, coef in model.items())
+
+
+def load_traffic(workload):
+    """Per-family HBM bytes per launch from the committed rocprofv3 counter
+    summary of this workload, or None when there is none or the kernel
+    sources changed since it was taken."""
+    from paper_2305_03317_amd import rocprof_summary
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("source_digest") != rocprof_summary.source_digest():
+        return None
+    doc["path"] = os.path.relpath(path, ROOT)
+    return doc
 
 
 def main():
@@ -116,38 +136,77 @@ def main():
         sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
     torch.cuda.synchronize()
 
-    sp.sp_profile_enable(True)
-    sp.sp_profile_read()  # discard warmup counts
-    times, dev_ms, statuses = [], [], []
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, st = sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        dev_ms.append(sp.sp_get_last_stats()["device_ms"])
-        statuses.append(st)
-        print("step %d: %.1f ms" % (len(times), times[-1] * 1e3), file=sys.stderr, flush=True)
-    prof = sp.sp_profile_read()
-    sp.sp_profile_enable(False)
+    def run_steps(tag):
+        times, dev_ms, statuses = [], [], []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            dev_ms.append(sp.sp_get_last_stats()["device_ms"])
+            statuses.append(st)
+            print("%s step %d: %.1f ms" % (tag, len(times), times[-1] * 1e3), file=sys.stderr, flush=True)
+        return times, dev_ms, statuses
+
+    # Timed region: the production configuration (forward level chunks
+    # replayed from captured hipGraphs, no per-kernel events).
+    times, dev_ms, statuses = run_steps("timed")
     stats = sp.sp_get_last_stats()
     step_s = float(np.mean(times))
     value = len(src) * m / step_s
 
-    # dominant kernel: most time inside the timed region
+    # Kernel-timed region: the same steps again with a HIP event pair around
+    # every launch (on the library's stream) and device work counters; the
+    # forward chunks are launched directly here, since events cannot be read
+    # per kernel inside a replayed graph.
+    sp.sp_profile_enable(True)
+    sp.sp_profile_read()  # discard anything earlier
+    ptimes, _, pstat = run_steps("kernel-timed")
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    statuses += pstat
+
+    traffic_doc = load_traffic(spec["name"])
+    # dominant kernel: most time inside the kernel-timed region
     dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"]) if prof else None
     roofline = None
     if dom:
         name, p = dom
+        launches = max(p["launches"], 1)
         achieved = algorithmic_bytes(name, p) / (p["total_ms"] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "launches": p["launches"],
-                    "avg_launch_ms": round(p["total_ms"] / max(p["launches"], 1), 4),
-                    "algorithmic_bytes_per_launch": int(algorithmic_bytes(name, p) / max(p["launches"], 1))}
-    kernels = {kname: {"launches": p["launches"], "total_ms": round(p["total_ms"], 3),
-                       "GBps_algorithmic": round(algorithmic_bytes(kname, p) / max(p["total_ms"], 1e-9) / 1e6, 1)}
-               for kname, p in prof.items()}
+        tr = traffic_doc["families"].get(name) if traffic_doc else None
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": round(tr["traffic_bytes_per_launch"]) if tr else None,
+                    "kernel": name, "launches": p["launches"],
+                    "avg_launch_ms": round(p["total_ms"] / launches, 4),
+                    "algorithmic_bytes_per_launch": int(algorithmic_bytes(name, p) / launches),
+                    "traffic_source": traffic_doc["path"] if tr else None}
+        if tr:
+            roofline["traffic_GBps"] = round(tr["traffic_bytes_per_launch"] / (p["total_ms"] / launches * 1e-3) / 1e9, 1)
+    kernels = {}
+    for kname, p in prof.items():
+        launches = max(p["launches"], 1)
+        e = {"launches": p["launches"], "ms_per_step": round(p["total_ms"] / args.steps, 3),
+             "avg_launch_ms": round(p["total_ms"] / launches, 4),
+             "GBps_algorithmic": round(algorithmic_bytes(kname, p) / max(p["total_ms"], 1e-9) / 1e6, 1)}
+        tr = traffic_doc["families"].get(kname) if traffic_doc else None
+        if tr:
+            e["GBps_hbm_counters"] = round(tr["traffic_bytes_per_launch"] * p["launches"] / max(p["total_ms"], 1e-9) / 1e6, 1)
+        kernels[kname] = e
+    fwd = [prof[k] for k in FORWARD if k in prof]
+    forward = None
+    if fwd:
+        f_ms = sum(p["total_ms"] for p in fwd)
+        f_alg = sum(algorithmic_bytes(k, prof[k]) for k in FORWARD if k in prof)
+        forward = {"ms_per_step": round(f_ms / args.steps, 2),
+                   "GBps_algorithmic": round(f_alg / (f_ms * 1e-3) / 1e9, 1)}
+        if traffic_doc and all(k in traffic_doc["families"] for k in FORWARD if k in prof):
+            hw = sum(traffic_doc["families"][k]["traffic_bytes_per_launch"] * prof[k]["launches"]
+                     for k in FORWARD if k in prof)
+            forward["GBps_hbm_counters"] = round(hw / (f_ms * 1e-3) / 1e9, 1)
+            forward["frac_of_peak_hbm_counters"] = round(hw / (f_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     # per-source GPU path on a sample of the same sources
     per_source = None
@@ -201,12 +260,15 @@ def main():
                    "levels_max": stats["max_levels"], "topdown_levels": stats["topdown_levels"],
                    "bottomup_levels": stats["bottomup_levels"]},
         "device_ms_per_step": float(np.mean(dev_ms)),
+        "ms_per_step_kernel_timed": float(np.mean(ptimes)) * 1e3,
+        "graph_launches_per_step": stats["graph_launches"],
         "status": max(statuses),
         "upload_ms": upload_ms,
         "graph_build_s": gen_s,
         "per_source_path": per_source,
         "batched_over_per_source": (value / per_source["teps"]) if per_source else None,
         "roofline": roofline,
+        "forward_pass": forward,
         "kernels": kernels,
         "cpu_baseline": cpu,
         "parity": parity,

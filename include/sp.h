@@ -123,11 +123,14 @@ sp_status sp_graph_info(sp_graph g, int32_t *n_vertices, int64_t *nnz, size_t *d
  * (autotuned value cached per graph, else the built-in default). */
 typedef struct sp_batch_config {
     int32_t batch_width;  /* sources per multi-source pass, 1..64 */
-    int32_t block_size;   /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    int32_t block_size;   /* threads per workgroup: 128, 256 or 512 */
     double alpha;         /* bottom-up when frontier edges * alpha > unsettled edges */
     double beta;          /* back to top-down when frontier vertices * beta < V */
-    int32_t chunk_levels; /* levels enqueued (or captured in one hipGraph) between
-                             host checks of the device "done" flag; < 0 disables capture */
+    int32_t chunk_levels; /* k > 0: the batched path captures k levels (rounded up
+                             to even) in one hipGraph and replays it, checking the
+                             device "done" flag on the host after each replay;
+                             k < 0: |k| levels per check, launched directly (no
+                             capture).  |k| <= 65536. */
     int32_t reserved[3];  /* must be zero */
 } sp_batch_config;
 

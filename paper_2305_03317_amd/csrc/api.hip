@@ -284,6 +284,10 @@ static sp_status check_batch_cfg(const sp_batch_config *cfg) {
         set_error("alpha/beta must be finite and >= 0");
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (cfg->chunk_levels < -65536 || cfg->chunk_levels > 65536) {
+        set_error("chunk_levels %d outside -65536..65536", cfg->chunk_levels);
+        return SP_ERR_INVALID_ARGUMENT;
+    }
     for (int r : cfg->reserved)
         if (r) {
             set_error("reserved fields must be zero");

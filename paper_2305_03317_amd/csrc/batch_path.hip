@@ -449,7 +449,7 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
     if (threadIdx.x == 0) s_or[0] = 0;
     __syncthreads();
     unsigned long long my_deg = 0, my_settled = 0, my_flag = 0, my_pairs = 0, my_items = 0,
-                       my_dag = 0, my_or = 0;
+                       my_dag = 0, my_or = 0, my_scan = 0;
     double my_max = 0.0;
     for (int32_t b = hi + (int32_t)(blockIdx.x * BS); b < tail; b += gridDim.x * BS) {
         const int32_t i = b + (int32_t)threadIdx.x;
@@ -506,6 +506,7 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
             my_flag |= __ballot(mine && sigma_is_large(acc));
         }
         if (hub) hub_register(c, hub_list, hub_cap, w, i, deg);
+        if (sparse || dense) my_scan += (unsigned long long)deg;  // hubs: k_ms_sigma_hub
         if (valid) {
             qmask[i] = m;
             qvb[i] = vb;
@@ -546,7 +547,7 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
         __syncthreads();
         block_add_u64<BS>(my_items, s_red, prof + 0);
         __syncthreads();
-        block_add_u64<BS>(my_deg, s_red, prof + 1);
+        block_add_u64<BS>(my_scan, s_red, prof + 1);
         __syncthreads();
         block_add_u64<BS>(my_dag, s_red, prof + 2);
         __syncthreads();
@@ -923,6 +924,10 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
 }
 
 void batch_ws_destroy(BatchWorkspace &ws) {
+    if (ws.fwd_exec) (void)hipGraphExecDestroy(ws.fwd_exec);
+    if (ws.cap_stream) (void)hipStreamDestroy(ws.cap_stream);
+    ws.fwd_exec = nullptr;
+    ws.cap_stream = nullptr;
     dev_free(ws.seen);
     dev_free(ws.nxt);
     dev_free(ws.front[0]);
@@ -962,13 +967,99 @@ static sp_status grow_queue(sp_graph g, BatchWorkspace &ws, int64_t qcap) {
     return SP_OK;
 }
 
+// The kernels of `count` forward levels starting at level `first`.  Every
+// kernel reads the level it works on from the control block, so the same
+// launches serve any chunk whose first level has the same parity.
+template <int BS>
+static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int count, int grid,
+                           int hub_grid, bool may_pull, unsigned long long active, hipStream_t s) {
+    const bool hubs = g->n_hubs > 0;
+    for (int k = 0; k < count; ++k) {
+        const int64_t l = first + k;  // level this group expands
+        uint4 *fcur = ws.front[l & 1], *fnxt = ws.front[(l + 1) & 1];
+        {
+            ProfScope ps(P_MS_TOPDOWN, s);
+            hipLaunchKernelGGL(k_ms_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
+                               g->row_ptr, g->col_idx, ws.queue, ws.qmask, ws.seen, ws.nxt,
+                               (const HubEntry *)ws.hub_list, (long long)ws.qcap,
+                               prof_counters(P_MS_TOPDOWN));
+        }
+        if (may_pull) {
+            ProfScope ps(P_MS_BOTTOMUP, s);
+            hipLaunchKernelGGL(k_ms_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
+                               g->col_idx, ws.seen, ws.nxt, fcur, ws.queue, active,
+                               (long long)ws.qcap, prof_counters(P_MS_BOTTOMUP));
+        }
+        {
+            ProfScope ps(P_MS_SIGMA, s);
+            hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
+                               g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
+                               ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
+                               active, (long long)ws.qcap, (int32_t)may_pull,
+                               prof_counters(P_MS_SIGMA));
+        }
+        hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off, ws.hub_off,
+                           ws.hub_lvl_chunks, (long long)ws.qcap, (long long)ws.hub_cap);
+        if (hubs) {
+            ProfScope ps(P_MS_SIGMA_HUB, s);
+            hipLaunchKernelGGL(k_ms_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s, ws.ctl,
+                               g->row_ptr, g->col_idx, (const unsigned long long *)ws.qmask,
+                               (const uint32_t *)ws.qvb, (const uint4 *)fcur, ws.val,
+                               (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
+                               prof_counters(P_MS_SIGMA_HUB));
+        }
+    }
+}
+
+// One chunk of forward levels.  With kernel profiling off the chunk runs as a
+// HIP graph: captured on the workspace's own stream the first time (and again
+// when a buffer, the grid or the slot set changes), then only replayed, so the
+// host submits one graph per chunk instead of four or five launches per level.
+// `first` must have the parity of level 0 (the chunk length is even).
+template <int BS>
+static sp_status run_level_chunk(sp_graph g, BatchWorkspace &ws, int64_t first, int chunk, int grid,
+                                 int hub_grid, bool may_pull, unsigned long long active,
+                                 bool capture, hipStream_t s, int32_t *graph_launches) {
+    if (!capture || prof_enabled()) {  // per-kernel events need direct launches
+        enqueue_levels<BS>(g, ws, first, chunk, grid, hub_grid, may_pull, active, s);
+        SP_HIP(hipGetLastError());
+        return SP_OK;
+    }
+    const std::array<long long, 10> key{BS, grid, hub_grid, chunk, (long long)active, may_pull,
+                                        (long long)(intptr_t)ws.queue, ws.qcap,
+                                        (long long)(intptr_t)ws.val, ws.vcap};
+    if (!ws.fwd_exec || ws.fwd_key != key) {
+        if (ws.fwd_exec) (void)hipGraphExecDestroy(ws.fwd_exec);
+        ws.fwd_exec = nullptr;
+        if (!ws.cap_stream) SP_HIP(hipStreamCreateWithFlags(&ws.cap_stream, hipStreamNonBlocking));
+        SP_HIP(hipStreamBeginCapture(ws.cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_levels<BS>(g, ws, 0, chunk, grid, hub_grid, may_pull, active, ws.cap_stream);
+        const hipError_t el = hipGetLastError();
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ws.cap_stream, &graph);
+        hipError_t ei = hipSuccess;
+        if (el == hipSuccess && ec == hipSuccess)
+            ei = hipGraphInstantiate(&ws.fwd_exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (el != hipSuccess || ec != hipSuccess || ei != hipSuccess) {
+            ws.fwd_exec = nullptr;
+            set_error("capturing the level chunk failed: %s",
+                      hipGetErrorString(el != hipSuccess ? el : ec != hipSuccess ? ec : ei));
+            return SP_ERR_DEVICE;
+        }
+        ws.fwd_key = key;
+    }
+    SP_HIP(hipGraphLaunch(ws.fwd_exec, s));
+    ++*graph_launches;
+    return SP_OK;
+}
+
 template <int BS>
 static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsigned long long active,
-                               const BatchRunOpts &o, hipStream_t s) {
+                               const BatchRunOpts &o, hipStream_t s, int32_t *graph_launches) {
     const int32_t n = g->n;
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
-    const bool hubs = g->n_hubs > 0;
     const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
     const int hub_grid = grid_for((int64_t)g->hub_chunks * kWave, BS, maxb);
     hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.seen, ws.nxt,
@@ -979,46 +1070,13 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
                        ws.hub_lvl_chunks, n, (long long)g->nnz, active,
                        may_pull ? o.alpha : 0.0, o.beta);  // alpha 0: never switch to bottom-up
     SP_HIP(hipGetLastError());
+    const bool capture = o.chunk_levels > 0;
+    const int req = std::abs(o.chunk_levels);
+    const int chunk = capture ? std::max(2, req + (req & 1)) : std::max(1, req);  // captured: even
     int64_t enqueued = 0;
     for (;;) {
-        const int chunk = std::max(1, o.chunk_levels);
-        for (int k = 0; k < chunk; ++k) {
-            const int64_t l = enqueued + k;  // level this group expands
-            uint4 *fcur = ws.front[l & 1], *fnxt = ws.front[(l + 1) & 1];
-            {
-                ProfScope ps(P_MS_TOPDOWN, s);
-                hipLaunchKernelGGL(k_ms_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
-                                   g->row_ptr, g->col_idx, ws.queue, ws.qmask, ws.seen, ws.nxt,
-                                   (const HubEntry *)ws.hub_list, (long long)ws.qcap,
-                                   prof_counters(P_MS_TOPDOWN));
-            }
-            if (may_pull) {
-                ProfScope ps(P_MS_BOTTOMUP, s);
-                hipLaunchKernelGGL(k_ms_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                                   g->col_idx, ws.seen, ws.nxt, fcur, ws.queue, active,
-                                   (long long)ws.qcap, prof_counters(P_MS_BOTTOMUP));
-            }
-            {
-                ProfScope ps(P_MS_SIGMA, s);
-                hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                                   g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
-                                   ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
-                                   active, (long long)ws.qcap, (int32_t)may_pull,
-                                   prof_counters(P_MS_SIGMA));
-            }
-            hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
-                               ws.hub_off, ws.hub_lvl_chunks, (long long)ws.qcap,
-                               (long long)ws.hub_cap);
-            if (hubs) {
-                ProfScope ps(P_MS_SIGMA, s);
-                hipLaunchKernelGGL(k_ms_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s, ws.ctl,
-                                   g->row_ptr, g->col_idx, (const unsigned long long *)ws.qmask,
-                                   (const uint32_t *)ws.qvb, (const uint4 *)fcur, ws.val,
-                                   (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
-                                   prof_counters(P_MS_SIGMA));
-            }
-        }
-        SP_HIP(hipGetLastError());
+        SP_TRY(run_level_chunk<BS>(g, ws, enqueued, chunk, grid, hub_grid, may_pull, active, capture,
+                                   s, graph_launches));
         enqueued += chunk;
         SP_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(LevelCtl), hipMemcpyDeviceToHost, s));
         SP_HIP(hipStreamSynchronize(s));
@@ -1066,11 +1124,12 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         }
         h_m[j] |= 1ull << i;
     }
+    int32_t graph_launches = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
         SP_HIP(hipMemcpyAsync(ws.queue, h_q, n0 * 4, hipMemcpyHostToDevice, s));
         SP_HIP(hipMemcpyAsync(ws.qmask, h_m, n0 * 8, hipMemcpyHostToDevice, s));
         SP_HIP(hipMemcpyAsync(ws.slot_src, h_src, kSlots * 4, hipMemcpyHostToDevice, s));
-        SP_TRY(batch_forward<BS>(g, ws, n0, active, o, s));
+        SP_TRY(batch_forward<BS>(g, ws, n0, active, o, s, &graph_launches));
         if (!ws.ctl_host->overflow_.v) break;
         if (attempt == 1) {
             set_error("multi-source queue overflow at capacity %lld", (long long)ws.qcap);
@@ -1102,13 +1161,13 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
                                ws.dlt, prof_counters(P_MS_DELTA));
         }
         if (!deepest && hch[l] > 0) {
-            ProfScope ps(P_MS_DELTA, s);
+            ProfScope ps(P_MS_DELTA_HUB, s);
             hipLaunchKernelGGL(k_ms_delta_hub<BS>, dim3(grid_for((int64_t)hch[l] * kWave, BS, maxb)),
                                dim3(BS), 0, s, (const int32_t *)ws.hub_off,
                                (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
                                (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
                                (const uint4 *)frd, ws.val, ws.dlt, (const HubEntry *)ws.hub_list,
-                               ws.hub_cnt, ws.partial, prof_counters(P_MS_DELTA));
+                               ws.hub_cnt, ws.partial, prof_counters(P_MS_DELTA_HUB));
         }
     }
     SP_HIP(hipGetLastError());
@@ -1133,6 +1192,7 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         res->td = c.topdown_levels;
         res->bu = c.bottomup_levels;
         res->entries = off[levels];
+        res->graph_launches = graph_launches;
     }
     return SP_OK;
 }

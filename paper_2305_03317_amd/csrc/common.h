@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -145,8 +146,9 @@ struct LevelCtl {
 // Measurement: kernel families timed with HIP events when profiling is on,
 // each with device counters of the work it did.
 enum ProfKind : int {
-    P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_DELTA,
-    P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_DELTA, P_MS_BC, P_COUNT
+    P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
+    P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_DELTA, P_MS_DELTA_HUB, P_MS_BC,
+    P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
 extern const char *const kProfNames[P_COUNT];
@@ -243,6 +245,11 @@ struct BatchWorkspace {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t bytes = 0;
     int32_t width = 0;                   // slots the value store is sized for
+    // A chunk of forward levels captured once as a HIP graph (on a private
+    // stream) and replayed on the caller's stream while its key still holds.
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t fwd_exec = nullptr;
+    std::array<long long, 10> fwd_key{};
 };
 size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width);
 sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws);

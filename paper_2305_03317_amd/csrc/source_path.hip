@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
     const WaveScratch ws{s_coff + wbase, s_beg + wbase, s_deg + wbase, s_acc + wbase, nullptr};
     const int32_t lvl = c->level, hi = c->hi, tail = min(c->tail_.v, c->n_vertices);
     const int lane = lane_id();
-    unsigned long long my_deg = 0, my_items = 0, my_pairs = 0;
+    unsigned long long my_deg = 0, my_items = 0, my_pairs = 0, my_scan = 0;
     double my_max = 0.0;
     bool large = false;
     for (int32_t b = hi + (int32_t)(blockIdx.x * BS + threadIdx.x) - lane; b < tail;
@@ -258,6 +258,7 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
             if (hub) {
                 hub_register(c, hub_list, hub_cap, w, i, deg);
             } else {
+                my_scan += (unsigned long long)deg;
                 sigma[w] = s;
                 my_max = fmax(my_max, s);
                 large |= sigma_is_large(s);
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
     if (lane == 0) atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
     if (__ballot(large) && lane == 0) atomicOr(&c->flagged_slots_.v, 1ull);
     block_add_u64<BS>(my_deg, s_red, &c->next_deg_.v);
-    flush_counters<BS>(prof, my_items, my_deg, my_pairs, s_red);
+    flush_counters<BS>(prof, my_items, my_scan, my_pairs, s_red);
 }
 
 __global__ void k_src_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
@@ -499,7 +500,7 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
     SP_HIP(hipGetLastError());
     int32_t enqueued = 0;
     for (;;) {
-        const int chunk = std::max(1, o.chunk_levels);
+        const int chunk = std::max(1, std::abs(o.chunk_levels));
         for (int k = 0; k < chunk; ++k) {
             {
                 ProfScope ps(P_SRC_TOPDOWN, s);
@@ -520,11 +521,13 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
             }
             hipLaunchKernelGGL(k_src_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks);
-            if (hubs)
+            if (hubs) {
+                ProfScope ps(P_SRC_SIGMA_HUB, s);
                 hipLaunchKernelGGL(k_src_sigma_hub<BS>, dim3(grid_for((int64_t)g->hub_chunks * kWave, BS, maxb)),
                                    dim3(BS), 0, s, ws.ctl, g->row_ptr, g->col_idx, ws.dist, ws.sigma,
                                    (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
-                                   prof_counters(P_SRC_SIGMA));
+                                   prof_counters(P_SRC_SIGMA_HUB));
+            }
         }
         SP_HIP(hipGetLastError());
         enqueued += chunk;
@@ -553,12 +556,14 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                                    ws.level_off, l, g->row_ptr, g->col_idx, ws.queue, ws.dist,
                                    ws.sigma, ws.delta, bc, prof_counters(P_SRC_DELTA));
             }
-            if (hubs && hchunks[l] > 0)
+            if (hubs && hchunks[l] > 0) {
+                ProfScope ps(P_SRC_DELTA_HUB, s);
                 hipLaunchKernelGGL(k_src_delta_hub<BS>, dim3(grid_for((int64_t)hchunks[l] * kWave, BS, maxb)),
                                    dim3(BS), 0, s, (const int32_t *)ws.hub_off,
                                    (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
                                    ws.dist, ws.sigma, ws.delta, bc, (const HubEntry *)ws.hub_list,
                                    ws.hub_cnt, ws.partial);
+            }
         }
         SP_HIP(hipGetLastError());
     }

@@ -233,6 +233,11 @@ def test_invalid_source_leaves_output_untouched(sp):
     assert ei.value.status == sp.SP_ERR_INVALID_ARGUMENT
     with pytest.raises(sp.SpError):
         sp.sp_bc_batch(g, [-1], out_bc=out)
+    for bad in ({"batch_width": 65}, {"block_size": 64}, {"alpha": -1.0},
+                {"chunk_levels": 70000}, {"chunk_levels": -70000}):
+        with pytest.raises(sp.SpError) as ei:
+            sp.sp_bc_batch(g, [0, 1], out_bc=out, config=bad)
+        assert ei.value.status == sp.SP_ERR_INVALID_ARGUMENT, bad
     assert torch.all(out == 7.0)
     g.release()
 
@@ -275,3 +280,33 @@ def test_star_and_meshes_never_switch_direction(sp):
         assert_bc(a, ref, "sp_bc")
         assert_bc(b, ref, "sp_bc_batch")
         g.release()
+
+
+@pytest.mark.parametrize("case", ["rmat", "road"])
+def test_hipgraph_capture_matches_direct_launches(sp, case):
+    """The forward level chunk replayed from a captured hipGraph gives the same
+    bits as direct launches, on every replay, with other device work between
+    calls; an odd chunk length and a narrower batch (new slot set, so a new
+    capture) still match the oracle."""
+    if case == "rmat":
+        rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 21)
+        srcs = graphs.sources(rp, 100, 22, min_degree=1)
+    else:
+        rp, ci = graphs.road(96, 0.02, 23)  # hundreds of levels: many replays per pass
+        srcs = graphs.sources(rp, 70, 24)
+    g = sp.sp_graph_upload(rp, ci)
+    ref = oracle.bc(rp, ci, srcs)
+    direct, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": -8})
+    assert st == sp.SP_OK and sp.sp_get_last_stats()["graph_launches"] == 0
+    direct = direct.cpu().numpy()
+    assert_bc(direct, ref, "%s direct launches" % case)
+    for rep in range(3):
+        got, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": 8})
+        assert st == sp.SP_OK
+        assert sp.sp_get_last_stats()["graph_launches"] > 0
+        assert np.array_equal(got.cpu().numpy(), direct), "%s replay %d differs" % (case, rep)
+        sp.sp_bc(g, srcs[:2])  # eager work on the same stream between calls
+    got, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": 3, "batch_width": 7})
+    assert st == sp.SP_OK
+    assert_bc(got.cpu().numpy(), ref, "%s odd chunk, width 7" % case)
+    g.release()
