@@ -8,12 +8,20 @@ check), with the graph already resident in HBM.  The graph is built and
 uploaded once before timing; upload time is reported separately.
 
 Default workload: RMAT scale 22 (4,194,304 vertices, edge factor 16,
-a/b/c = 0.57/0.19/0.19, deduplicated, relabelled), 1,024 seeded sources among
-vertices of degree >= 1, batches of 64.  TEPS = sources x undirected edges /
-step time.  Also reported: the per-source GPU path on a sample of the same
-sources (the "batched vs per-source" ratio), the dominant kernel's achieved
-algorithmic bandwidth against the HBM peak, and the CPU oracle on a bounded
-sample of the same sources (which doubles as a parity check of this run).
+a/b/c = 0.57/0.19/0.19, deduplicated, vertex ids permuted), 1,024 seeded
+sources among vertices of degree >= 1, batches of 64.  TEPS = sources x
+undirected edges / step time.
+
+Regions: (1) the timed steps, in the production configuration (forward level
+chunks replayed from captured hipGraphs) -> value, ms_per_step; (2) the same
+steps with a HIP event pair around every kernel launch and device work
+counters -> kernels, roofline (dominant kernel: algorithmic bytes per launch /
+average launch time against 8 TB/s; traffic from the committed rocprofv3
+counter summary while the kernel sources are unchanged), forward_pass.
+Also: the per-source GPU path on a sample of the same sources (the batched
+vs per-source ratio), the CPU oracle on a bounded sample (cpu_baseline, which
+doubles as a parity check of this run), and the serving workload (eight
+resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS).
 
 Prints one JSON line.
 """
@@ -76,6 +84,72 @@ def load_traffic(workload):
     return doc
 
 
+def serving_benchmark(sp, torch, n_requests, seed=2005):
+    """Serving workload: eight resident graphs, seeded requests (graph uniform,
+    1..512 sources log-uniform), continuous batching by the library's server.
+    Phase "burst" submits every request at once (saturation throughput);
+    phases at 50% and 80% of that rate submit them with seeded exponential
+    gaps (Poisson arrivals).  Latency is the library's submit-to-completion
+    time of each request."""
+    import numpy as np
+    from paper_2305_03317_amd import graphs
+    t0 = time.perf_counter()
+    gs = graphs.serving_graphs()
+    reqs = graphs.serving_requests([rp for _, rp, _ in gs], n_requests, seed)
+    build_s = time.perf_counter() - t0
+    handles = [sp.sp_graph_upload(rp, ci) for _, rp, ci in gs]
+    edges = [len(ci) // 2 for _, _, ci in gs]
+    srv = sp.Server()
+    ids = [srv.add_graph(h) for h in handles]
+    outs = [torch.empty(max(h.n, 1), dtype=torch.float64, device="cuda") for h in handles]
+    for gid, h in zip(ids, handles):  # warm: workspaces and captured graphs exist before timing
+        r = srv.submit(gid, graphs.sources(gs[gid][1], 64, 7, min_degree=1), out_bc=outs[gid])
+        assert r.wait() == sp.SP_OK
+        r.release()
+    work = sum(len(src) * edges[gi] for gi, src in reqs)
+
+    def phase(rate):
+        rng = np.random.default_rng(seed + 1)
+        gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
+        live = []
+        start = time.perf_counter()
+        t_next = start
+        for (gi, src), gap in zip(reqs, gaps):
+            t_next += gap
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            out = torch.empty(max(handles[gi].n, 1), dtype=torch.float64, device="cuda")
+            live.append(srv.submit(ids[gi], src, out_bc=out))
+        bad = 0
+        for r in live:
+            bad += r.wait() != sp.SP_OK
+        wall = time.perf_counter() - start
+        lat = np.array([r.latency_us() for r in live]) / 1e3
+        for r in live:
+            r.release()
+        print("serving phase rate=%s: %.1f s" % (rate, wall), file=sys.stderr, flush=True)
+        return {"offered_qps": round(rate, 3) if rate else None, "achieved_qps": round(len(reqs) / wall, 3),
+                "teps": work / wall, "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "max_ms": round(float(lat.max()), 2),
+                "wall_s": round(wall, 2), "failed": int(bad)}
+
+    burst = phase(0)
+    sat = burst["achieved_qps"]
+    res = {"graphs": [n for n, _, _ in gs], "requests": len(reqs),
+           "mean_sources": round(float(np.mean([len(s) for _, s in reqs])), 1),
+           "graph_build_s": round(build_s, 1), "burst": burst,
+           "load50": phase(0.5 * sat), "load80": phase(0.8 * sat)}
+    st = srv.stats()
+    res["passes"] = st["passes"]
+    res["mean_slots_per_pass"] = round(st["slots_used"] / max(st["passes"], 1), 1)
+    res["peak_admitted_GB"] = round(st["peak_admitted_bytes"] / 1e9, 2)
+    srv.destroy()
+    for h in handles:
+        h.release()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +162,8 @@ def main():
                     help="sources timed through the per-source path (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="sources timed through the CPU oracle (0 = skip)")
+    ap.add_argument("--serving-requests", type=int, default=80,
+                    help="requests per phase of the serving workload (0 = skip)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="run one device-to-device copy of this many GiB first (a known-size "
                          "kernel that calibrates hardware byte counters in a profiler run)")
@@ -241,6 +317,12 @@ def main():
         parity = {"sources": len(cs), "max_rel_err": rel, "zero_exact": bool(np.all(got[~nz] == 0)),
                   "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}
 
+    g.release()
+    del out
+    serving = None
+    if args.serving_requests > 0:
+        serving = serving_benchmark(sp, torch, args.serving_requests)
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -272,8 +354,8 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
         "parity": parity,
+        "serving": serving,
     }
-    g.release()
     print(json.dumps(line))
 
 

@@ -116,6 +116,31 @@ SERVING_GRAPHS = [("rmat", 16), ("rmat", 18), ("rmat", 20), ("rmat", 22),
                   ("road", 512), ("road", 1024), ("road", 2048), ("road", 4096)]
 
 
+def serving_requests(graph_sizes, count: int, seed: int = 2005):
+    """Seeded request list of the serving workload: (graph index, sources).
+
+    The graph is chosen uniformly; the source count is log-uniform on
+    [1, 512]; sources are distinct vertices of degree >= 1 of that graph.
+    graph_sizes: list of (row_ptr) arrays, one per resident graph.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        gi = int(rng.integers(0, len(graph_sizes)))
+        k = int(min(512, max(1, np.floor(np.exp(rng.uniform(0.0, np.log(513.0)))))))
+        out.append((gi, sources(graph_sizes[gi], k, int(rng.integers(0, 2**31 - 1)), min_degree=1)))
+    return out
+
+
+def serving_graphs(seed: int = 1005):
+    """The eight resident graphs of the serving workload: [(name, row_ptr, col_idx)]."""
+    res = []
+    for i, (kind, size) in enumerate(SERVING_GRAPHS):
+        rp, ci = make_graph(kind, size, seed + 100 * i)
+        res.append(("%s-%d" % (kind, size), rp, ci))
+    return res
+
+
 def make_graph(kind: str, size: int, seed: int):
     if kind == "rmat":
         return rmat(size, 16, RMAT_ABC, seed)
