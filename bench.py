@@ -193,6 +193,19 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    # Device copy bandwidth on this machine (a 2 GiB device-to-device copy, best of
+    # 3): the streaming reference that the kernels' rates are also quoted against.
+    cbuf = torch.empty(1 << 29, dtype=torch.int32, device="cuda").fill_(1)
+    cdst = torch.empty_like(cbuf)
+    copy_gbps = 0.0
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cdst.copy_(cbuf)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbps = max(copy_gbps, 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del cbuf, cdst
     k = WORKLOADS[args.workload]
 
     t0 = time.perf_counter()
@@ -259,6 +272,7 @@ def main():
                     "avg_launch_ms": round(p["total_ms"] / launches, 4),
                     "algorithmic_bytes_per_launch": int(algorithmic_bytes(name, p) / launches),
                     "traffic_source": traffic_doc["path"] if tr else None}
+        roofline["frac_of_measured_copy"] = round(achieved / copy_gbps, 4)
         if tr:
             roofline["traffic_GBps"] = round(tr["traffic_bytes_per_launch"] / (p["total_ms"] / launches * 1e-3) / 1e9, 1)
     kernels = {}
@@ -346,6 +360,7 @@ def main():
         "graph_launches_per_step": stats["graph_launches"],
         "status": max(statuses),
         "upload_ms": upload_ms,
+        "hbm_copy_GBps_measured": round(copy_gbps, 1),
         "graph_build_s": gen_s,
         "per_source_path": per_source,
         "batched_over_per_source": (value / per_source["teps"]) if per_source else None,
