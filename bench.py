@@ -313,6 +313,7 @@ def main():
 
     # CPU oracle on a bounded sample (also a parity check at full size)
     cpu = None
+    cpu_par = None
     parity = None
     if args.cpu_sample > 0:
         import oracle
@@ -324,6 +325,20 @@ def main():
         cpu = {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
                "sample": "first %d of the %d sources, single-threaded C oracle, %.1f s"
                          % (len(cs), len(src), cpu_s)}
+        # The same oracle function on P host threads over disjoint chunks of a
+        # larger sample (ctypes releases the GIL during each call); per-thread
+        # BC summed in chunk order.
+        import concurrent.futures as cf
+        P = max(1, min(16, os.cpu_count() or 1))
+        ps_src = src[:P * args.cpu_sample]
+        chunks = [ps_src[i::P] for i in range(P)]
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(P) as ex:
+            parts = list(ex.map(lambda c: oracle.bc(rp, ci, c), chunks))
+        par_s = time.perf_counter() - t0
+        cpu_par = {"value": len(ps_src) * m / par_s, "unit": "TEPS", "cores": P, "kind": "oracle",
+                   "sample": "first %d sources, %d threads x %d sources, %.1f s"
+                             % (len(ps_src), P, args.cpu_sample, par_s)}
         got, _ = sp.sp_bc_batch(g, cs, config=cfg)
         got = got.cpu().numpy()
         nz = ref != 0
@@ -368,6 +383,7 @@ def main():
         "forward_pass": forward,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "cpu_baseline_parallel": cpu_par,
         "parity": parity,
         "serving": serving,
     }

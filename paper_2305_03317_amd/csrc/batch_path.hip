@@ -75,57 +75,134 @@ __device__ __forceinline__ int rank_in(unsigned long long m, int s) {
 
 // lane = slot: sum over adjacency entries [beg, end) of the value of slot
 // `lane` of each neighbour's level-`tag` entry, for neighbours whose entry
-// holds the lane and m holds it too.  The sum runs in CSR order; up to 8
-// neighbour values are loaded at once.  Forward: parents' sigma.  Reverse:
-// children's rho.
+// holds the lane and m holds it too.  The sum runs in CSR order, one window
+// of kWave entries at a time; within a window up to 8 neighbour values are
+// loaded at once.  Forward: parents' sigma.  Reverse: children's rho.
+//
+// Latency: a window needs three dependent loads (column ids, front records,
+// values).  The loop keeps them in flight together: while the values of
+// window k are loaded, the front records of window k+1 and the column ids of
+// window k+2 are already on their way (issued first, so waiting for the
+// values does not wait for more than they need).
+
+// One window: add the values of the matching neighbours whose front records
+// are `fu` (lane i holds the record of the window's i-th entry).
+__device__ __forceinline__ void window_acc(uint4 fu, unsigned long long m, uint32_t tag,
+                                           const double *__restrict__ val, double &acc,
+                                           unsigned long long &pairs) {
+    const int lane = lane_id();
+    unsigned long long mu = 0;
+    uint32_t vb = 0;
+    if (fu.z == tag) {
+        mu = mask_of(fu);
+        vb = fu.w;
+    }
+    unsigned long long nz = __ballot((mu & m) != 0ull);
+    while (nz) {
+        unsigned long long mj[8];
+        uint32_t vj[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (nz) {
+                const int j = __ffsll((long long)nz) - 1;
+                nz &= nz - 1;
+                mj[t] = rl_u64(mu, j);
+                vj[t] = (uint32_t)rl_i32((int32_t)vb, j);
+            } else {
+                mj[t] = 0;
+                vj[t] = 0;
+            }
+        }
+        double x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bool on = ((mj[t] & m) >> lane) & 1ull;
+            x[t] = on ? val[(int64_t)vj[t] + rank_in(mj[t], lane)] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (((mj[t] & m) >> lane) & 1ull) acc += x[t];
+            pairs += (unsigned long long)__popcll(mj[t] & m);
+        }
+    }
+}
+
+__device__ __forceinline__ uint4 no_front() { return make_uint4(0u, 0u, kNoTag, 0u); }
+
+// dense_sum given the records `f` of the first window (entries [beg, beg+kWave)).
+__device__ __forceinline__ double dense_sum_from(uint4 f, int32_t beg, int32_t end,
+                                                 unsigned long long m, uint32_t tag,
+                                                 const int32_t *__restrict__ ci,
+                                                 const uint4 *__restrict__ front,
+                                                 const double *__restrict__ val,
+                                                 unsigned long long &pairs) {
+    const int lane = lane_id();
+    double acc = 0.0;
+    int32_t un = beg + kWave + lane < end ? ci[beg + kWave + lane] : -1;
+    for (int32_t e0 = beg; e0 < end; e0 += kWave) {
+        const uint4 fn = un >= 0 ? front[un] : no_front();  // window k+1
+        const int32_t e2 = e0 + 2 * kWave + lane;
+        un = e2 < end ? ci[e2] : -1;                         // window k+2
+        window_acc(f, m, tag, val, acc, pairs);
+        f = fn;
+    }
+    return acc;
+}
+
 __device__ __forceinline__ double dense_sum(int32_t beg, int32_t end, unsigned long long m,
                                             uint32_t tag, const int32_t *__restrict__ ci,
                                             const uint4 *__restrict__ front,
                                             const double *__restrict__ val,
                                             unsigned long long &pairs) {
     const int lane = lane_id();
-    double acc = 0.0;
-    for (int32_t e0 = beg; e0 < end; e0 += kWave) {
-        const int32_t e = e0 + lane;
-        unsigned long long mu = 0;
-        uint32_t vb = 0;
-        if (e < end) {
-            const uint4 fu = front[ci[e]];
-            if (fu.z == tag) {
-                mu = mask_of(fu);
-                vb = fu.w;
-            }
+    const int32_t u = beg + lane < end ? ci[beg + lane] : -1;
+    return dense_sum_from(u >= 0 ? front[u] : no_front(), beg, end, m, tag, ci, front, val, pairs);
+}
+
+// dense_sum for every lane j set in dm, one after another in lane order
+// (lane j's vertex: entries [beg_j, end_j), slots m_j), calling
+// fin(j, sum, pairs) for each.  The next vertex's first window is fetched
+// while the current one is summed, and the column ids of the one after it.
+template <class Fin>
+__device__ __forceinline__ void dense_each(unsigned long long dm, int32_t beg, int32_t end,
+                                           unsigned long long m, uint32_t tag,
+                                           const int32_t *__restrict__ ci,
+                                           const uint4 *__restrict__ front,
+                                           const double *__restrict__ val, Fin fin) {
+    const int lane = lane_id();
+    auto take = [&](int32_t &j, int32_t &b, int32_t &e, int32_t &u) {
+        if (!dm) {
+            j = -1;
+            u = -1;
+            return;
         }
-        unsigned long long nz = __ballot((mu & m) != 0ull);
-        while (nz) {
-            unsigned long long mj[8];
-            uint32_t vj[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (nz) {
-                    const int j = __ffsll((long long)nz) - 1;
-                    nz &= nz - 1;
-                    mj[t] = rl_u64(mu, j);
-                    vj[t] = (uint32_t)rl_i32((int32_t)vb, j);
-                } else {
-                    mj[t] = 0;
-                    vj[t] = 0;
-                }
-            }
-            double x[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const bool on = ((mj[t] & m) >> lane) & 1ull;
-                x[t] = on ? val[(int64_t)vj[t] + rank_in(mj[t], lane)] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (((mj[t] & m) >> lane) & 1ull) acc += x[t];
-                pairs += (unsigned long long)__popcll(mj[t] & m);
-            }
-        }
+        j = __ffsll((long long)dm) - 1;
+        dm &= dm - 1;
+        b = rl_i32(beg, j);
+        e = rl_i32(end, j);
+        u = b + lane < e ? ci[b + lane] : -1;
+    };
+    int32_t jl, bl = 0, el = 0, ul;
+    int32_t jn, bn = 0, en = 0, un;
+    take(jl, bl, el, ul);
+    take(jn, bn, en, un);
+    uint4 fl = ul >= 0 ? front[ul] : no_front();
+    while (jl >= 0) {
+        const uint4 fn = un >= 0 ? front[un] : no_front();
+        int32_t jm, bm = 0, em = 0, um;
+        take(jm, bm, em, um);
+        unsigned long long pr = 0;
+        const double acc = dense_sum_from(fl, bl, el, rl_u64(m, jl), tag, ci, front, val, pr);
+        fin(jl, acc, pr);
+        jl = jn;
+        bl = bn;
+        el = en;
+        fl = fn;
+        jn = jm;
+        bn = bm;
+        en = em;
+        un = um;
     }
-    return acc;
 }
 
 // One lane, one slot s: the same sum as dense_sum for slot s alone.  Four
@@ -236,6 +313,7 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->flagged_slots_.v = 0;
         c->live = active;  // every slot's level-0 frontier holds its source
         c->nlive_.v = 0;
+        c->blocks_done_.v = 0;
         c->alpha = alpha;
         c->beta = beta;
         c->n_vertices = n;
@@ -423,13 +501,97 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
+// Coherent read of a counter other blocks updated with device-scope atomics
+// (relaxed: no cache invalidation is needed for the counters themselves).
+template <class T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// End of a forward level (one thread): close the new frontier, turn the hub
+// registrations into the next level's hub segment, decide the next
+// direction, or set `done`.
+__device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
+                              int32_t *hub_lvl_chunks, long long qcap, long long hub_cap) {
+    if (c->done) return;
+    if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
+    const int32_t tail = ld_agent(&c->tail_.v);
+    const unsigned long long hp = ld_agent(&c->hub_pack_.v);
+    if ((long long)tail > qcap || ld_agent(&c->overflow_.v) ||
+        (long long)c->hub_next + (long long)(hp >> 40) > hub_cap) {
+        c->overflow_.v = 1;
+        c->done = 1;
+        return;
+    }
+    const int32_t nf = tail - c->hi;
+    if (nf <= 0) {
+        c->done = 1;
+        return;
+    }
+    const int32_t nl = c->level + 1;
+    level_off[nl + 1] = tail;
+    c->hub_lo = c->hub_next;
+    c->hub_hi = c->hub_next + (int32_t)(hp >> 40);
+    c->hub_nchunks = (int32_t)(hp & ((1ull << 40) - 1));
+    c->hub_next = c->hub_hi;
+    c->hub_pack_.v = 0;
+    hub_off[nl + 1] = c->hub_hi;
+    hub_lvl_chunks[nl] = c->hub_nchunks;
+    c->front_deg = ld_agent(&c->next_deg_.v);
+    c->unset_deg -= ld_agent(&c->settled_deg_.v);
+    c->next_deg_.v = 0;
+    c->settled_deg_.v = 0;
+    c->reached_pairs = ld_agent(&c->vtail_.v);  // every reached (slot, vertex) pair owns one value
+    c->live = ld_agent(&c->nlive_.v);
+    c->nlive_.v = 0;
+    c->lo = c->hi;
+    c->hi = tail;
+    c->level = nl;
+    if (c->mode == MODE_TOPDOWN) {
+        if ((double)c->front_deg * c->alpha > (double)c->unset_deg) c->mode = MODE_BOTTOMUP;
+    } else {
+        if ((double)nf * c->beta < (double)c->n_vertices) c->mode = MODE_TOPDOWN;
+    }
+}
+
+// True in exactly one block: the last of the first `nb` blocks (those that
+// had work; blockIdx.x < nb) to get here, or block 0 when nb is 0.  Every
+// thread of a block calls it after the block's last atomic update of the
+// control block; blocks without work return false at once, so only working
+// blocks touch the counter, which is left at zero for the next kernel.  The
+// chosen block reads only counters updated with device-scope atomics, so no
+// cache write-back is needed: each wave waits until its own atomics are
+// acknowledged (a barrier alone does not wait for them), then one thread
+// counts the block.
+__device__ __forceinline__ bool last_block(LevelCtl *c, int nb) {
+    __shared__ int s_last;
+    if (nb <= 0) return blockIdx.x == 0;
+    if ((int)blockIdx.x >= nb) return false;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int prev = atomicAdd(&c->blocks_done_.v, 1);
+        s_last = prev == nb - 1;
+        if (s_last) atomicExch(&c->blocks_done_.v, 0);
+    }
+    __syncthreads();
+    return s_last != 0;
+}
+
+// Blocks of a grid-stride loop over `items` in steps of `per_block` that get
+// at least one item.
+__device__ __forceinline__ int working_blocks(int64_t items, int per_block) {
+    if (items <= 0) return 0;
+    return (int)min((int64_t)gridDim.x, (items + per_block - 1) / per_block);
+}
+
 // Path counts of the new entries [hi, tail).  Wave takes 64 entries, gives
 // each its value range, then: sparse entries are reduced by their own lane,
 // dense ones by the whole wave in turn, hubs are registered for
 // k_ms_sigma_hub.  Every entry's bookkeeping (qmask, value base, nxt reset,
 // seen, front of the new level) is done here.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
                                                  const int32_t *__restrict__ queue,
                                                  unsigned long long *qmask, uint32_t *qvb,
@@ -438,7 +600,9 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
                                                  uint4 *front_nxt, double *val, long long vcap,
                                                  HubEntry *hub_list, long long hub_cap,
                                                  unsigned long long active, long long qcap,
-                                                 int32_t track_deg, unsigned long long *prof) {
+                                                 int32_t track_deg, int32_t *level_off,
+                                                 int32_t *hub_off, int32_t *hub_lvl_chunks,
+                                                 unsigned long long *prof) {
     if (c->done) return;
     __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
     __shared__ int32_t s_scan[BS / kWave + 1];
@@ -488,23 +652,18 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
                 if (sigma_is_large(acc)) my_flag |= 1ull << s;
             }
         }
-        unsigned long long dm = __ballot(dense);
-        while (dm) {
-            const int jl = __ffsll((long long)dm) - 1;
-            dm &= dm - 1;
-            const int32_t bj = rl_i32(beg, jl), ej = rl_i32(end, jl);
-            const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
-            const unsigned long long mj = rl_u64(m, jl);
-            unsigned long long pr = 0;
-            const double acc = dense_sum(bj, ej, mj, lvl, ci, front_cur, val, pr);
-            if (lane == 0) my_dag += pr;
-            const bool mine = (mj >> lane) & 1ull;
-            if (mine) {
-                val[vbj + rank_in(mj, lane)] = acc;
-                my_max = fmax(my_max, acc);
-            }
-            my_flag |= __ballot(mine && sigma_is_large(acc));
-        }
+        dense_each(__ballot(dense), beg, end, m, lvl, ci, front_cur, val,
+                   [&](int jl, double acc, unsigned long long pr) {
+                       const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
+                       const unsigned long long mj = rl_u64(m, jl);
+                       if (lane == 0) my_dag += pr;
+                       const bool mine = (mj >> lane) & 1ull;
+                       if (mine) {
+                           val[vbj + rank_in(mj, lane)] = acc;
+                           my_max = fmax(my_max, acc);
+                       }
+                       my_flag |= __ballot(mine && sigma_is_large(acc));
+                   });
         if (hub) hub_register(c, hub_list, hub_cap, w, i, deg);
         if (sparse || dense) my_scan += (unsigned long long)deg;  // hubs: k_ms_sigma_hub
         if (valid) {
@@ -553,49 +712,11 @@ __global__ __launch_bounds__(BS) void k_ms_sigma(LevelCtl *c, const int32_t *__r
         __syncthreads();
         block_add_u64<BS>(my_pairs, s_red, prof + 3);
     }
+    // the last block to finish closes the level
+    if (last_block(c, working_blocks((int64_t)tail - hi, BS)) && threadIdx.x == 0)
+        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap);
 }
 
-__global__ void k_ms_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
-                             int32_t *hub_lvl_chunks, long long qcap, long long hub_cap) {
-    if (c->done) return;
-    if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
-    const unsigned long long hp = c->hub_pack_.v;
-    if ((long long)c->tail_.v > qcap || c->overflow_.v ||
-        (long long)c->hub_next + (long long)(hp >> 40) > hub_cap) {
-        c->overflow_.v = 1;
-        c->done = 1;
-        return;
-    }
-    const int32_t nf = c->tail_.v - c->hi;
-    if (nf <= 0) {
-        c->done = 1;
-        return;
-    }
-    const int32_t nl = c->level + 1;
-    level_off[nl + 1] = c->tail_.v;
-    c->hub_lo = c->hub_next;
-    c->hub_hi = c->hub_next + (int32_t)(hp >> 40);
-    c->hub_nchunks = (int32_t)(hp & ((1ull << 40) - 1));
-    c->hub_next = c->hub_hi;
-    c->hub_pack_.v = 0;
-    hub_off[nl + 1] = c->hub_hi;
-    hub_lvl_chunks[nl] = c->hub_nchunks;
-    c->front_deg = c->next_deg_.v;
-    c->unset_deg -= c->settled_deg_.v;
-    c->next_deg_.v = 0;
-    c->settled_deg_.v = 0;
-    c->reached_pairs = c->vtail_.v;  // every reached (slot, vertex) pair owns one value
-    c->live = c->nlive_.v;
-    c->nlive_.v = 0;
-    c->lo = c->hi;
-    c->hi = c->tail_.v;
-    c->level = nl;
-    if (c->mode == MODE_TOPDOWN) {
-        if ((double)c->front_deg * c->alpha > (double)c->unset_deg) c->mode = MODE_BOTTOMUP;
-    } else {
-        if ((double)nf * c->beta < (double)c->n_vertices) c->mode = MODE_TOPDOWN;
-    }
-}
 
 // One chunk of a hub, lane = slot: partial row of 64 doubles.  The last chunk
 // of the hub to finish sums the rows in chunk order and hands the result to
@@ -685,16 +806,21 @@ __device__ __forceinline__ void finish_slot(double acc, double *vp, double *drow
 // base} in front(l); dense and sparse entries are finished here, hubs in
 // k_ms_delta_hub.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ level_off, int32_t lvl,
-                                                 int32_t deepest, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(BS, 6) void k_ms_delta(LevelCtl *c, int32_t step,
+                                                 const int32_t *__restrict__ level_off,
+                                                 const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ ci,
                                                  const int32_t *__restrict__ queue,
                                                  const unsigned long long *__restrict__ qmask,
-                                                 const uint32_t *__restrict__ qvb,
-                                                 const uint4 *__restrict__ front_rd,
-                                                 uint4 *front_wr, double *val, double *dlt,
+                                                 const uint32_t *__restrict__ qvb, uint4 *f0,
+                                                 uint4 *f1, double *val, double *dlt,
                                                  unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
+    const int32_t lvl = c->bwd_level;  // the reverse sweep's level; 0 = finished
+    if (lvl < 1) return;
+    const bool deepest = lvl == c->bwd_last;
+    const uint4 *__restrict__ front_rd = ((lvl + 1) & 1) ? f1 : f0;  // children's records
+    uint4 *front_wr = (lvl & 1) ? f1 : f0;
     const int32_t lo = level_off[lvl], hi = level_off[lvl + 1];
     const uint32_t nl = (uint32_t)lvl + 1;
     const int lane = lane_id();
@@ -739,22 +865,19 @@ __global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ lev
                 finish_slot(acc, val + vb + rank_in(m, s), dlt + (int64_t)v * kSlots + s);
             }
         }
-        unsigned long long dm = __ballot(dense);
-        while (dm) {
-            const int jl = __ffsll((long long)dm) - 1;
-            dm &= dm - 1;
-            const int32_t vj = rl_i32(v, jl), bj = rl_i32(beg, jl), ej = rl_i32(end, jl);
-            const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
-            const unsigned long long mj = rl_u64(m, jl);
-            unsigned long long pr = 0;
-            const double acc = dense_sum(bj, ej, mj, nl, ci, front_rd, val, pr);
-            if (lane == 0) {
-                my_pairs += pr;
-                my_edges += (unsigned long long)(ej - bj);
-            }
-            if ((mj >> lane) & 1ull)
-                finish_slot(acc, val + vbj + rank_in(mj, lane), dlt + (int64_t)vj * kSlots + lane);
-        }
+        dense_each(__ballot(dense), beg, end, m, nl, ci, front_rd, val,
+                   [&](int jl, double acc, unsigned long long pr) {
+                       const int32_t vj = rl_i32(v, jl);
+                       const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
+                       const unsigned long long mj = rl_u64(m, jl);
+                       if (lane == 0) {
+                           my_pairs += pr;
+                           my_edges += (unsigned long long)(rl_i32(end, jl) - rl_i32(beg, jl));
+                       }
+                       if ((mj >> lane) & 1ull)
+                           finish_slot(acc, val + vbj + rank_in(mj, lane),
+                                       dlt + (int64_t)vj * kSlots + lane);
+                   });
     }
     if (prof) {
         block_add_u64<BS>(my_items, s_red, prof + 0);
@@ -765,17 +888,24 @@ __global__ __launch_bounds__(BS) void k_ms_delta(const int32_t *__restrict__ lev
         __syncthreads();
         block_add_u64<BS>(my_slots, s_red, prof + 3);
     }
+    // when no hub kernel follows, the last block moves the sweep one level up
+    if (step && last_block(c, working_blocks((int64_t)hi - lo, BS)) && threadIdx.x == 0)
+        c->bwd_level = lvl - 1;
 }
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_delta_hub(
-    const int32_t *__restrict__ hub_off, const int32_t *__restrict__ hub_lvl_chunks, int32_t lvl,
-    const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const unsigned long long *__restrict__ qmask, const uint32_t *__restrict__ qvb,
-    const uint4 *__restrict__ front_rd, double *val, double *dlt, const HubEntry *hub_list,
-    unsigned int *hub_cnt, double *partial, unsigned long long *prof) {
+    LevelCtl *c, int32_t step, const int32_t *__restrict__ hub_off,
+    const int32_t *__restrict__ hub_lvl_chunks, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ ci, const unsigned long long *__restrict__ qmask,
+    const uint32_t *__restrict__ qvb, const uint4 *f0, const uint4 *f1, double *val, double *dlt,
+    const HubEntry *hub_list, unsigned int *hub_cnt, double *partial, unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
-    const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1], nch = hub_lvl_chunks[lvl];
+    const int32_t lvl = c->bwd_level;
+    if (lvl < 1) return;
+    const uint4 *__restrict__ front_rd = ((lvl + 1) & 1) ? f1 : f0;
+    const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1];
+    const int32_t nch = lvl == c->bwd_last ? 0 : hub_lvl_chunks[lvl];  // deepest: no children
     const uint32_t nl = (uint32_t)lvl + 1;
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
@@ -803,6 +933,8 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
         __syncthreads();
         block_add_u64<BS>(my_pairs, s_red, prof + 2);
     }
+    if (step && last_block(c, working_blocks((int64_t)nch * kWave, BS)) && threadIdx.x == 0)
+        c->bwd_level = lvl - 1;
 }
 
 // BC[v] += delta[v][s] for slots in ascending order; consecutive slots with
@@ -847,6 +979,14 @@ __global__ __launch_bounds__(BS) void k_ms_bc(int32_t n, const unsigned long lon
 // Per-slot results of one level into source-major arrays (for checks):
 // distance and sigma after the forward pass (values still hold sigma),
 // delta after the reverse pass.
+// Reverse-pass control: start at the deepest level; the last kernel of each
+// reverse level moves it one level up.
+__global__ void k_ms_bwd_init(LevelCtl *c) {
+    c->bwd_level = c->level;
+    c->bwd_last = c->level;
+    c->blocks_done_.v = 0;
+}
+
 __global__ void k_ms_extract(const int32_t *__restrict__ queue,
                              const unsigned long long *__restrict__ qmask,
                              const uint32_t *__restrict__ qvb, int32_t lo, int32_t hi, int32_t lvl,
@@ -924,9 +1064,11 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
 }
 
 void batch_ws_destroy(BatchWorkspace &ws) {
-    if (ws.fwd_exec) (void)hipGraphExecDestroy(ws.fwd_exec);
+    for (CapturedChunk *c : {&ws.fwd_short, &ws.fwd_long, &ws.bwd}) {
+        if (c->exec) (void)hipGraphExecDestroy(c->exec);
+        c->exec = nullptr;
+    }
     if (ws.cap_stream) (void)hipStreamDestroy(ws.cap_stream);
-    ws.fwd_exec = nullptr;
     ws.cap_stream = nullptr;
     dev_free(ws.seen);
     dev_free(ws.nxt);
@@ -995,11 +1137,9 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
             hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
                                ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
-                               active, (long long)ws.qcap, (int32_t)may_pull,
-                               prof_counters(P_MS_SIGMA));
+                               active, (long long)ws.qcap, (int32_t)may_pull, ws.level_off,
+                               ws.hub_off, ws.hub_lvl_chunks, prof_counters(P_MS_SIGMA));
         }
-        hipLaunchKernelGGL(k_ms_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off, ws.hub_off,
-                           ws.hub_lvl_chunks, (long long)ws.qcap, (long long)ws.hub_cap);
         if (hubs) {
             ProfScope ps(P_MS_SIGMA_HUB, s);
             hipLaunchKernelGGL(k_ms_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s, ws.ctl,
@@ -1011,49 +1151,44 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
     }
 }
 
-// One chunk of forward levels.  With kernel profiling off the chunk runs as a
-// HIP graph: captured on the workspace's own stream the first time (and again
-// when a buffer, the grid or the slot set changes), then only replayed, so the
-// host submits one graph per chunk instead of four or five launches per level.
-// `first` must have the parity of level 0 (the chunk length is even).
-template <int BS>
-static sp_status run_level_chunk(sp_graph g, BatchWorkspace &ws, int64_t first, int chunk, int grid,
-                                 int hub_grid, bool may_pull, unsigned long long active,
-                                 bool capture, hipStream_t s, int32_t *graph_launches) {
-    if (!capture || prof_enabled()) {  // per-kernel events need direct launches
-        enqueue_levels<BS>(g, ws, first, chunk, grid, hub_grid, may_pull, active, s);
-        SP_HIP(hipGetLastError());
-        return SP_OK;
-    }
-    const std::array<long long, 10> key{BS, grid, hub_grid, chunk, (long long)active, may_pull,
-                                        (long long)(intptr_t)ws.queue, ws.qcap,
-                                        (long long)(intptr_t)ws.val, ws.vcap};
-    if (!ws.fwd_exec || ws.fwd_key != key) {
-        if (ws.fwd_exec) (void)hipGraphExecDestroy(ws.fwd_exec);
-        ws.fwd_exec = nullptr;
+// Replay `slot`'s captured graph on stream s, capturing it first (on the
+// workspace's own stream, with enqueue(stream)) when absent or when its key
+// differs from `key`.
+template <class Enqueue>
+static sp_status replay_chunk(BatchWorkspace &ws, CapturedChunk &slot,
+                              const std::array<long long, 12> &key, Enqueue enqueue,
+                              hipStream_t s) {
+    if (!slot.exec || slot.key != key) {
+        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+        slot.exec = nullptr;
         if (!ws.cap_stream) SP_HIP(hipStreamCreateWithFlags(&ws.cap_stream, hipStreamNonBlocking));
         SP_HIP(hipStreamBeginCapture(ws.cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue_levels<BS>(g, ws, 0, chunk, grid, hub_grid, may_pull, active, ws.cap_stream);
+        enqueue(ws.cap_stream);
         const hipError_t el = hipGetLastError();
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(ws.cap_stream, &graph);
         hipError_t ei = hipSuccess;
         if (el == hipSuccess && ec == hipSuccess)
-            ei = hipGraphInstantiate(&ws.fwd_exec, graph, nullptr, nullptr, 0);
+            ei = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
         if (el != hipSuccess || ec != hipSuccess || ei != hipSuccess) {
-            ws.fwd_exec = nullptr;
-            set_error("capturing the level chunk failed: %s",
+            slot.exec = nullptr;
+            set_error("capturing a level chunk failed: %s",
                       hipGetErrorString(el != hipSuccess ? el : ec != hipSuccess ? ec : ei));
             return SP_ERR_DEVICE;
         }
-        ws.fwd_key = key;
+        slot.key = key;
     }
-    SP_HIP(hipGraphLaunch(ws.fwd_exec, s));
-    ++*graph_launches;
+    SP_HIP(hipGraphLaunch(slot.exec, s));
     return SP_OK;
 }
 
+// Forward levels.  With capture on (chunk_levels > 0) and kernel profiling
+// off, chunks of levels run as replayed HIP graphs so the host submits one
+// graph per chunk instead of four or five launches per level; after four
+// chunks without reaching the end (a deep BFS, as on road graphs) the chunks
+// grow fourfold.  Chunk lengths are even and every chunk starts at an even
+// level, so the captured front-buffer parity holds for all of them.
 template <int BS>
 static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsigned long long active,
                                const BatchRunOpts &o, hipStream_t s, int32_t *graph_launches) {
@@ -1070,13 +1205,28 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
                        ws.hub_lvl_chunks, n, (long long)g->nnz, active,
                        may_pull ? o.alpha : 0.0, o.beta);  // alpha 0: never switch to bottom-up
     SP_HIP(hipGetLastError());
-    const bool capture = o.chunk_levels > 0;
+    const bool capture = o.chunk_levels > 0 && !prof_enabled();  // events need direct launches
     const int req = std::abs(o.chunk_levels);
-    const int chunk = capture ? std::max(2, req + (req & 1)) : std::max(1, req);  // captured: even
+    const int short_chunk = o.chunk_levels > 0 ? std::max(2, req + (req & 1)) : std::max(1, req);
     int64_t enqueued = 0;
-    for (;;) {
-        SP_TRY(run_level_chunk<BS>(g, ws, enqueued, chunk, grid, hub_grid, may_pull, active, capture,
-                                   s, graph_launches));
+    for (int rounds = 0;; ++rounds) {
+        const bool deep = rounds >= 4;
+        const int chunk = deep ? 4 * short_chunk : short_chunk;
+        if (capture) {
+            const std::array<long long, 12> key{BS, grid, hub_grid, chunk, (long long)active, may_pull,
+                                                (long long)(intptr_t)ws.queue, ws.qcap,
+                                                (long long)(intptr_t)ws.val, ws.vcap, 0, 0};
+            SP_TRY(replay_chunk(ws, deep ? ws.fwd_long : ws.fwd_short, key,
+                                [&](hipStream_t cs) {
+                                    enqueue_levels<BS>(g, ws, 0, chunk, grid, hub_grid, may_pull,
+                                                       active, cs);
+                                },
+                                s));
+            ++*graph_launches;
+        } else {
+            enqueue_levels<BS>(g, ws, enqueued, chunk, grid, hub_grid, may_pull, active, s);
+            SP_HIP(hipGetLastError());
+        }
         enqueued += chunk;
         SP_HIP(hipMemcpyAsync(ws.ctl_host, ws.ctl, sizeof(LevelCtl), hipMemcpyDeviceToHost, s));
         SP_HIP(hipStreamSynchronize(s));
@@ -1087,6 +1237,39 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
         }
     }
     return SP_OK;
+}
+
+// `count` reverse levels: each step sweeps the control block's bwd_level
+// (non-hub entries, then hub chunks; the last block of the step's last kernel
+// moves it one level up); steps past level 1 return at once.
+template <int BS>
+static void enqueue_reverse(sp_graph g, BatchWorkspace &ws, int count, int grid_d, int grid_h,
+                            bool hubs, hipStream_t s) {
+    for (int k = 0; k < count; ++k) {
+        {
+            ProfScope ps(P_MS_DELTA, s);
+            hipLaunchKernelGGL(k_ms_delta<BS>, dim3(grid_d), dim3(BS), 0, s, ws.ctl, (int32_t)!hubs,
+                               (const int32_t *)ws.level_off, g->row_ptr, g->col_idx, ws.queue,
+                               ws.qmask, (const uint32_t *)ws.qvb, ws.front[0], ws.front[1], ws.val,
+                               ws.dlt, prof_counters(P_MS_DELTA));
+        }
+        if (hubs) {
+            ProfScope ps(P_MS_DELTA_HUB, s);
+            hipLaunchKernelGGL(k_ms_delta_hub<BS>, dim3(grid_h), dim3(BS), 0, s, ws.ctl, 1,
+                               (const int32_t *)ws.hub_off,
+                               (const int32_t *)ws.hub_lvl_chunks, g->row_ptr, g->col_idx,
+                               (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
+                               (const uint4 *)ws.front[0], (const uint4 *)ws.front[1], ws.val, ws.dlt,
+                               (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
+                               prof_counters(P_MS_DELTA_HUB));
+        }
+    }
+}
+
+static int pow2_at_least(int64_t x, int cap) {
+    int p = 1;
+    while (p < x && p < cap) p <<= 1;
+    return std::min(p, cap);
 }
 
 static sp_status launch_extract(sp_graph g, BatchWorkspace &ws, const std::vector<int32_t> &off,
@@ -1148,27 +1331,36 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
     SP_HIP(hipStreamSynchronize(s));
     if (ex && (ex->dist || ex->sigma))
         SP_TRY(launch_extract(g, ws, off, ex->dist, ex->sigma, nullptr, s));
+    // Reverse pass, device-driven: grids sized for the largest level (rounded
+    // up to a power of two so that consecutive batches reuse one capture).
     const int maxb = device_cu_count() * 8;
-    for (int32_t l = levels - 1; l >= 1; --l) {
-        const int64_t cnt = off[l + 1] - off[l];
-        const bool deepest = l == levels - 1;
-        uint4 *frd = ws.front[(l + 1) & 1], *fwr = ws.front[l & 1];
-        {
-            ProfScope ps(P_MS_DELTA, s);
-            hipLaunchKernelGGL(k_ms_delta<BS>, dim3(grid_for(cnt, BS, maxb)), dim3(BS), 0, s,
-                               ws.level_off, l, (int32_t)deepest, g->row_ptr, g->col_idx, ws.queue,
-                               ws.qmask, (const uint32_t *)ws.qvb, (const uint4 *)frd, fwr, ws.val,
-                               ws.dlt, prof_counters(P_MS_DELTA));
+    int64_t maxcnt = 1;
+    int32_t maxh = 0;
+    for (int32_t l = 1; l < levels; ++l) {
+        maxcnt = std::max<int64_t>(maxcnt, off[l + 1] - off[l]);
+        if (l < levels - 1) maxh = std::max(maxh, hch[l]);
+    }
+    const int grid_d = pow2_at_least(grid_for(maxcnt, BS, maxb), maxb);
+    const int grid_h = pow2_at_least(grid_for((int64_t)std::max(maxh, 1) * kWave, BS, maxb), maxb);
+    const bool hubs = maxh > 0;
+    hipLaunchKernelGGL(k_ms_bwd_init, dim3(1), dim3(1), 0, s, ws.ctl);
+    const int32_t steps = levels - 1;  // levels L-1 .. 1
+    const bool capture = o.chunk_levels > 0 && !prof_enabled();
+    if (steps > 0 && capture) {
+        constexpr int kBwdChunk = 8;
+        const std::array<long long, 12> key{BS, grid_d, grid_h, kBwdChunk, hubs,
+                                            (long long)(intptr_t)ws.queue, ws.qcap,
+                                            (long long)(intptr_t)ws.val, ws.vcap, 0, 0, 0};
+        for (int32_t done = 0; done < steps; done += kBwdChunk) {
+            SP_TRY(replay_chunk(ws, ws.bwd, key,
+                                [&](hipStream_t cs) {
+                                    enqueue_reverse<BS>(g, ws, kBwdChunk, grid_d, grid_h, hubs, cs);
+                                },
+                                s));
+            ++graph_launches;
         }
-        if (!deepest && hch[l] > 0) {
-            ProfScope ps(P_MS_DELTA_HUB, s);
-            hipLaunchKernelGGL(k_ms_delta_hub<BS>, dim3(grid_for((int64_t)hch[l] * kWave, BS, maxb)),
-                               dim3(BS), 0, s, (const int32_t *)ws.hub_off,
-                               (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
-                               (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
-                               (const uint4 *)frd, ws.val, ws.dlt, (const HubEntry *)ws.hub_list,
-                               ws.hub_cnt, ws.partial, prof_counters(P_MS_DELTA_HUB));
-        }
+    } else if (steps > 0) {
+        enqueue_reverse<BS>(g, ws, steps, grid_d, grid_h, hubs, s);
     }
     SP_HIP(hipGetLastError());
     if (ex && ex->delta) SP_TRY(launch_extract(g, ws, off, nullptr, nullptr, ex->delta, s));

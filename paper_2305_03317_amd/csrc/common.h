@@ -125,6 +125,7 @@ struct LevelCtl {
     unsigned long long reached_pairs;  // (slot, vertex) pairs reached (per-source: vertices)
     double alpha, beta;                // direction thresholds
     unsigned long long live;           // batched: slots with a nonempty current frontier
+    int32_t bwd_level, bwd_last;       // batched reverse pass: level being swept, deepest level
     // Hubs: entries of the level being built are appended at hub_next, with
     // hub_pack = (count << 40) | chunks accumulating; `advance` turns them into
     // the current level's segment [hub_lo, hub_hi) with hub_nchunks chunks.
@@ -140,6 +141,8 @@ struct LevelCtl {
                              // value order; NaN sorts above inf)
     HotU64 flagged_slots_;   // slots with sigma > 1e300 / non-finite
     HotU64 nlive_;           // batched: slots of the next frontier (accumulating)
+    HotI32 blocks_done_;     // batched: blocks of the current kernel that finished (last one
+                             // ends the level); zero between kernels
 };
 
 
@@ -213,6 +216,11 @@ sp_status source_run(sp_graph g, SourceWorkspace &ws, int32_t src, double *bc, b
 // ---------------------------------------------------------------------------
 constexpr int kSlots = 64;  // bits per source bitmap; also the slot stride of sigma/delta rows
 
+struct CapturedChunk {
+    hipGraphExec_t exec = nullptr;
+    std::array<long long, 12> key{};
+};
+
 struct BatchWorkspace {
     int device = -1;
     int32_t n = 0;
@@ -245,11 +253,11 @@ struct BatchWorkspace {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     size_t bytes = 0;
     int32_t width = 0;                   // slots the value store is sized for
-    // A chunk of forward levels captured once as a HIP graph (on a private
-    // stream) and replayed on the caller's stream while its key still holds.
+    // Chunks of levels captured once as HIP graphs (on a private stream) and
+    // replayed on the caller's stream while their keys still hold: short and
+    // long forward chunks, and the reverse chunk.
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t fwd_exec = nullptr;
-    std::array<long long, 10> fwd_key{};
+    CapturedChunk fwd_short, fwd_long, bwd;
 };
 size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width);
 sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws);
