@@ -52,6 +52,11 @@ BYTE_MODEL = {
     "ms_delta": dict(items=40, edges=20, pairs=8, item_slots=24),
     "ms_delta_hub": dict(edges=20, pairs=8),
     "ms_topdown": dict(items=20, edges=20),
+    # fused road-like level: items = frontier entries (queue, front record,
+    # qmask/qvb writes, row offsets), edges = their adjacency (column id, seen,
+    # claim), pairs = (slot, parent) pairs summed, item_slots = entries of the
+    # new vertices' rows read while gathering parent slots (column id, front)
+    "ms_expand": dict(items=40, edges=16, pairs=8, item_slots=20),
     "ms_bottomup": dict(items=16, edges=20),
     "ms_bc": dict(items=24, item_slots=8),
     "src_topdown": dict(items=12, edges=8),
@@ -60,7 +65,7 @@ BYTE_MODEL = {
     "src_sigma_hub": dict(edges=8, pairs=8),
     "src_delta": dict(items=44, edges=8, pairs=16),
 }
-FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub")
+FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_expand")
 
 
 def algorithmic_bytes(name, prof):
@@ -157,7 +162,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat-22", choices=sorted(WORKLOADS))
     ap.add_argument("--sources", type=int, default=None, help="override the workload's source count")
-    ap.add_argument("--batch-width", type=int, default=0)
+    ap.add_argument("--batch-width", type=int, default=0,
+                    help="fixed batch width (skips the autotuner)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in defaults instead of sp_autotune's choice")
     ap.add_argument("--per-source-sample", type=int, default=32,
                     help="sources timed through the per-source path (0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
@@ -219,6 +227,16 @@ def main():
     torch.cuda.synchronize()
     upload_ms = (time.perf_counter() - t0) * 1e3
     cfg = {"batch_width": args.batch_width} if args.batch_width else None
+    tuned = None
+    if cfg is None and not args.no_autotune:
+        # sp_autotune times candidate configurations on (up to) 128 of the
+        # sources and caches its choice on the graph; sp_bc_batch with no
+        # config then uses it.  Not part of the timed region.
+        t0 = time.perf_counter()
+        tuned = sp.sp_autotune(g, src)
+        tuned = {k: tuned[k] for k in ("batch_width", "block_size", "alpha", "beta", "chunk_levels")}
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 2)
+        print("autotuned:", tuned, file=sys.stderr, flush=True)
 
     out = torch.empty(n, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
@@ -369,7 +387,9 @@ def main():
                    "nnz": len(ci), "sources": len(src), "batch_width": stats["batch_width"],
                    "graph_seed": spec["graph_seed"], "source_seed": spec["source_seed"],
                    "levels_max": stats["max_levels"], "topdown_levels": stats["topdown_levels"],
-                   "bottomup_levels": stats["bottomup_levels"]},
+                   "bottomup_levels": stats["bottomup_levels"], "block_size": stats["block_size"],
+                   "alpha": stats["alpha"], "beta": stats["beta"], "chunk_levels": stats["chunk_levels"],
+                   "autotuned": tuned},
         "device_ms_per_step": float(np.mean(dev_ms)),
         "ms_per_step_kernel_timed": float(np.mean(ptimes)) * 1e3,
         "graph_launches_per_step": stats["graph_launches"],

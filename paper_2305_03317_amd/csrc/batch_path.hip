@@ -718,6 +718,166 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
 }
 
 
+// One forward level in one kernel, for sparse graphs (maximum degree
+// kExpandDeg or less, so never bottom-up and no hubs; road-like): discovery of
+// the next frontier and its path counts.  A thread takes one frontier entry
+// and walks its row; for a neighbour x with new slots, the thread that raises
+// x's claim tag to this level first (atomicMax on `claim`, which only grows)
+// owns x's entry and puts x on the block's LDS list.  Then each thread takes
+// one owned vertex: it gathers the slots of all x's parents on the current
+// level (pulling over x's row, so the mask is complete whichever parent got
+// there first), sums each slot's parents' sigma in CSR order (sparse_sum: the
+// same order as k_ms_sigma, so the results are the same bits) and writes the
+// entry.  Other threads reaching x see either its updated `seen` or a lost
+// claim.  The frontier's own qmask/qvb are filled here from its front records
+// (an owner appends only the vertex).  The last working block closes the level.
+constexpr int kExpandDeg = 8;
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ms_expand(
+    LevelCtl *c, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t *queue,
+    unsigned long long *qmask, uint32_t *qvb, unsigned long long *seen, int32_t *claim,
+    const uint4 *__restrict__ front_cur, uint4 *front_nxt, double *val, long long vcap,
+    unsigned long long active, long long qcap, int32_t *level_off, int32_t *hub_off,
+    int32_t *hub_lvl_chunks, long long hub_cap, unsigned long long *prof) {
+    if (c->done) return;
+    __shared__ int32_t s_own[kExpandDeg * BS], s_cnt[1], s_scan[BS / kWave + 1];
+    __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
+    __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
+    StagedQueue<BS, 4 * BS> q;
+    q.init(s_qbuf, s_meta);
+    if (threadIdx.x == 0) {
+        s_or[0] = 0;
+        s_cnt[0] = 0;
+    }
+    __syncthreads();
+    const int32_t lo = c->lo, hi = c->hi;
+    const uint32_t lvl = (uint32_t)c->level;
+    const int32_t nl = (int32_t)lvl + 1;
+    const int lane = lane_id();
+    unsigned long long my_items = 0, my_edges = 0, my_pairs = 0, my_pull = 0, my_flag = 0, my_or = 0;
+    double my_max = 0.0;
+    for (int32_t b = lo + blockIdx.x * BS; b < hi; b += gridDim.x * BS) {
+        // claims: one frontier entry per thread, its row four entries at a time
+        const int32_t i = b + threadIdx.x;
+        if (i < hi) {
+            const int32_t v = queue[i];
+            const uint4 f = front_cur[v];
+            const unsigned long long fm = mask_of(f);
+            qmask[i] = fm;
+            qvb[i] = f.w;
+            const int32_t beg = rp[v], end = rp[v + 1];
+            ++my_items;
+            my_edges += (unsigned long long)(end - beg);
+            for (int32_t e0 = beg; e0 < end; e0 += 4) {
+                int32_t x[4];
+                unsigned long long sx[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) x[t] = e0 + t < end ? ci[e0 + t] : -1;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) sx[t] = x[t] >= 0 ? seen[x[t]] : ~0ull;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if ((fm & ~sx[t]) && atomicMax(&claim[x[t]], nl) < nl)
+                        s_own[atomicAdd(&s_cnt[0], 1)] = x[t];
+            }
+        }
+        __syncthreads();
+        const int32_t n_own = s_cnt[0];
+        // owned vertices: one per thread
+        for (int32_t t0 = 0; t0 < n_own; t0 += BS) {
+            const int32_t t = t0 + threadIdx.x;
+            const bool own = t < n_own;
+            int32_t x = 0;
+            unsigned long long sx = 0, mx = 0;
+            uint4 fu[kExpandDeg];  // x's row's front records, kept for the sums below
+            if (own) {
+                x = s_own[t];
+                sx = seen[x];
+                const int32_t xb = rp[x], xe = rp[x + 1];
+                int32_t u[kExpandDeg];
+#pragma unroll
+                for (int k = 0; k < kExpandDeg; ++k) u[k] = xb + k < xe ? ci[xb + k] : -1;
+#pragma unroll
+                for (int k = 0; k < kExpandDeg; ++k) {
+                    fu[k] = u[k] >= 0 ? front_cur[u[k]] : no_front();
+                    if (fu[k].z == lvl) mx |= mask_of(fu[k]);
+                }
+                mx &= active & ~sx;
+                my_pull += (unsigned long long)(xe - xb);
+            }
+            const int32_t pc = __popcll(mx);
+            int32_t btotal;
+            const int32_t excl = block_excl_scan<BS>(pc, s_scan, &btotal);
+            if (threadIdx.x == 0)
+                s_base[0] = btotal ? atomicAdd(&c->vtail_.v, (unsigned long long)btotal) : 0ull;
+            __syncthreads();
+            const unsigned long long vb64 = s_base[0] + (unsigned long long)excl;
+            const bool fits = vb64 + (unsigned long long)pc <= (unsigned long long)vcap;
+            if (own && mx && !fits) atomicOr(&c->overflow_.v, 1);
+            const bool take = own && mx != 0ull && fits;
+            if (take) {
+                const uint32_t vb = (uint32_t)vb64;
+                unsigned long long bits = mx;
+                while (bits) {  // per slot: parents' sigma in CSR order (as sparse_sum)
+                    const int sl = __ffsll((long long)bits) - 1;
+                    bits &= bits - 1;
+                    double xv[kExpandDeg];
+#pragma unroll
+                    for (int k = 0; k < kExpandDeg; ++k) {
+                        const unsigned long long mu = mask_of(fu[k]);
+                        xv[k] = (fu[k].z == lvl && ((mu >> sl) & 1ull))
+                                    ? val[(int64_t)fu[k].w + rank_in(mu, sl)] : 0.0;
+                    }
+                    double acc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < kExpandDeg; ++k) {
+                        const unsigned long long mu = mask_of(fu[k]);
+                        if (fu[k].z == lvl && ((mu >> sl) & 1ull)) {
+                            acc += xv[k];
+                            ++my_pairs;
+                        }
+                    }
+                    val[vb + rank_in(mx, sl)] = acc;
+                    my_max = fmax(my_max, acc);
+                    if (sigma_is_large(acc)) my_flag |= 1ull << sl;
+                }
+                front_nxt[x] = make_front(mx, (uint32_t)nl, vb);
+                seen[x] = sx | mx;
+                my_or |= mx;
+            }
+            q.stage(take, x, &c->tail_.v, queue, qcap, &c->overflow_.v);
+        }
+        if (threadIdx.x == 0) s_cnt[0] = 0;
+        __syncthreads();
+    }
+    q.finish(&c->tail_.v, queue, qcap, &c->overflow_.v);
+    my_max = wave_max_f64(my_max);
+    for (int o = 32; o > 0; o >>= 1) {
+        my_flag |= __shfl_xor(my_flag, o, kWave);
+        my_or |= __shfl_xor(my_or, o, kWave);
+    }
+    if (lane == 0) {
+        atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
+        if (my_flag) atomicOr(&c->flagged_slots_.v, my_flag);
+        if (my_or) atomicOr(&s_or[0], my_or);  // LDS
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_or[0]) atomicOr(&c->nlive_.v, s_or[0]);
+    if (prof) {
+        __syncthreads();
+        block_add_u64<BS>(my_items, s_red, prof + 0);
+        __syncthreads();
+        block_add_u64<BS>(my_edges, s_red, prof + 1);
+        __syncthreads();
+        block_add_u64<BS>(my_pairs, s_red, prof + 2);
+        __syncthreads();
+        block_add_u64<BS>(my_pull, s_red, prof + 3);
+    }
+    if (last_block(c, working_blocks((int64_t)hi - lo, BS)) && threadIdx.x == 0)
+        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap);
+}
+
 // One chunk of a hub, lane = slot: partial row of 64 doubles.  The last chunk
 // of the hub to finish sums the rows in chunk order and hands the result to
 // fin(lane_sum) (all lanes).
@@ -1119,6 +1279,15 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
     for (int k = 0; k < count; ++k) {
         const int64_t l = first + k;  // level this group expands
         uint4 *fcur = ws.front[l & 1], *fnxt = ws.front[(l + 1) & 1];
+        if (!hubs && !may_pull && g->max_degree <= kExpandDeg) {  // road-like: one kernel per level
+            ProfScope ps(P_MS_EXPAND, s);
+            hipLaunchKernelGGL(k_ms_expand<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
+                               g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, (int32_t *)ws.nxt,
+                               (const uint4 *)fcur, fnxt, ws.val, (long long)ws.vcap, active,
+                               (long long)ws.qcap, ws.level_off, ws.hub_off, ws.hub_lvl_chunks,
+                               (long long)ws.hub_cap, prof_counters(P_MS_EXPAND));
+            continue;
+        }
         {
             ProfScope ps(P_MS_TOPDOWN, s);
             hipLaunchKernelGGL(k_ms_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,

@@ -150,7 +150,8 @@ struct LevelCtl {
 // each with device counters of the work it did.
 enum ProfKind : int {
     P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
-    P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_DELTA, P_MS_DELTA_HUB, P_MS_BC,
+    P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_EXPAND, P_MS_DELTA, P_MS_DELTA_HUB,
+    P_MS_BC,
     P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
