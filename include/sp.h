@@ -160,11 +160,17 @@ typedef struct sp_stats {
 sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
                 sp_stream s);
 
-/* Batched path: sources are cut, in list order, into batches of
- * cfg->batch_width; each batch runs as one multi-source BFS with a 64-bit
- * source bitmap per vertex (one bit per batch slot), all slots advancing level
- * by level together.  Same inputs, outputs and status as sp_bc; cfg may be
- * NULL.  BC is accumulated per vertex in source-list order. */
+/* Batched path: sources are cut into batches of cfg->batch_width; each batch
+ * runs as one multi-source BFS with a 64-bit source bitmap per vertex (one bit
+ * per batch slot), all slots advancing level by level together.  Same inputs,
+ * outputs and status as sp_bc; cfg may be NULL.  When the sources need more
+ * than one batch they are first grouped so that a batch holds sources with
+ * similar BFS depth profiles (fewer distinct levels per vertex, so less work):
+ * ordered by their summed distance to the four highest-degree vertices
+ * (computed once per graph, on the first such call), then by descending
+ * degree, then by list position.  BC is accumulated per vertex batch by batch
+ * in that order, slot order within a batch; the order is a function of the
+ * graph and the source list alone, so results are reproducible. */
 sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
                       const sp_batch_config *cfg, sp_stream s);
 

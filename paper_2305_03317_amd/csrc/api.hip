@@ -424,8 +424,10 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     dev_free(bad);
     bad = nullptr;
     int32_t md = 0;
+    g->host_deg.resize(n_vertices);
     for (int32_t v = 0; v < n_vertices; ++v) {
         const int32_t d = deg_rp[v + 1] - deg_rp[v];
+        g->host_deg[v] = d;
         md = std::max(md, d);
         if (d > kHubDeg) {
             g->n_hubs++;
@@ -539,6 +541,59 @@ sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *o
     SP_GUARD_END
 }
 
+// Order in which sp_bc_batch cuts `sources` into batches: ascending summed
+// BFS distance to the kGroupHubs highest-degree vertices, then descending
+// degree, then list position.  Sources with similar depth profiles share a
+// batch, so each vertex is reached at fewer distinct levels per batch.  The
+// distances are computed once per graph with the per-source path.
+constexpr int kGroupHubs = 4;
+
+static sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sources, int32_t width,
+                               hipStream_t st, std::vector<int32_t> &order) {
+    order.resize(n_sources);
+    for (int32_t i = 0; i < n_sources; ++i) order[i] = i;
+    if (n_sources <= width) return SP_OK;
+    bool ready;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        ready = !g->group_key.empty();
+    }
+    if (!ready) {
+        const int32_t n = g->n;
+        std::vector<int32_t> hubs(n);
+        for (int32_t v = 0; v < n; ++v) hubs[v] = v;
+        const int32_t k = std::min(kGroupHubs, n);
+        std::partial_sort(hubs.begin(), hubs.begin() + k, hubs.end(), [&](int32_t a, int32_t b) {
+            return g->host_deg[a] != g->host_deg[b] ? g->host_deg[a] > g->host_deg[b] : a < b;
+        });
+        std::vector<int32_t> key(n, 0), dist(n);
+        SourceWorkspace *ws = nullptr;
+        SP_TRY(acquire_source_ws(g, &ws));
+        struct Rel {
+            sp_graph g;
+            SourceWorkspace *ws;
+            ~Rel() { release_source_ws(g, ws); }
+        } rel{g, ws};
+        SourceRunOpts o;
+        for (int32_t h = 0; h < k; ++h) {
+            SourceResult r;
+            SP_TRY(source_run(g, *ws, hubs[h], nullptr, false, o, st, &r));
+            SP_HIP(hipMemcpyAsync(dist.data(), ws->dist, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+            SP_HIP(hipStreamSynchronize(st));
+            for (int32_t v = 0; v < n; ++v) key[v] += dist[v] >= 0 ? dist[v] : n;
+        }
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->group_key.empty()) g->group_key = std::move(key);
+    }
+    const std::vector<int32_t> &key = g->group_key;  // immutable once set
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const int32_t sa = sources[a], sb = sources[b];
+        if (key[sa] != key[sb]) return key[sa] < key[sb];
+        return g->host_deg[sa] > g->host_deg[sb];
+    });
+    return SP_OK;
+}
+
 sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
                       const sp_batch_config *cfg, sp_stream s) {
     SP_GUARD_BEGIN
@@ -581,6 +636,10 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
             (void)hipEventDestroy(b);
         }
     } evrel{e0, e1};
+    std::vector<int32_t> order;
+    SP_TRY(source_groups(g, sources, n_sources, width, st, order));
+    std::vector<int32_t> grouped(n_sources);
+    for (int32_t i = 0; i < n_sources; ++i) grouped[i] = sources[order[i]];
     SP_HIP(hipEventRecord(e0, st));
     SP_TRY(launch_fill_f64(out_bc, g->n, 0.0, st));
     double *slots[kSlots];
@@ -589,7 +648,7 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
     for (int32_t b = 0; b < n_sources; b += width) {
         const int32_t nb = std::min(width, n_sources - b);
         BatchResult r;
-        SP_TRY(batch_run(g, *ws, sources + b, nb, slots, o, st, &r));
+        SP_TRY(batch_run(g, *ws, grouped.data() + b, nb, slots, o, st, &r));
         stats.n_passes++;
         stats.max_levels = std::max(stats.max_levels, r.levels);
         stats.levels_total += r.levels;

@@ -66,7 +66,10 @@ struct sp_graph_s {
     int32_t n_hubs = 0;          // vertices of degree > kHubDeg
     int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
     size_t bytes = 0;
-    std::mutex mu;               // guards `tuned` and the workspace pools
+    std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
+    std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
+                                     // (unreached: n each); empty until first needed
+    std::mutex mu;               // guards `tuned`, `group_key` and the workspace pools
     sp::TuneEntry tuned;
     std::vector<sp::SourceWorkspace *> src_pool;
     std::vector<sp::BatchWorkspace *> batch_pool;
