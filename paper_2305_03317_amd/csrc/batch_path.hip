@@ -878,27 +878,24 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
         advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap);
 }
 
-// One chunk of a hub, lane = slot: partial row of 64 doubles.  The last chunk
-// of the hub to finish sums the rows in chunk order and hands the result to
-// fin(lane_sum) (all lanes).
-template <class Row, class Final>
-__device__ __forceinline__ void ms_hub_chunk(const HubEntry &h, int32_t k, double *partial,
-                                             unsigned int *cnt, Row row, Final fin) {
+// Hubs, lane = slot: each chunk of kHubChunk adjacency entries is reduced by
+// its own wave into a row of `partial` (64 doubles); a second kernel adds a
+// hub's rows in chunk order.  The kernel boundary between them makes the rows
+// visible without fences inside either kernel.
+__device__ __forceinline__ double sum_rows(const double *__restrict__ partial, int32_t base,
+                                           int32_t n) {
     const int lane = lane_id();
-    const double x = row();
-    partial[(int64_t)k * kSlots + lane] = x;
-    __threadfence();
-    unsigned int old = 0;
-    if (lane == 0) old = atomicAdd(cnt, 1u);
-    old = __shfl(old, 0, kWave);
-    if (old == (unsigned int)h.nchunks - 1) {
-        __threadfence();
-        const volatile double *vp = partial;
-        double s = 0.0;
-        for (int32_t q = 0; q < h.nchunks; ++q) s += vp[(int64_t)(h.chunk_base + q) * kSlots + lane];
-        if (lane == 0) *cnt = 0;
-        fin(s);
+    double s = 0.0;
+    int32_t q = 0;
+    for (; q + 8 <= n; q += 8) {  // eight rows in flight, added in chunk order
+        double x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = partial[(int64_t)(base + q + t) * kSlots + lane];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += x[t];
     }
+    for (; q < n; ++q) s += partial[(int64_t)(base + q) * kSlots + lane];
+    return s;
 }
 
 // Path counts of the current level's hubs (after advance), chunk by chunk.
@@ -928,27 +925,44 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
-        ms_hub_chunk(h, (int32_t)k, partial, hub_cnt + (jh - hlo),
-                     [&] { return dense_sum(beg, end, m, pl, ci, front_par, val, pr); },
-                     [&](double s) {
-                         const bool mine = (m >> lane) & 1ull;
-                         if (mine) {
-                             val[qvb[h.entry] + rank_in(m, lane)] = s;
-                             my_max = fmax(my_max, s);
-                         }
-                         my_flag |= __ballot(mine && sigma_is_large(s));
-                     });
+        partial[(int64_t)k * kSlots + lane] = dense_sum(beg, end, m, pl, ci, front_par, val, pr);
         if (lane == 0) my_dag += pr;
-    }
-    my_max = wave_max_f64(my_max);
-    if (lane == 0) {
-        atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
-        if (my_flag) atomicOr(&c->flagged_slots_.v, my_flag);
     }
     if (prof) {
         block_add_u64<BS>(my_edges, s_red, prof + 1);
         __syncthreads();
         block_add_u64<BS>(my_dag, s_red, prof + 2);
+    }
+}
+
+// Path counts of the current level's hubs: each hub's chunk rows added in
+// chunk order (one wave per hub entry).
+__global__ void k_ms_sigma_hub_fin(LevelCtl *c, const unsigned long long *__restrict__ qmask,
+                                   const uint32_t *__restrict__ qvb, double *val,
+                                   const HubEntry *__restrict__ hub_list,
+                                   const double *__restrict__ partial) {
+    if (c->done) return;
+    const int32_t hlo = c->hub_lo, hhi = c->hub_hi;
+    const int lane = lane_id();
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    unsigned long long my_flag = 0;
+    double my_max = 0.0;
+    for (int64_t j = hlo + wave0; j < hhi; j += nwaves) {
+        const HubEntry h = hub_list[j];
+        const unsigned long long m = qmask[h.entry];
+        const double s = sum_rows(partial, h.chunk_base, h.nchunks);
+        const bool mine = (m >> lane) & 1ull;
+        if (mine) {
+            val[qvb[h.entry] + rank_in(m, lane)] = s;
+            my_max = fmax(my_max, s);
+        }
+        my_flag |= __ballot(mine && sigma_is_large(s));
+    }
+    my_max = wave_max_f64(my_max);
+    if (lane == 0) {
+        atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
+        if (my_flag) atomicOr(&c->flagged_slots_.v, my_flag);
     }
 }
 
@@ -1055,11 +1069,11 @@ __global__ __launch_bounds__(BS, 6) void k_ms_delta(LevelCtl *c, int32_t step,
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_delta_hub(
-    LevelCtl *c, int32_t step, const int32_t *__restrict__ hub_off,
+    const LevelCtl *c, const int32_t *__restrict__ hub_off,
     const int32_t *__restrict__ hub_lvl_chunks, const int32_t *__restrict__ rp,
     const int32_t *__restrict__ ci, const unsigned long long *__restrict__ qmask,
-    const uint32_t *__restrict__ qvb, const uint4 *f0, const uint4 *f1, double *val, double *dlt,
-    const HubEntry *hub_list, unsigned int *hub_cnt, double *partial, unsigned long long *prof) {
+    const uint4 *f0, const uint4 *f1, const double *val, const HubEntry *hub_list,
+    double *partial, unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
     const int32_t lvl = c->bwd_level;
     if (lvl < 1) return;
@@ -1079,13 +1093,7 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
-        ms_hub_chunk(h, (int32_t)k, partial, hub_cnt + (jh - hlo),
-                     [&] { return dense_sum(beg, end, m, nl, ci, front_rd, val, pr); },
-                     [&](double s) {
-                         if ((m >> lane) & 1ull)
-                             finish_slot(s, val + qvb[h.entry] + rank_in(m, lane),
-                                         dlt + (int64_t)h.v * kSlots + lane);
-                     });
+        partial[(int64_t)k * kSlots + lane] = dense_sum(beg, end, m, nl, ci, front_rd, val, pr);
         if (lane == 0) my_pairs += pr;
     }
     if (prof) {
@@ -1093,7 +1101,31 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
         __syncthreads();
         block_add_u64<BS>(my_pairs, s_red, prof + 2);
     }
-    if (step && last_block(c, working_blocks((int64_t)nch * kWave, BS)) && threadIdx.x == 0)
+}
+
+// Reverse sums of the swept level's hubs: chunk rows added in chunk order, then
+// delta and rho as for other entries; the last working block moves the sweep
+// one level up.
+__global__ void k_ms_delta_hub_fin(LevelCtl *c, const int32_t *__restrict__ hub_off,
+                                   const unsigned long long *__restrict__ qmask,
+                                   const uint32_t *__restrict__ qvb, double *val, double *dlt,
+                                   const HubEntry *__restrict__ hub_list,
+                                   const double *__restrict__ partial) {
+    const int32_t lvl = c->bwd_level;
+    if (lvl < 1) return;
+    const int32_t hlo = hub_off[lvl];
+    const int32_t nh = lvl == c->bwd_last ? 0 : hub_off[lvl + 1] - hlo;  // deepest: done in k_ms_delta
+    const int lane = lane_id();
+    const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t j = wave0; j < nh; j += nwaves) {
+        const HubEntry h = hub_list[hlo + j];
+        const unsigned long long m = qmask[h.entry];
+        const double s = sum_rows(partial, h.chunk_base, h.nchunks);
+        if ((m >> lane) & 1ull)
+            finish_slot(s, val + qvb[h.entry] + rank_in(m, lane), dlt + (int64_t)h.v * kSlots + lane);
+    }
+    if (last_block(c, working_blocks((int64_t)nh * kWave, (int)blockDim.x)) && threadIdx.x == 0)
         c->bwd_level = lvl - 1;
 }
 
@@ -1276,6 +1308,7 @@ template <int BS>
 static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int count, int grid,
                            int hub_grid, bool may_pull, unsigned long long active, hipStream_t s) {
     const bool hubs = g->n_hubs > 0;
+    const int hub_fin_grid = grid_for((int64_t)g->n_hubs * kWave, 256, device_cu_count() * 8);
     for (int k = 0; k < count; ++k) {
         const int64_t l = first + k;  // level this group expands
         uint4 *fcur = ws.front[l & 1], *fnxt = ws.front[(l + 1) & 1];
@@ -1316,6 +1349,10 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
                                (const uint32_t *)ws.qvb, (const uint4 *)fcur, ws.val,
                                (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
                                prof_counters(P_MS_SIGMA_HUB));
+            // (timed with the chunk kernel)
+            hipLaunchKernelGGL(k_ms_sigma_hub_fin, dim3(hub_fin_grid), dim3(256), 0, s, ws.ctl,
+                               (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
+                               ws.val, (const HubEntry *)ws.hub_list, (const double *)ws.partial);
         }
     }
 }
@@ -1414,6 +1451,7 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
 template <int BS>
 static void enqueue_reverse(sp_graph g, BatchWorkspace &ws, int count, int grid_d, int grid_h,
                             bool hubs, hipStream_t s) {
+    const int hub_fin_grid = grid_for((int64_t)g->n_hubs * kWave, 256, device_cu_count() * 8);
     for (int k = 0; k < count; ++k) {
         {
             ProfScope ps(P_MS_DELTA, s);
@@ -1423,14 +1461,20 @@ static void enqueue_reverse(sp_graph g, BatchWorkspace &ws, int count, int grid_
                                ws.dlt, prof_counters(P_MS_DELTA));
         }
         if (hubs) {
-            ProfScope ps(P_MS_DELTA_HUB, s);
-            hipLaunchKernelGGL(k_ms_delta_hub<BS>, dim3(grid_h), dim3(BS), 0, s, ws.ctl, 1,
-                               (const int32_t *)ws.hub_off,
-                               (const int32_t *)ws.hub_lvl_chunks, g->row_ptr, g->col_idx,
-                               (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
-                               (const uint4 *)ws.front[0], (const uint4 *)ws.front[1], ws.val, ws.dlt,
-                               (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
-                               prof_counters(P_MS_DELTA_HUB));
+            ProfScope ps(P_MS_DELTA_HUB, s);  // chunk and finishing kernels together
+            {
+                hipLaunchKernelGGL(k_ms_delta_hub<BS>, dim3(grid_h), dim3(BS), 0, s,
+                                   (const LevelCtl *)ws.ctl, (const int32_t *)ws.hub_off,
+                                   (const int32_t *)ws.hub_lvl_chunks, g->row_ptr, g->col_idx,
+                                   (const unsigned long long *)ws.qmask, (const uint4 *)ws.front[0],
+                                   (const uint4 *)ws.front[1], (const double *)ws.val,
+                                   (const HubEntry *)ws.hub_list, ws.partial,
+                                   prof_counters(P_MS_DELTA_HUB));
+            }
+            hipLaunchKernelGGL(k_ms_delta_hub_fin, dim3(hub_fin_grid), dim3(256), 0, s, ws.ctl,
+                               (const int32_t *)ws.hub_off, (const unsigned long long *)ws.qmask,
+                               (const uint32_t *)ws.qvb, ws.val, ws.dlt,
+                               (const HubEntry *)ws.hub_list, (const double *)ws.partial);
         }
     }
 }
