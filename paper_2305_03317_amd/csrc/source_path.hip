@@ -306,32 +306,33 @@ __global__ void k_src_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
 }
 
 // One chunk of a hub: lanes stride over its entries, each summing in order,
-// then a fixed xor tree.  The last chunk of the hub to finish adds the
-// partials in chunk order.  Returns true in the wave that finalised.
-template <class Term, class Final>
-__device__ __forceinline__ void hub_chunk(const HubEntry &h, int32_t k, int32_t beg, int32_t end,
-                                          double *partial, unsigned int *cnt, Term term, Final fin) {
+// then a fixed xor tree; the chunk's sum goes to partial[k].  A finishing
+// kernel adds a hub's chunk sums in chunk order (the kernel boundary makes
+// them visible, so no fence is needed here).
+template <class Term>
+__device__ __forceinline__ void hub_chunk(int32_t k, int32_t beg, int32_t end, double *partial,
+                                          Term term) {
     const int lane = lane_id();
     double x = 0.0;
     for (int32_t e = beg + lane; e < end; e += kWave) x += term(e);
     x = wave_sum_f64(x);
-    unsigned int old = 0;
-    if (lane == 0) {
-        partial[k] = x;
-        __threadfence();
-        old = atomicAdd(cnt, 1u);
+    if (lane == 0) partial[k] = x;
+}
+
+// Sum of partial[base .. base+n) in index order, eight loads in flight.
+__device__ __forceinline__ double sum_chunks(const double *__restrict__ partial, int32_t base,
+                                             int32_t n) {
+    double s = 0.0;
+    int32_t q = 0;
+    for (; q + 8 <= n; q += 8) {
+        double x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = partial[base + q + t];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += x[t];
     }
-    old = __shfl(old, 0, kWave);
-    if (old == (unsigned int)h.nchunks - 1) {
-        __threadfence();
-        if (lane == 0) {
-            double s = 0.0;
-            const volatile double *vp = partial;
-            for (int32_t q = 0; q < h.nchunks; ++q) s += vp[h.chunk_base + q];
-            *cnt = 0;
-            fin(s);
-        }
-    }
+    for (; q < n; ++q) s += partial[base + q];
+    return s;
 }
 
 // Path counts of the current level's hubs (parents one level up).
@@ -351,18 +352,28 @@ __global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t
         const HubEntry h = hub_list[j];
         const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
-        hub_chunk(h, (int32_t)k, beg, end, partial, hub_cnt + (j - hlo),
-                  [&](int32_t e) {
-                      const int32_t u = ci[e];
-                      return dist[u] == pl ? sigma[u] : 0.0;
-                  },
-                  [&](double s) {
-                      sigma[h.v] = s;
-                      atomic_max_nonneg_f64(&c->sigma_max_bits_.v, s);
-                      if (sigma_is_large(s)) atomicOr(&c->flagged_slots_.v, 1ull);
-                  });
+        hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) {
+            const int32_t u = ci[e];
+            return dist[u] == pl ? sigma[u] : 0.0;
+        });
     }
+    (void)hub_cnt;
     (void)prof;
+}
+
+// Path counts of the current level's hubs from their chunk sums (a thread per hub).
+__global__ void k_src_sigma_hub_fin(LevelCtl *c, double *sigma, const HubEntry *__restrict__ hub_list,
+                                    const double *__restrict__ partial) {
+    if (c->done) return;
+    const int32_t hlo = c->hub_lo, hhi = c->hub_hi;
+    for (int64_t j = hlo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hhi;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const HubEntry h = hub_list[j];
+        const double s = sum_chunks(partial, h.chunk_base, h.nchunks);
+        sigma[h.v] = s;
+        atomic_max_nonneg_f64(&c->sigma_max_bits_.v, s);
+        if (sigma_is_large(s)) atomicOr(&c->flagged_slots_.v, 1ull);
+    }
 }
 
 // Reverse sweep over one level (hubs excluded; see k_src_delta_hub).
@@ -427,15 +438,26 @@ __global__ __launch_bounds__(BS) void k_src_delta_hub(
         const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
         const double sv = sigma[h.v];
-        hub_chunk(h, (int32_t)k, beg, end, partial, hub_cnt + (j - hlo),
-                  [&](int32_t e) {
-                      const int32_t w = ci[e];
-                      return dist[w] == nl ? (sv / sigma[w]) * (1.0 + delta[w]) : 0.0;
-                  },
-                  [&](double s) {
-                      delta[h.v] = s;
-                      if (bc) bc[h.v] += s;
-                  });
+        hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) {
+            const int32_t w = ci[e];
+            return dist[w] == nl ? (sv / sigma[w]) * (1.0 + delta[w]) : 0.0;
+        });
+    }
+    (void)hub_cnt;
+    (void)bc;
+}
+
+// Dependencies of one level's hubs from their chunk sums (a thread per hub).
+__global__ void k_src_delta_hub_fin(const int32_t *__restrict__ hub_off, int32_t lvl, double *delta,
+                                    double *bc, const HubEntry *__restrict__ hub_list,
+                                    const double *__restrict__ partial) {
+    const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1];
+    for (int64_t j = hlo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hhi;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const HubEntry h = hub_list[j];
+        const double s = sum_chunks(partial, h.chunk_base, h.nchunks);
+        delta[h.v] = s;
+        if (bc) bc[h.v] += s;
     }
 }
 
@@ -527,6 +549,9 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                                    dim3(BS), 0, s, ws.ctl, g->row_ptr, g->col_idx, ws.dist, ws.sigma,
                                    (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
                                    prof_counters(P_SRC_SIGMA_HUB));
+                hipLaunchKernelGGL(k_src_sigma_hub_fin, dim3(grid_for(g->n_hubs, 256, maxb)), dim3(256), 0, s,
+                                   ws.ctl, ws.sigma, (const HubEntry *)ws.hub_list,
+                                   (const double *)ws.partial);
             }
         }
         SP_HIP(hipGetLastError());
@@ -563,6 +588,9 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                                    (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
                                    ws.dist, ws.sigma, ws.delta, bc, (const HubEntry *)ws.hub_list,
                                    ws.hub_cnt, ws.partial);
+                hipLaunchKernelGGL(k_src_delta_hub_fin, dim3(grid_for(g->n_hubs, 256, maxb)), dim3(256), 0, s,
+                                   (const int32_t *)ws.hub_off, l, ws.delta, bc,
+                                   (const HubEntry *)ws.hub_list, (const double *)ws.partial);
             }
         }
         SP_HIP(hipGetLastError());
