@@ -173,8 +173,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=80,
                     help="requests per phase of the serving workload (0 = skip)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
-                    help="run one device-to-device copy of this many GiB first (a known-size "
-                         "kernel that calibrates hardware byte counters in a profiler run)")
+                    help="first run one elementwise kernel that reads and writes this many GiB "
+                         "(a known-size kernel that calibrates hardware byte counters in a "
+                         "profiler run)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -194,25 +195,30 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.copy_gib > 0:
+        # one full-grid elementwise kernel that reads and writes copy_gib GiB
+        # (int32 negation), found by name in the counter output
         nbytes = int(args.copy_gib * (1 << 30))
         a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
     # Device copy bandwidth on this machine (a 2 GiB device-to-device copy, best of
     # 3): the streaming reference that the kernels' rates are also quoted against.
+    # Skipped in counter-calibration runs, whose only large copy must be the
+    # calibration copy above.
     cbuf = torch.empty(1 << 29, dtype=torch.int32, device="cuda").fill_(1)
     cdst = torch.empty_like(cbuf)
-    copy_gbps = 0.0
-    for _ in range(3):
+    copy_gbps = float("nan")
+    for _ in range(0 if args.copy_gib > 0 else 3):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         cdst.copy_(cbuf)
         e1.record()
         torch.cuda.synchronize()
-        copy_gbps = max(copy_gbps, 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
     k = WORKLOADS[args.workload]
 
@@ -244,8 +250,11 @@ def main():
     torch.cuda.synchronize()
 
     def run_steps(tag):
+        return run_steps_n(args.steps, tag)
+
+    def run_steps_n(k, tag):
         times, dev_ms, statuses = [], [], []
-        for _ in range(args.steps):
+        for _ in range(k):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, st = sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
@@ -264,15 +273,25 @@ def main():
     value = len(src) * m / step_s
 
     # Kernel-timed region: the same steps again with a HIP event pair around
-    # every launch (on the library's stream) and device work counters; the
-    # forward chunks are launched directly here, since events cannot be read
-    # per kernel inside a replayed graph.
-    sp.sp_profile_enable(True)
+    # every launch (on the library's stream); the level chunks are launched
+    # directly here, since events cannot be read per kernel inside a replayed
+    # graph.  Then one more step with the device work counters on (they add
+    # reductions to the kernels, so they are not on while timing): the work is
+    # the same every step, so the counts per launch apply to the timed launches.
     sp.sp_profile_read()  # discard anything earlier
+    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
     ptimes, _, pstat = run_steps("kernel-timed")
     prof = sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
+    _, _, cstat = run_steps_n(1, "counted")
+    counted = sp.sp_profile_read()
     sp.sp_profile_enable(False)
-    statuses += pstat
+    statuses += pstat + cstat
+    for kname, p in prof.items():  # counts per launch x timed launches
+        c = counted.get(kname)
+        scale = p["launches"] / c["launches"] if c and c["launches"] else 0.0
+        for unit in ("items", "edges", "pairs", "item_slots"):
+            p[unit] = (c[unit] * scale) if c else 0
 
     traffic_doc = load_traffic(spec["name"])
     # dominant kernel: most time inside the kernel-timed region
@@ -290,7 +309,7 @@ def main():
                     "avg_launch_ms": round(p["total_ms"] / launches, 4),
                     "algorithmic_bytes_per_launch": int(algorithmic_bytes(name, p) / launches),
                     "traffic_source": traffic_doc["path"] if tr else None}
-        roofline["frac_of_measured_copy"] = round(achieved / copy_gbps, 4)
+        roofline["frac_of_measured_copy"] = round(achieved / copy_gbps, 4) if copy_gbps == copy_gbps else None
         if tr:
             roofline["traffic_GBps"] = round(tr["traffic_bytes_per_launch"] / (p["total_ms"] / launches * 1e-3) / 1e9, 1)
     kernels = {}
@@ -395,7 +414,7 @@ def main():
         "graph_launches_per_step": stats["graph_launches"],
         "status": max(statuses),
         "upload_ms": upload_ms,
-        "hbm_copy_GBps_measured": round(copy_gbps, 1),
+        "hbm_copy_GBps_measured": round(copy_gbps, 1) if copy_gbps == copy_gbps else None,
         "graph_build_s": gen_s,
         "per_source_path": per_source,
         "batched_over_per_source": (value / per_source["teps"]) if per_source else None,

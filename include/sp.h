@@ -211,18 +211,24 @@ sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_sources,
 /* Per kernel family: launches, HIP-event time, and the work it did. */
 typedef struct sp_kernel_profile {
     char name[32];      /* kernel family, e.g. "ms_delta" */
-    int64_t launches;
+    int64_t launches;   /* launches while profiling was on (either bit) */
     double total_ms;    /* sum over launches of the time between HIP events recorded
-                           on the launch stream immediately before and after it */
+                           on the launch stream immediately before and after it
+                           (0 unless SP_PROFILE_TIMES) */
     int64_t items;      /* vertices (per-source path) or (vertex, level) entries (batched) */
     int64_t edges;      /* adjacency entries scanned */
     int64_t pairs;      /* DAG edges accumulated (per-source) or (slot, DAG edge) pairs (batched) */
     int64_t item_slots; /* batched: sum over entries of their slot count; per-source: = items */
 } sp_kernel_profile;
 
-/* Turn timing on or off for all later launches of this process (off by
- * default; on adds two event records per launch). */
-sp_status sp_profile_enable(int32_t on);
+/* What sp_profile_enable turns on for all later launches of this process
+ * (0 = off, the default).  Either one makes the batched path launch its
+ * level kernels directly instead of replaying captured graphs. */
+#define SP_PROFILE_TIMES 1  /* a HIP event pair around every launch (total_ms) */
+#define SP_PROFILE_COUNTS 2 /* device work counters (items, edges, pairs, item_slots); they
+                               add reductions to the kernels, so time and count in
+                               separate runs when the times matter */
+sp_status sp_profile_enable(int32_t what); /* SP_ERR_INVALID_ARGUMENT on unknown bits */
 
 /* Synchronise every stream used, write up to `cap` families with at least one
  * launch into out[], their count into *n_out, and reset the totals. */

@@ -1149,15 +1149,30 @@ __global__ __launch_bounds__(BS) void k_ms_bc(int32_t n, const unsigned long lon
         const double *row = delta + (int64_t)v * kSlots;
         double *cur = nullptr;
         double acc = 0.0;
-        for (int32_t s = 0; s < nslots; ++s) {
-            double *out = tbl.out[s];
-            if (!out) continue;
-            if (out != cur) {
-                if (cur) cur[v] = acc;
-                cur = out;
-                acc = out[v];
+        // The row is read a cache line (16 doubles) at a time, so each line is
+        // fetched once and used whole; slots are still added one by one in order.
+        for (int32_t s0 = 0; s0 < nslots; s0 += 16) {
+            double x[16];
+            const double2 *r2 = reinterpret_cast<const double2 *>(row + s0);  // inside the 64-slot row
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double2 p = r2[t];
+                x[2 * t] = p.x;
+                x[2 * t + 1] = p.y;
             }
-            if (((sm >> s) & 1ull) && s_src[s] != v) acc += row[s];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int32_t s = s0 + t;
+                if (s >= nslots) break;
+                double *out = tbl.out[s];
+                if (!out) continue;
+                if (out != cur) {
+                    if (cur) cur[v] = acc;
+                    cur = out;
+                    acc = out[v];
+                }
+                if (((sm >> s) & 1ull) && s_src[s] != v) acc += x[t];
+            }
         }
         if (cur) cur[v] = acc;
     }
@@ -1564,7 +1579,9 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         const std::array<long long, 12> key{BS, grid_d, grid_h, kBwdChunk, hubs,
                                             (long long)(intptr_t)ws.queue, ws.qcap,
                                             (long long)(intptr_t)ws.val, ws.vcap, 0, 0, 0};
-        for (int32_t done = 0; done < steps; done += kBwdChunk) {
+        // whole chunks from the graph, the remainder directly (no idle launches)
+        const int32_t whole = steps / kBwdChunk * kBwdChunk;
+        for (int32_t done = 0; done < whole; done += kBwdChunk) {
             SP_TRY(replay_chunk(ws, ws.bwd, key,
                                 [&](hipStream_t cs) {
                                     enqueue_reverse<BS>(g, ws, kBwdChunk, grid_d, grid_h, hubs, cs);
@@ -1572,6 +1589,7 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
                                 s));
             ++graph_launches;
         }
+        if (steps > whole) enqueue_reverse<BS>(g, ws, steps - whole, grid_d, grid_h, hubs, s);
     } else if (steps > 0) {
         enqueue_reverse<BS>(g, ws, steps, grid_d, grid_h, hubs, s);
     }

@@ -1,6 +1,8 @@
 // Kernel timing for measurement: HIP events recorded on the launch stream
-// immediately before and after each launch of a kernel family, plus device
-// counters of the work each family did.  Off unless sp_profile_enable(1).
+// immediately before and after each launch of a kernel family
+// (SP_PROFILE_TIMES), and device counters of the work each family did
+// (SP_PROFILE_COUNTS).  The counters add reductions to the kernels, so the two
+// are best taken in separate runs.  Off unless sp_profile_enable.
 #include <atomic>
 #include <vector>
 
@@ -15,7 +17,7 @@ const char *const kProfNames[P_COUNT] = {
 };
 
 namespace {
-std::atomic<bool> g_on{false};
+std::atomic<int> g_on{0};  // SP_PROFILE_* bits
 std::mutex g_mu;
 struct Pending {
     int kind;
@@ -33,16 +35,18 @@ hipEvent_t take_event() {
         g_pool.pop_back();
         return e;
     }
+    // Timing only: without the system-scope fence an event record does not
+    // write back and invalidate the caches, which would slow the next kernel.
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 }  // namespace
 
-bool prof_enabled() { return g_on.load(std::memory_order_relaxed); }
+bool prof_enabled() { return g_on.load(std::memory_order_relaxed) != 0; }
 
 unsigned long long *prof_counters(int kind) {
-    if (!prof_enabled()) return nullptr;
+    if (!(g_on.load(std::memory_order_relaxed) & SP_PROFILE_COUNTS)) return nullptr;
     int d = 0;
     if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -57,8 +61,11 @@ unsigned long long *prof_counters(int kind) {
 }
 
 ProfScope::ProfScope(int kind, hipStream_t s) : kind_(kind), s_(s) {
-    if (!prof_enabled()) return;
+    const int on = g_on.load(std::memory_order_relaxed);
+    if (!on) return;
     std::lock_guard<std::mutex> lk(g_mu);
+    g_launches[kind]++;
+    if (!(on & SP_PROFILE_TIMES)) return;
     a_ = take_event();
     if (a_ && hipEventRecord(a_, s_) != hipSuccess) a_ = nullptr;
 }
@@ -76,8 +83,12 @@ using namespace sp;
 
 extern "C" {
 
-sp_status sp_profile_enable(int32_t on) {
-    g_on.store(on != 0);
+sp_status sp_profile_enable(int32_t what) {
+    if (what & ~(int32_t)(SP_PROFILE_TIMES | SP_PROFILE_COUNTS)) {
+        set_error("sp_profile_enable: unknown bits 0x%x", (unsigned)what);
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    g_on.store(what);
     return SP_OK;
 }
 
@@ -89,10 +100,8 @@ sp_status sp_profile_read(sp_kernel_profile *out, int32_t cap, int32_t *n_out) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &p : g_pending) {
         float ms = 0.f;
-        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-            g_launches[p.kind]++;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess)
             g_ms[p.kind] += ms;
-        }
         g_pool.push_back(p.a);
         g_pool.push_back(p.b);
     }

@@ -6,8 +6,9 @@ Inputs are the CSV directories of three runs of the same bench.py command:
   (per-kernel calls, total and average duration);
 * ``--fetch DIR`` / ``--write DIR``: ``rocprofv3 --pmc FETCH_SIZE`` and
   ``--pmc WRITE_SIZE`` (KiB per dispatch), each run with ``bench.py
-  --copy-gib G`` so that a device-to-device copy of G GiB (read G, write G)
-  calibrates the counters: factor = known bytes / counted bytes.
+  --copy-gib G`` so that one elementwise kernel that reads G GiB and writes
+  G GiB (int32 negation) calibrates the counters: factor = known bytes /
+  counted bytes.  Optional: without them only the kernel trace is summarised.
 
 Writes a Markdown summary (the commands, the kernel table, calibrated HBM bytes
 per dispatch) and a JSON file of per-family bytes per launch that bench.py
@@ -92,18 +93,21 @@ def read_pmc(d, counter):
 
 
 def calibration(per, copy_bytes):
-    copies = [v for k, vals in per.items() if "copyBuffer" in k for v in vals]
-    if not copies:
-        raise SystemExit("no copy kernel in the counter run (run bench.py with --copy-gib)")
-    big = max(copies)
-    return copy_bytes / big, big
+    """Factor = known bytes of the calibration kernel / bytes the counter saw.
+    The calibration kernel is the one elementwise negation bench.py runs with
+    --copy-gib; its dispatches are summed in case the runtime splits it."""
+    hits = [v for k, vals in per.items() if "neg" in k.lower() for v in vals if v >= copy_bytes / 16]
+    if not hits:
+        raise SystemExit("no calibration kernel in the counter run (run bench.py with --copy-gib)")
+    seen = sum(hits)
+    return copy_bytes / seen, seen
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--copy-gib", type=float, default=1.0)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--command", action="append", default=[], help="command line(s) that made the runs")
@@ -113,10 +117,11 @@ def main():
 
     copy_bytes = a.copy_gib * (1 << 30)
     stats = read_stats(a.stats)
-    fetch = read_pmc(a.fetch, "FETCH_SIZE")
-    write = read_pmc(a.write, "WRITE_SIZE")
-    cf, fb = calibration(fetch, copy_bytes)
-    cw, wb = calibration(write, copy_bytes)
+    counters = bool(a.fetch and a.write)
+    fetch = read_pmc(a.fetch, "FETCH_SIZE") if counters else {}
+    write = read_pmc(a.write, "WRITE_SIZE") if counters else {}
+    cf, fb = calibration(fetch, copy_bytes) if counters else (0.0, 0.0)
+    cw, wb = calibration(write, copy_bytes) if counters else (0.0, 0.0)
     digest = source_digest()
 
     fam = {}
@@ -128,10 +133,12 @@ def main():
               "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
     for r in sorted(stats, key=lambda r: -r["total_ms"])[:20]:
         lines.append("| %s | %d | %.3f | %.2f | %.2f |" % (r["name"], r["calls"], r["total_ms"], r["avg_us"], r["pct"]))
-    lines += ["", "## HBM traffic (--pmc FETCH_SIZE, --pmc WRITE_SIZE, separate runs)", "",
-              "Calibration: a device copy of %.0f MiB (reads and writes that many bytes) counted "
-              "FETCH_SIZE %.1f MiB and WRITE_SIZE %.1f MiB, so FETCH_SIZE is scaled by %.4f and "
-              "WRITE_SIZE by %.4f." % (copy_bytes / 2**20, fb / 2**20, wb / 2**20, cf, cw), "",
+    if not counters:
+        lines += ["", "(No counter runs for this workload.)"]
+    lines += [] if not counters else ["", "## HBM traffic (--pmc FETCH_SIZE, --pmc WRITE_SIZE, separate runs)", "",
+              "Calibration: one elementwise kernel (int32 negation) that reads and writes %.0f MiB "
+              "counted FETCH_SIZE %.1f MiB and WRITE_SIZE %.1f MiB, so FETCH_SIZE is scaled by %.4f "
+              "and WRITE_SIZE by %.4f." % (copy_bytes / 2**20, fb / 2**20, wb / 2**20, cf, cw), "",
               "| kernel | dispatches | FETCH MiB/dispatch (raw) | WRITE MiB/dispatch (raw) | "
               "calibrated MB/dispatch | calibrated GB total |", "|---|---:|---:|---:|---:|---:|"]
     names = sorted(set(fetch) | set(write), key=lambda k: -sum(fetch.get(k, [])))

@@ -311,8 +311,14 @@ def sp_bc_workspace_bytes(g: Graph, batch_width: int) -> int:
     return b.value
 
 
-def sp_profile_enable(on: bool = True):
-    _check(lib().sp_profile_enable(1 if on else 0), "sp_profile_enable")
+SP_PROFILE_TIMES = 1
+SP_PROFILE_COUNTS = 2
+
+
+def sp_profile_enable(on=True):
+    """True: times and counters; False: off; or an int of SP_PROFILE_* bits."""
+    what = (SP_PROFILE_TIMES | SP_PROFILE_COUNTS) if on is True else (0 if on is False else int(on))
+    _check(lib().sp_profile_enable(what), "sp_profile_enable")
 
 
 def sp_profile_read() -> dict:

@@ -120,3 +120,16 @@ def test_server_calls_reject_bad_arguments_on_the_host():
     n = ctypes.c_int32()
     assert L.sp_profile_read(None, 4, ctypes.byref(n)) == sp.SP_ERR_INVALID_ARGUMENT
     assert L.sp_profile_enable(0) == sp.SP_OK
+    assert L.sp_profile_enable(8) == sp.SP_ERR_INVALID_ARGUMENT
+
+
+def test_header_constants_match_binding():
+    """Every #define in include/sp.h that the binding mirrors has the same value."""
+    import re
+    text = open(os.path.join(ROOT, "include", "sp.h")).read()
+    defs = dict((k, int(v.rstrip("u"), 0)) for k, v in
+                re.findall(r"#define\s+(SP_\w+)\s+\(?(-?(?:0x)?[0-9a-fA-F]+u?)\)?", text))
+    mirrored = [k for k in defs if hasattr(sp, k)]
+    assert {"SP_OK", "SP_PTR_DEVICE", "SP_VALIDATE", "SP_PROFILE_TIMES", "SP_PROFILE_COUNTS"} <= set(mirrored)
+    for k in mirrored:
+        assert getattr(sp, k) == defs[k], k
