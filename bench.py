@@ -89,7 +89,7 @@ def load_traffic(workload):
     return doc
 
 
-def serving_benchmark(sp, torch, n_requests, seed=2005):
+def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
     """Serving workload: eight resident graphs, seeded requests (graph uniform,
     1..512 sources log-uniform), continuous batching by the library's server.
     Phase "burst" submits every request at once (saturation throughput);
@@ -104,7 +104,9 @@ def serving_benchmark(sp, torch, n_requests, seed=2005):
     build_s = time.perf_counter() - t0
     handles = [sp.sp_graph_upload(rp, ci) for _, rp, ci in gs]
     edges = [len(ci) // 2 for _, _, ci in gs]
-    srv = sp.Server()
+    # an explicit workspace budget (the library's default is a quarter of the
+    # free memory at creation, which depends on what ran before)
+    srv = sp.Server(memory_budget=budget_gb << 30)
     ids = [srv.add_graph(h) for h in handles]
     outs = [torch.empty(max(h.n, 1), dtype=torch.float64, device="cuda") for h in handles]
     for gid, h in zip(ids, handles):  # warm: workspaces and captured graphs exist before timing
@@ -126,9 +128,19 @@ def serving_benchmark(sp, torch, n_requests, seed=2005):
                 time.sleep(delay)
             out = torch.empty(max(handles[gi].n, 1), dtype=torch.float64, device="cuda")
             live.append(srv.submit(ids[gi], src, out_bc=out))
-        bad = 0
-        for r in live:
-            bad += r.wait() != sp.SP_OK
+        bad, warned, errors = 0, 0, {}
+        for k, r in enumerate(live):
+            st = r.wait()
+            if (k + 1) % 20 == 0:
+                print("  %d/%d requests done, %.1f s" % (k + 1, len(live), time.perf_counter() - start),
+                      file=sys.stderr, flush=True)
+            if st < 0:
+                bad += 1
+                msg = sp.lib().sp_last_error()
+                msg = msg.decode() if isinstance(msg, bytes) else str(msg)
+                errors[msg] = errors.get(msg, 0) + 1
+            elif st > 0:
+                warned += 1
         wall = time.perf_counter() - start
         lat = np.array([r.latency_us() for r in live]) / 1e3
         for r in live:
@@ -137,7 +149,8 @@ def serving_benchmark(sp, torch, n_requests, seed=2005):
         return {"offered_qps": round(rate, 3) if rate else None, "achieved_qps": round(len(reqs) / wall, 3),
                 "teps": work / wall, "p50_ms": round(float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(float(np.percentile(lat, 99)), 2), "max_ms": round(float(lat.max()), 2),
-                "wall_s": round(wall, 2), "failed": int(bad)}
+                "wall_s": round(wall, 2), "failed": int(bad), "sigma_warnings": int(warned),
+                "errors": errors or None}
 
     burst = phase(0)
     sat = burst["achieved_qps"]
@@ -149,6 +162,9 @@ def serving_benchmark(sp, torch, n_requests, seed=2005):
     res["passes"] = st["passes"]
     res["mean_slots_per_pass"] = round(st["slots_used"] / max(st["passes"], 1), 1)
     res["peak_admitted_GB"] = round(st["peak_admitted_bytes"] / 1e9, 2)
+    res["memory_budget_GB"] = round((budget_gb << 30) / 1e9, 1)
+    res["workspaces_created"] = st["workspaces_created"]
+    res["workspaces_evicted"] = st["workspaces_evicted"]
     srv.destroy()
     for h in handles:
         h.release()

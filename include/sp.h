@@ -254,6 +254,8 @@ typedef struct sp_server_stats {
     size_t peak_admitted_bytes;
     int32_t queue_depth;     /* sources waiting */
     int32_t in_flight;       /* passes on the device */
+    int64_t workspaces_created;  /* pass workspaces allocated */
+    int64_t workspaces_evicted;  /* idle workspaces freed to admit another graph's */
 } sp_server_stats;
 
 /* Start a server: a scheduler thread packs queued sources of each graph into
@@ -275,7 +277,9 @@ sp_status sp_stream_submit(sp_server srv, int32_t graph_id, const int32_t *sourc
 
 /* Wait until the request finishes or timeout_us passes (< 0 waits forever).
  * Returns SP_OK when finished (its status in *result), SP_ERR_TIMEOUT
- * otherwise. */
+ * otherwise.  A request's status carries SP_WARN_SIGMA_LARGE only when one of
+ * its own sources overflowed; when it failed (negative status),
+ * sp_last_error() on the waiting thread then gives the detail. */
 sp_status sp_request_wait(sp_request r, int64_t timeout_us, sp_status *result);
 
 /* Non-blocking: 1 in *done if finished (status in *result), else 0. */

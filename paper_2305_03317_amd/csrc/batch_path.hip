@@ -312,6 +312,7 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->sigma_max_bits_.v = (unsigned long long)__double_as_longlong(1.0);
         c->flagged_slots_.v = 0;
         c->live = active;  // every slot's level-0 frontier holds its source
+        c->active = active;
         c->nlive_.v = 0;
         c->blocks_done_.v = 0;
         c->alpha = alpha;
@@ -427,8 +428,8 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
                                                     const unsigned long long *__restrict__ seen,
                                                     unsigned long long *nxt,
                                                     const uint4 *__restrict__ front_cur,
-                                                    int32_t *queue, unsigned long long active,
-                                                    long long qcap, unsigned long long *prof) {
+                                                    int32_t *queue, long long qcap,
+                                                    unsigned long long *prof) {
     if (c->done || c->mode != MODE_BOTTOMUP) return;
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
     __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
         int32_t beg = 0, deg = 0;
         unsigned long long u_s = 0;
         if (v < n) {
-            u_s = active & c->live & ~seen[v];
+            u_s = c->live & ~seen[v];  // live only ever holds slots in use
             if (u_s) {
                 beg = rp[v];
                 deg = rp[v + 1] - beg;
@@ -599,11 +600,11 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                                                  const uint4 *__restrict__ front_cur,
                                                  uint4 *front_nxt, double *val, long long vcap,
                                                  HubEntry *hub_list, long long hub_cap,
-                                                 unsigned long long active, long long qcap,
-                                                 int32_t track_deg, int32_t *level_off,
+                                                 long long qcap, int32_t track_deg, int32_t *level_off,
                                                  int32_t *hub_off, int32_t *hub_lvl_chunks,
                                                  unsigned long long *prof) {
     if (c->done) return;
+    const unsigned long long active = c->active;
     __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
     __shared__ int32_t s_scan[BS / kWave + 1];
     const uint32_t lvl = (uint32_t)c->level;
@@ -738,9 +739,10 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
     LevelCtl *c, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t *queue,
     unsigned long long *qmask, uint32_t *qvb, unsigned long long *seen, int32_t *claim,
     const uint4 *__restrict__ front_cur, uint4 *front_nxt, double *val, long long vcap,
-    unsigned long long active, long long qcap, int32_t *level_off, int32_t *hub_off,
-    int32_t *hub_lvl_chunks, long long hub_cap, unsigned long long *prof) {
+    long long qcap, int32_t *level_off, int32_t *hub_off, int32_t *hub_lvl_chunks, long long hub_cap,
+    unsigned long long *prof) {
     if (c->done) return;
+    const unsigned long long active = c->active;
     __shared__ int32_t s_own[kExpandDeg * BS], s_cnt[1], s_scan[BS / kWave + 1];
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
     __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
@@ -1321,7 +1323,7 @@ static sp_status grow_queue(sp_graph g, BatchWorkspace &ws, int64_t qcap) {
 // launches serve any chunk whose first level has the same parity.
 template <int BS>
 static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int count, int grid,
-                           int hub_grid, bool may_pull, unsigned long long active, hipStream_t s) {
+                           int hub_grid, bool may_pull, hipStream_t s) {
     const bool hubs = g->n_hubs > 0;
     const int hub_fin_grid = grid_for((int64_t)g->n_hubs * kWave, 256, device_cu_count() * 8);
     for (int k = 0; k < count; ++k) {
@@ -1331,7 +1333,7 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
             ProfScope ps(P_MS_EXPAND, s);
             hipLaunchKernelGGL(k_ms_expand<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, (int32_t *)ws.nxt,
-                               (const uint4 *)fcur, fnxt, ws.val, (long long)ws.vcap, active,
+                               (const uint4 *)fcur, fnxt, ws.val, (long long)ws.vcap,
                                (long long)ws.qcap, ws.level_off, ws.hub_off, ws.hub_lvl_chunks,
                                (long long)ws.hub_cap, prof_counters(P_MS_EXPAND));
             continue;
@@ -1346,15 +1348,15 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
         if (may_pull) {
             ProfScope ps(P_MS_BOTTOMUP, s);
             hipLaunchKernelGGL(k_ms_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                               g->col_idx, ws.seen, ws.nxt, fcur, ws.queue, active,
-                               (long long)ws.qcap, prof_counters(P_MS_BOTTOMUP));
+                               g->col_idx, ws.seen, ws.nxt, fcur, ws.queue, (long long)ws.qcap,
+                               prof_counters(P_MS_BOTTOMUP));
         }
         {
             ProfScope ps(P_MS_SIGMA, s);
             hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
                                ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
-                               active, (long long)ws.qcap, (int32_t)may_pull, ws.level_off,
+                               (long long)ws.qcap, (int32_t)may_pull, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks, prof_counters(P_MS_SIGMA));
         }
         if (hubs) {
@@ -1434,18 +1436,18 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
         const bool deep = rounds >= 4;
         const int chunk = deep ? 4 * short_chunk : short_chunk;
         if (capture) {
-            const std::array<long long, 12> key{BS, grid, hub_grid, chunk, (long long)active, may_pull,
+            // the slot set lives in the control block, so one capture serves every pass
+            const std::array<long long, 12> key{BS, grid, hub_grid, chunk, 0, may_pull,
                                                 (long long)(intptr_t)ws.queue, ws.qcap,
                                                 (long long)(intptr_t)ws.val, ws.vcap, 0, 0};
             SP_TRY(replay_chunk(ws, deep ? ws.fwd_long : ws.fwd_short, key,
                                 [&](hipStream_t cs) {
-                                    enqueue_levels<BS>(g, ws, 0, chunk, grid, hub_grid, may_pull,
-                                                       active, cs);
+                                    enqueue_levels<BS>(g, ws, 0, chunk, grid, hub_grid, may_pull, cs);
                                 },
                                 s));
             ++*graph_launches;
         } else {
-            enqueue_levels<BS>(g, ws, enqueued, chunk, grid, hub_grid, may_pull, active, s);
+            enqueue_levels<BS>(g, ws, enqueued, chunk, grid, hub_grid, may_pull, s);
             SP_HIP(hipGetLastError());
         }
         enqueued += chunk;
@@ -1612,6 +1614,7 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         res->reached = (int64_t)c.reached_pairs;
         std::memcpy(&res->sigma_max, &c.sigma_max_bits_.v, sizeof(double));
         res->flagged = __builtin_popcountll(c.flagged_slots_.v);
+        res->flagged_mask = c.flagged_slots_.v;
         res->td = c.topdown_levels;
         res->bu = c.bottomup_levels;
         res->entries = off[levels];

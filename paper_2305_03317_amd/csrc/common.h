@@ -128,6 +128,7 @@ struct LevelCtl {
     unsigned long long reached_pairs;  // (slot, vertex) pairs reached (per-source: vertices)
     double alpha, beta;                // direction thresholds
     unsigned long long live;           // batched: slots with a nonempty current frontier
+    unsigned long long active;         // batched: slots in use in this pass
     int32_t bwd_level, bwd_last;       // batched reverse pass: level being swept, deepest level
     // Hubs: entries of the level being built are appended at hub_next, with
     // hub_pack = (count << 40) | chunks accumulating; `advance` turns them into
@@ -289,6 +290,7 @@ struct BatchResult {
     int64_t entries = 0;    // (vertex, level) entries
     double sigma_max = 0.0;
     int32_t flagged = 0;    // slots with some sigma > 1e300 or not finite
+    unsigned long long flagged_mask = 0;  // which slots
     int32_t td = 0, bu = 0;
     int32_t graph_launches = 0;
 };

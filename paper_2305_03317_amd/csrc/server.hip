@@ -46,6 +46,7 @@ struct sp_request_s {
     bool finished = false;
     bool cancelled = false;
     sp_status status = SP_OK;
+    std::string error;         // detail of a failure, handed to the waiting thread
     Clock::time_point t_submit, t_done;
     std::condition_variable cv;
 };
@@ -107,6 +108,7 @@ static bool admit(sp_server_s *srv, size_t need, int keep_graph) {
         BatchWorkspace *ws = srv->graphs[victim].idle.back();
         srv->graphs[victim].idle.pop_back();
         srv->admitted -= ws->bytes;
+        srv->stats.workspaces_evicted++;
         batch_ws_destroy(*ws);
         delete ws;
     }
@@ -156,6 +158,7 @@ static void worker_main(sp_server_s *srv) {
                     while (!gs.waiting.empty() && !gs.waiting.front()->in_flight) {
                         sp_request r = gs.waiting.front();
                         gs.waiting.pop_front();
+                        r->error = "a pass's workspace does not fit the server's memory budget";
                         finish_request(srv, r, SP_ERR_OUT_OF_MEMORY);
                     }
                     continue;
@@ -165,6 +168,7 @@ static void worker_main(sp_server_s *srv) {
             }
             srv->admitted += need;
             srv->held++;
+            srv->stats.workspaces_created++;
             srv->stats.admitted_bytes = srv->admitted;
             srv->stats.peak_admitted_bytes = std::max(srv->stats.peak_admitted_bytes, srv->admitted);
             lk.unlock();
@@ -182,6 +186,7 @@ static void worker_main(sp_server_s *srv) {
                 while (!gs.waiting.empty() && !gs.waiting.front()->in_flight) {
                     sp_request r = gs.waiting.front();
                     gs.waiting.pop_front();
+                    r->error = sp_last_error();
                     finish_request(srv, r, st);
                 }
                 srv->work_cv.notify_all();
@@ -230,12 +235,16 @@ static void worker_main(sp_server_s *srv) {
         lk.unlock();
 
         sp_status st = SP_OK;
+        clear_error();
         for (auto &p : parts)
             if (p.first && st >= 0) st = launch_fill_f64(p.r->out_bc, g->n, 0.0, stream);
         BatchResult res;
         if (st >= 0) st = batch_run(g, *ws, srcs.data(), (int32_t)srcs.size(), outs.data(), o, stream, &res);
-        if (st >= 0 && hipStreamSynchronize(stream) != hipSuccess) st = SP_ERR_DEVICE;
-        if (st >= 0 && res.flagged) st = SP_WARN_SIGMA_LARGE;
+        if (st >= 0 && hipStreamSynchronize(stream) != hipSuccess) {
+            set_error("serving pass: stream synchronisation failed");
+            st = SP_ERR_DEVICE;
+        }
+        const std::string err = st < 0 ? std::string(sp_last_error()) : std::string();
 
         lk.lock();
         srv->stats.in_flight--;
@@ -248,12 +257,20 @@ static void worker_main(sp_server_s *srv) {
         }
         gs.idle.push_back(ws);
         gs.last_used = Clock::now();
+        int32_t slot0 = 0;  // the part's slots are [slot0, slot0 + count)
         for (auto &p : parts) {
             sp_request r = p.r;
             r->in_flight = false;
             r->done_sources += p.count;
-            if (st < 0) r->status = st;
-            else if (st > 0) r->status |= st;
+            const unsigned long long mine =
+                (p.count >= 64 ? ~0ull : ((1ull << p.count) - 1ull)) << slot0;
+            slot0 += p.count;
+            if (st < 0) {
+                r->status = st;
+                r->error = err;
+            } else if (r->status >= 0 && (res.flagged_mask & mine)) {
+                r->status |= SP_WARN_SIGMA_LARGE;  // only the request that owns the slot
+            }
             srv->stats.edges_traversed += (int64_t)p.count * (g->nnz / 2);
             if (r->done_sources >= (int32_t)r->sources.size() || r->status < 0) {
                 if (r->status < 0)
@@ -401,6 +418,7 @@ sp_status sp_request_wait(sp_request r, int64_t timeout_us, sp_status *result) {
         }
     }
     if (result) *result = r->cancelled ? SP_ERR_CANCELLED : r->status;
+    if (!r->cancelled && r->status < 0 && !r->error.empty()) set_error("%s", r->error.c_str());
     return SP_OK;
 }
 
@@ -426,6 +444,7 @@ sp_status sp_request_poll(sp_request r, int32_t *done, sp_status *result) {
     const bool f = __atomic_load_n(&r->finished, __ATOMIC_ACQUIRE);
     *done = f ? 1 : 0;
     if (f && result) *result = r->cancelled ? SP_ERR_CANCELLED : r->status;
+    if (f && !r->cancelled && r->status < 0 && !r->error.empty()) set_error("%s", r->error.c_str());
     return SP_OK;
 }
 

@@ -57,7 +57,8 @@ class sp_server_stats(ctypes.Structure):
                 ("rejected", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("slots_used", ctypes.c_int64), ("edges_traversed", ctypes.c_int64),
                 ("admitted_bytes", ctypes.c_size_t), ("peak_admitted_bytes", ctypes.c_size_t),
-                ("queue_depth", ctypes.c_int32), ("in_flight", ctypes.c_int32)]
+                ("queue_depth", ctypes.c_int32), ("in_flight", ctypes.c_int32),
+                ("workspaces_created", ctypes.c_int64), ("workspaces_evicted", ctypes.c_int64)]
 
 
 class sp_kernel_profile(ctypes.Structure):

@@ -124,3 +124,42 @@ def test_cancel_invalid_and_empty(sp, resident):
     for r in (first, last, empty):
         r.release()
     srv.destroy()
+
+
+def test_sigma_warning_goes_only_to_the_request_that_overflowed(sp):
+    """A diamond chain of 1030 diamonds (2^1030 shortest paths from its first
+    vertex, above the 1e300 flag) plus a separate path: two requests that
+    share one pass; only the chain request carries the warning, and the path
+    request's BC matches the oracle."""
+    k = 1030
+    edges = []
+    for i in range(k):
+        a, b, c, d = 3 * i, 3 * i + 1, 3 * i + 2, 3 * i + 3
+        edges += [(a, b), (a, c), (b, d), (c, d)]
+    base = 3 * k + 1
+    edges += [(base + i, base + i + 1) for i in range(9)]
+    e = np.array(edges)
+    n = base + 10
+    rp, ci = graphs.from_edges(n, e[:, 0], e[:, 1])
+    g = sp.sp_graph_upload(rp, ci)
+    frp, fci = graphs.road(256, 0.02, 3)  # a long first pass keeps the one worker busy
+    fg = sp.sp_graph_upload(frp, fci)
+    srv = sp.Server(n_streams=1)
+    gid = srv.add_graph(g)
+    fid = srv.add_graph(fg)
+    filler = srv.submit(fid, graphs.sources(frp, 64, 4))
+    ra = srv.submit(gid, [0])                  # both wait for the filler,
+    rb = srv.submit(gid, [base + 2, base + 7])  # then share one pass
+    assert ra.wait() == sp.SP_WARN_SIGMA_LARGE
+    assert rb.wait() == sp.SP_OK
+    ref = oracle.bc(rp, ci, np.array([base + 2, base + 7], np.int32))
+    got = rb.out_bc[:n].cpu().numpy()
+    assert np.array_equal(got == 0, ref == 0)
+    nz = ref != 0
+    assert np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz])) <= 1e-9
+    assert filler.wait() == sp.SP_OK
+    for r in (ra, rb, filler):
+        r.release()
+    srv.destroy()
+    g.release()
+    fg.release()
