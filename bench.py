@@ -157,7 +157,7 @@ def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
     res = {"graphs": [n for n, _, _ in gs], "requests": len(reqs),
            "mean_sources": round(float(np.mean([len(s) for _, s in reqs])), 1),
            "graph_build_s": round(build_s, 1), "burst": burst,
-           "load50": phase(0.5 * sat), "load80": phase(0.8 * sat)}
+           "load50": phase(0.5 * sat), "load80": phase(0.8 * sat), "load95": phase(0.95 * sat)}
     st = srv.stats()
     res["passes"] = st["passes"]
     res["mean_slots_per_pass"] = round(st["slots_used"] / max(st["passes"], 1), 1)
@@ -174,7 +174,7 @@ def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat-22", choices=sorted(WORKLOADS))
     ap.add_argument("--sources", type=int, default=None, help="override the workload's source count")
@@ -182,8 +182,8 @@ def main():
                     help="fixed batch width (skips the autotuner)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in defaults instead of sp_autotune's choice")
-    ap.add_argument("--per-source-sample", type=int, default=32,
-                    help="sources timed through the per-source path (0 = skip)")
+    ap.add_argument("--per-source-sample", type=int, default=-1,
+                    help="sources timed through the per-source path (-1 = all, 0 = skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="sources timed through the CPU oracle (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=80,
@@ -353,8 +353,8 @@ def main():
 
     # per-source GPU path on a sample of the same sources
     per_source = None
-    if args.per_source_sample > 0:
-        ps_src = src[:args.per_source_sample]
+    if args.per_source_sample != 0:
+        ps_src = src if args.per_source_sample < 0 else src[:args.per_source_sample]
         sp.sp_bc(g, ps_src[:1])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
