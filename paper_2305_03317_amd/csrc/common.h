@@ -87,13 +87,15 @@ sp_stats &tls_stats();
 // ---------------------------------------------------------------------------
 enum : int32_t { MODE_TOPDOWN = 0, MODE_BOTTOMUP = 1 };
 
-// Vertices with more than kHubDeg neighbours ("hubs") are not reduced by one
-// wave: their adjacency is cut into chunks of kHubChunk entries, each chunk is
-// reduced by its own wave into a partial, and the last chunk to finish sums
+// Vertices with more than kHubDeg neighbours ("hubs") are not reduced inside
+// the wave that holds their entry (which would walk a long row while its other
+// entries wait): their adjacency is cut into chunks of kHubChunk entries, each
+// chunk is reduced by its own wave into a partial, and a finishing kernel adds
 // the partials in chunk order.  The result depends only on the degree, not on
-// scheduling.
-constexpr int32_t kHubDeg = 1024;
-constexpr int32_t kHubChunk = 1024;
+// scheduling.  256/512 measured best on RMAT-22 among thresholds 128-1024 and
+// chunks 256-1024.
+constexpr int32_t kHubDeg = 256;
+constexpr int32_t kHubChunk = 512;
 
 // One hub occurrence on a level: vertex, its queue entry, and the range of
 // level-local chunk ids [chunk_base, chunk_base + nchunks).
