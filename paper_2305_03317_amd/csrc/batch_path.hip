@@ -256,7 +256,8 @@ __global__ void k_ms_clear(unsigned long long *seen, unsigned long long *nxt, ui
 __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int32_t *queue,
                           const unsigned long long *qmask, uint32_t *qvb, int32_t n0,
                           unsigned long long *seen, uint4 *front0, double *val, int32_t *level_off,
-                          HubEntry *hub_list, int32_t *hub_off, int32_t *hub_lvl_chunks, int32_t n,
+                          HubEntry *hub_list, int32_t *hub_off, int32_t *hub_lvl_chunks,
+                          int32_t *owner, int32_t *chunk_off, int32_t n,
                           long long nnz, unsigned long long active, double alpha, double beta) {
     __shared__ uint32_t s_vb[kSlots + 1];
     if (threadIdx.x == 0) {
@@ -292,6 +293,7 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
             if (qmask[i] == active) settled += (unsigned long long)d;
             if (d > kHubDeg) {
                 const int32_t k = (d + kHubChunk - 1) / kHubChunk;
+                for (int32_t q = 0; q < k; ++q) owner[nch + q] = nh;  // at most kSlots hubs
                 hub_list[nh++] = HubEntry{v, i, nch, k};
                 nch += k;
             }
@@ -328,6 +330,8 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         hub_off[0] = 0;
         hub_off[1] = nh;
         hub_lvl_chunks[0] = nch;
+        chunk_off[0] = 0;
+        c->chunk_next = nch;
         level_off[0] = 0;
         level_off[1] = n0;
     }
@@ -343,6 +347,8 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
                                                    const unsigned long long *__restrict__ seen,
                                                    unsigned long long *nxt,
                                                    const HubEntry *__restrict__ hub_list,
+                                                   const int32_t *__restrict__ owner,
+                                                   const int32_t *__restrict__ chunk_off,
                                                    long long qcap, unsigned long long *prof) {
     if (c->done || c->mode != MODE_TOPDOWN) return;
     __shared__ int32_t s_beg[BS], s_off[BS], s_scan[BS / kWave + 1];
@@ -396,9 +402,9 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
             __syncthreads();
         }
     } else {
-        const int32_t hlo = c->hub_lo, hhi = c->hub_hi, nch = c->hub_nchunks;
+        const int32_t nch = c->hub_nchunks, obase = chunk_off[c->level];
         for (int32_t k = blockIdx.x; k < nch; k += gridDim.x) {
-            const HubEntry h = hub_list[hub_find(hub_list, hlo, hhi, k)];
+            const HubEntry h = hub_list[owner[obase + k]];
             const unsigned long long fm = qmask[h.entry];
             const int32_t beg = rp[h.v] + (k - h.chunk_base) * kHubChunk;
             const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
@@ -513,13 +519,16 @@ __device__ __forceinline__ T ld_agent(const T *p) {
 // registrations into the next level's hub segment, decide the next
 // direction, or set `done`.
 __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
-                              int32_t *hub_lvl_chunks, long long qcap, long long hub_cap) {
+                              int32_t *hub_lvl_chunks, long long qcap, long long hub_cap,
+                              int32_t *chunk_off, long long owner_cap) {
     if (c->done) return;
     if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
     const int32_t tail = ld_agent(&c->tail_.v);
     const unsigned long long hp = ld_agent(&c->hub_pack_.v);
+    const long long nchk = (long long)(hp & ((1ull << 40) - 1));
     if ((long long)tail > qcap || ld_agent(&c->overflow_.v) ||
-        (long long)c->hub_next + (long long)(hp >> 40) > hub_cap) {
+        (long long)c->hub_next + (long long)(hp >> 40) > hub_cap ||
+        (long long)c->chunk_next + nchk > owner_cap) {
         c->overflow_.v = 1;
         c->done = 1;
         return;
@@ -538,6 +547,8 @@ __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
     c->hub_pack_.v = 0;
     hub_off[nl + 1] = c->hub_hi;
     hub_lvl_chunks[nl] = c->hub_nchunks;
+    chunk_off[nl] = c->chunk_next;  // where this level's registrations put their chunk owners
+    c->chunk_next += c->hub_nchunks;
     c->front_deg = ld_agent(&c->next_deg_.v);
     c->unset_deg -= ld_agent(&c->settled_deg_.v);
     c->next_deg_.v = 0;
@@ -602,7 +613,8 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                                                  HubEntry *hub_list, long long hub_cap,
                                                  long long qcap, int32_t track_deg, int32_t *level_off,
                                                  int32_t *hub_off, int32_t *hub_lvl_chunks,
-                                                 unsigned long long *prof) {
+                                                 int32_t *owner, long long owner_cap,
+                                                 int32_t *chunk_off, unsigned long long *prof) {
     if (c->done) return;
     const unsigned long long active = c->active;
     __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
@@ -665,7 +677,7 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                        }
                        my_flag |= __ballot(mine && sigma_is_large(acc));
                    });
-        if (hub) hub_register(c, hub_list, hub_cap, w, i, deg);
+        if (hub) hub_register(c, hub_list, hub_cap, w, i, deg, owner, owner_cap);
         if (sparse || dense) my_scan += (unsigned long long)deg;  // hubs: k_ms_sigma_hub
         if (valid) {
             qmask[i] = m;
@@ -715,7 +727,7 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
     }
     // the last block to finish closes the level
     if (last_block(c, working_blocks((int64_t)tail - hi, BS)) && threadIdx.x == 0)
-        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap);
+        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap, chunk_off, owner_cap);
 }
 
 
@@ -740,7 +752,7 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
     unsigned long long *qmask, uint32_t *qvb, unsigned long long *seen, int32_t *claim,
     const uint4 *__restrict__ front_cur, uint4 *front_nxt, double *val, long long vcap,
     long long qcap, int32_t *level_off, int32_t *hub_off, int32_t *hub_lvl_chunks, long long hub_cap,
-    unsigned long long *prof) {
+    int32_t *chunk_off, long long owner_cap, unsigned long long *prof) {
     if (c->done) return;
     const unsigned long long active = c->active;
     __shared__ int32_t s_own[kExpandDeg * BS], s_cnt[1], s_scan[BS / kWave + 1];
@@ -877,7 +889,7 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
         block_add_u64<BS>(my_pull, s_red, prof + 3);
     }
     if (last_block(c, working_blocks((int64_t)hi - lo, BS)) && threadIdx.x == 0)
-        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap);
+        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap, chunk_off, owner_cap);
 }
 
 // Hubs, lane = slot: each chunk of kHubChunk adjacency entries is reduced by
@@ -908,11 +920,12 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
                                                      const uint32_t *__restrict__ qvb,
                                                      const uint4 *__restrict__ front_par,
                                                      double *val, const HubEntry *hub_list,
-                                                     unsigned int *hub_cnt, double *partial,
-                                                     unsigned long long *prof) {
+                                                     const int32_t *__restrict__ owner,
+                                                     const int32_t *__restrict__ chunk_off,
+                                                     double *partial, unsigned long long *prof) {
     if (c->done) return;
     __shared__ unsigned long long s_red[1];
-    const int32_t hlo = c->hub_lo, hhi = c->hub_hi, nch = c->hub_nchunks;
+    const int32_t nch = c->hub_nchunks, obase = chunk_off[c->level];
     const uint32_t pl = (uint32_t)c->level - 1;
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
@@ -920,8 +933,7 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
     unsigned long long my_dag = 0, my_edges = 0, my_flag = 0;
     double my_max = 0.0;
     for (int64_t k = wave0; k < nch; k += nwaves) {
-        const int32_t jh = hub_find(hub_list, hlo, hhi, (int32_t)k);
-        const HubEntry h = hub_list[jh];
+        const HubEntry h = hub_list[owner[obase + k]];
         const unsigned long long m = qmask[h.entry];
         const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
@@ -1075,21 +1087,21 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
     const int32_t *__restrict__ hub_lvl_chunks, const int32_t *__restrict__ rp,
     const int32_t *__restrict__ ci, const unsigned long long *__restrict__ qmask,
     const uint4 *f0, const uint4 *f1, const double *val, const HubEntry *hub_list,
-    double *partial, unsigned long long *prof) {
+    const int32_t *__restrict__ owner, const int32_t *__restrict__ chunk_off, double *partial,
+    unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
     const int32_t lvl = c->bwd_level;
     if (lvl < 1) return;
     const uint4 *__restrict__ front_rd = ((lvl + 1) & 1) ? f1 : f0;
-    const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1];
     const int32_t nch = lvl == c->bwd_last ? 0 : hub_lvl_chunks[lvl];  // deepest: no children
+    const int32_t obase = chunk_off[lvl];
     const uint32_t nl = (uint32_t)lvl + 1;
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
     unsigned long long my_edges = 0, my_pairs = 0;
     for (int64_t k = wave0; k < nch; k += nwaves) {
-        const int32_t jh = hub_find(hub_list, hlo, hhi, (int32_t)k);
-        const HubEntry h = hub_list[jh];
+        const HubEntry h = hub_list[owner[obase + k]];
         const unsigned long long m = qmask[h.entry];
         const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
         const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
@@ -1220,6 +1232,8 @@ __global__ void k_ms_extract(const int32_t *__restrict__ queue,
 // Host side
 // ---------------------------------------------------------------------------
 static int64_t hub_capacity(sp_graph g) { return (int64_t)g->n_hubs * kSlots + kSlots; }
+// A hub has at most one entry per slot, so at most kSlots entries per pass.
+static int64_t owner_capacity(sp_graph g) { return g->hub_chunks * kSlots + kSlots; }
 
 static int64_t value_capacity(sp_graph g, int32_t width) {
     return (int64_t)std::max(g->n, 1) * width + kSlots;
@@ -1230,6 +1244,7 @@ size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
     return V * (8 + 8 + 16 + 16) + V * kSlots * 8 + (size_t)value_capacity(g, width) * 8 +
            (size_t)qcap * 16 + (V + 2) * 12 + kSlots * 4 +
            (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
+           (size_t)owner_capacity(g) * 4 + (V + 2) * 4 +
            ((size_t)g->hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
 }
 
@@ -1246,6 +1261,9 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
     }
     ws.level_cap = (int32_t)std::min<int64_t>((int64_t)V + 2, (int64_t)INT32_MAX);
     ws.hub_cap = hub_capacity(g);
+    ws.owner_cap = owner_capacity(g);
+    SP_TRY(dev_alloc((void **)&ws.owner, (size_t)ws.owner_cap * 4));
+    SP_TRY(dev_alloc((void **)&ws.chunk_off, (size_t)ws.level_cap * 4));
     SP_TRY(dev_alloc((void **)&ws.seen, V * 8));
     SP_TRY(dev_alloc((void **)&ws.nxt, V * 8));
     SP_TRY(dev_alloc((void **)&ws.front[0], V * 16));
@@ -1292,6 +1310,8 @@ void batch_ws_destroy(BatchWorkspace &ws) {
     dev_free(ws.hub_off);
     dev_free(ws.hub_lvl_chunks);
     dev_free(ws.hub_list);
+    dev_free(ws.owner);
+    dev_free(ws.chunk_off);
     dev_free(ws.hub_cnt);
     dev_free(ws.partial);
     dev_free(ws.slot_src);
@@ -1335,14 +1355,16 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, (int32_t *)ws.nxt,
                                (const uint4 *)fcur, fnxt, ws.val, (long long)ws.vcap,
                                (long long)ws.qcap, ws.level_off, ws.hub_off, ws.hub_lvl_chunks,
-                               (long long)ws.hub_cap, prof_counters(P_MS_EXPAND));
+                               (long long)ws.hub_cap, ws.chunk_off, (long long)ws.owner_cap,
+                               prof_counters(P_MS_EXPAND));
             continue;
         }
         {
             ProfScope ps(P_MS_TOPDOWN, s);
             hipLaunchKernelGGL(k_ms_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
                                g->row_ptr, g->col_idx, ws.queue, ws.qmask, ws.seen, ws.nxt,
-                               (const HubEntry *)ws.hub_list, (long long)ws.qcap,
+                               (const HubEntry *)ws.hub_list, (const int32_t *)ws.owner,
+                               (const int32_t *)ws.chunk_off, (long long)ws.qcap,
                                prof_counters(P_MS_TOPDOWN));
         }
         if (may_pull) {
@@ -1357,14 +1379,16 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
                                ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
                                (long long)ws.qcap, (int32_t)may_pull, ws.level_off,
-                               ws.hub_off, ws.hub_lvl_chunks, prof_counters(P_MS_SIGMA));
+                               ws.hub_off, ws.hub_lvl_chunks, ws.owner, (long long)ws.owner_cap,
+                               ws.chunk_off, prof_counters(P_MS_SIGMA));
         }
         if (hubs) {
             ProfScope ps(P_MS_SIGMA_HUB, s);
             hipLaunchKernelGGL(k_ms_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s, ws.ctl,
                                g->row_ptr, g->col_idx, (const unsigned long long *)ws.qmask,
                                (const uint32_t *)ws.qvb, (const uint4 *)fcur, ws.val,
-                               (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
+                               (const HubEntry *)ws.hub_list, (const int32_t *)ws.owner,
+                               (const int32_t *)ws.chunk_off, ws.partial,
                                prof_counters(P_MS_SIGMA_HUB));
             // (timed with the chunk kernel)
             hipLaunchKernelGGL(k_ms_sigma_hub_fin, dim3(hub_fin_grid), dim3(256), 0, s, ws.ctl,
@@ -1425,7 +1449,7 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, s, ws.ctl, (const int32_t *)g->row_ptr,
                        (const int32_t *)ws.queue, (const unsigned long long *)ws.qmask, ws.qvb, n0,
                        ws.seen, ws.front[0], ws.val, ws.level_off, ws.hub_list, ws.hub_off,
-                       ws.hub_lvl_chunks, n, (long long)g->nnz, active,
+                       ws.hub_lvl_chunks, ws.owner, ws.chunk_off, n, (long long)g->nnz, active,
                        may_pull ? o.alpha : 0.0, o.beta);  // alpha 0: never switch to bottom-up
     SP_HIP(hipGetLastError());
     const bool capture = o.chunk_levels > 0 && !prof_enabled();  // events need direct launches
@@ -1485,7 +1509,8 @@ static void enqueue_reverse(sp_graph g, BatchWorkspace &ws, int count, int grid_
                                    (const int32_t *)ws.hub_lvl_chunks, g->row_ptr, g->col_idx,
                                    (const unsigned long long *)ws.qmask, (const uint4 *)ws.front[0],
                                    (const uint4 *)ws.front[1], (const double *)ws.val,
-                                   (const HubEntry *)ws.hub_list, ws.partial,
+                                   (const HubEntry *)ws.hub_list, (const int32_t *)ws.owner,
+                                   (const int32_t *)ws.chunk_off, ws.partial,
                                    prof_counters(P_MS_DELTA_HUB));
             }
             hipLaunchKernelGGL(k_ms_delta_hub_fin, dim3(hub_fin_grid), dim3(256), 0, s, ws.ctl,

@@ -132,6 +132,7 @@ struct LevelCtl {
     unsigned long long live;           // batched: slots with a nonempty current frontier
     unsigned long long active;         // batched: slots in use in this pass
     int32_t bwd_level, bwd_last;       // batched reverse pass: level being swept, deepest level
+    int32_t chunk_next;                // batched: first owner-map slot of the level being built
     // Hubs: entries of the level being built are appended at hub_next, with
     // hub_pack = (count << 40) | chunks accumulating; `advance` turns them into
     // the current level's segment [hub_lo, hub_hi) with hub_nchunks chunks.
@@ -250,6 +251,9 @@ struct BatchWorkspace {
     int32_t *slot_src = nullptr;         // device, 64: source vertex of each slot (-1 = empty)
     HubEntry *hub_list = nullptr;        // device, hub_cap entries
     int64_t hub_cap = 0;
+    int32_t *owner = nullptr;            // device, owner_cap: hub list index of each hub chunk,
+    int64_t owner_cap = 0;               //   levels concatenated
+    int32_t *chunk_off = nullptr;        // device, level_cap: first owner slot of each level
     int32_t *hub_off = nullptr;          // device, level_cap: hub segment of each level
     int32_t *hub_lvl_chunks = nullptr;   // device, level_cap
     unsigned int *hub_cnt = nullptr;     // device, n_hubs + 1

@@ -10,14 +10,22 @@ namespace sp {
 
 // Register a hub of the level being built: reserve its chunk ids.
 // `cap` is the list's capacity; an index past it is dropped and reported by
-// `advance` as an overflow.
+// `advance` as an overflow.  With an owner map (batched path), each of the
+// hub's chunks also records the hub's list index at owner[chunk_next + id],
+// so chunk kernels find their hub with one load; `advance` checks owner_cap.
 __device__ __forceinline__ void hub_register(LevelCtl *c, HubEntry *list, long long cap, int32_t v,
-                                             int32_t entry, int32_t deg) {
+                                             int32_t entry, int32_t deg, int32_t *owner = nullptr,
+                                             long long owner_cap = 0) {
     const int32_t nch = (deg + kHubChunk - 1) / kHubChunk;
     const unsigned long long old = atomicAdd(&c->hub_pack_.v, (1ull << 40) | (unsigned long long)nch);
     const int32_t idx = (int32_t)(old >> 40);
     const int32_t base = (int32_t)(old & ((1ull << 40) - 1));
     if ((long long)c->hub_next + idx < cap) list[c->hub_next + idx] = HubEntry{v, entry, base, nch};
+    if (owner)
+        for (int32_t q = 0; q < nch; ++q) {
+            const long long p = (long long)c->chunk_next + base + q;
+            if (p < owner_cap) owner[p] = c->hub_next + idx;
+        }
 }
 
 // The hub whose chunk range holds chunk id k, in segment [lo, hi) sorted by
