@@ -10,6 +10,9 @@ Contents
   centrality in C (``bc_oracle.c``), following the paper's BC specification
   (Appendix, Fig. "BC computation in StarPlat") and the BFS-DAG semantics of
   ``iterateInBFS`` / ``iterateInReverse`` (Section 2.3.2).
+* ``sssp``: single-source shortest paths on a weighted CSR (``sssp_oracle.c``,
+  Dijkstra): the distances the paper's SSSP (Section 2.2, Fig. "SSSP
+  computation in StarPlat"; pull form in the Appendix) converges to.
 * ``csr_from_edges``: the CSR the paper's graph library stores (Section 2.3.1
   "Data Types": offsets plus concatenated neighbour lists), built from an edge
   list with plain numpy set operations.
@@ -28,7 +31,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "bc_oracle.c")
+_SRCS = [os.path.join(_HERE, "bc_oracle.c"), os.path.join(_HERE, "sssp_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -36,12 +39,12 @@ SIGMA_LIMIT = 1e300
 
 
 def build(force: bool = False) -> str:
-    """Compile bc_oracle.c with gcc: -O2, no FP contraction, no fast-math."""
+    """Compile the oracle C sources with gcc: -O2, no FP contraction, no fast-math."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-            "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+            "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -58,6 +61,8 @@ def _load():
         lib.oracle_source_detail.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32,
                                              i32p, f64p, f64p, i32p]
         lib.oracle_source_detail.restype = ctypes.c_int
+        lib.oracle_sssp.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int32, i32p]
+        lib.oracle_sssp.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -106,6 +111,25 @@ def source_detail(row_ptr, col_idx, source: int):
     if rc != 0:
         raise ValueError("oracle_source_detail rejected its input (code %d)" % rc)
     return dist, sigma, delta
+
+
+INF = np.iinfo(np.int32).max  # distance of a vertex no path reaches
+
+
+def sssp(row_ptr, col_idx, weights, source: int):
+    """Shortest-path distances (int32[n]) from `source`; INF where unreached.
+    weights: int32 per CSR entry (aligned with col_idx), non-negative."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx if len(col_idx) else np.zeros(1, np.int32))
+    w, wp = _i32(weights if len(weights) else np.zeros(1, np.int32))
+    n = len(rp) - 1
+    dist = np.empty(max(n, 1), np.int32)
+    rc = lib.oracle_sssp(n, rpp, cip, wp, int(source),
+                         dist.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc != 0:
+        raise ValueError("oracle_sssp rejected its input (code %d)" % rc)
+    return dist[:n]
 
 
 def sigma_flag(sigma_max: float) -> bool:

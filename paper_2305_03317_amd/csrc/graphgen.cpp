@@ -408,4 +408,24 @@ int spg_sources(int32_t n, const int32_t *row_ptr, int32_t count, int32_t min_de
     return SPG_OK;
 }
 
+// Edge weights for the weighted algorithms (SSSP): one int32 per CSR entry,
+// uniform on [lo, hi] (the paper draws weights uniformly from [1, 100] for
+// graphs that have none, Section 5).  The weight of {u, v} is a hash of the
+// seed and the unordered pair, so both stored directions get the same value
+// and the result does not depend on the CSR's entry order.
+int spg_weights(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t lo, int32_t hi,
+                uint64_t seed, int32_t *out) {
+    if (n < 0 || !row_ptr || lo > hi || (n > 0 && row_ptr[n] > 0 && (!col_idx || !out)))
+        return SPG_BAD_ARG;
+    const uint64_t span = (uint64_t)((int64_t)hi - (int64_t)lo + 1);
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+            const uint32_t v = (uint32_t)col_idx[e];
+            const uint64_t a = std::min((uint32_t)u, v), b = std::max((uint32_t)u, v);
+            SplitMix64 sm(seed ^ ((a << 32) | b) * 0xD1B54A32D192ED03ull);
+            out[e] = (int32_t)((int64_t)lo + (int64_t)(sm.next() % span));
+        }
+    return SPG_OK;
+}
+
 }  // extern "C"

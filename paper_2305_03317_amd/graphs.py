@@ -44,6 +44,8 @@ def _load():
         lib.spg_release.restype = None
         lib.spg_sources.argtypes = [ctypes.c_int32, i32p, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_uint64, i32p]
+        lib.spg_weights.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_uint64, i32p]
         _lib = lib
     return _lib
 
@@ -102,6 +104,20 @@ def sources(row_ptr, count: int, seed: int, min_degree: int = 0):
     if rc != 0:
         raise ValueError("not enough candidate sources")
     return out[:count]
+
+
+def weights(row_ptr, col_idx, seed: int, lo: int = 1, hi: int = 100):
+    """int32 weight per CSR entry, uniform on [lo, hi], equal in both directions
+    of an edge (the paper's recipe for graphs without weights, Section 5)."""
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col_idx, np.int32)
+    out = np.empty(max(len(ci), 1), np.int32)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    rc = _load().spg_weights(len(rp) - 1, rp.ctypes.data_as(i32p), ci.ctypes.data_as(i32p), lo, hi, seed,
+                             out.ctypes.data_as(i32p))
+    if rc != 0:
+        raise ValueError("weight generator rejected its arguments (code %d)" % rc)
+    return out[:len(ci)]
 
 
 WORKLOADS = {
