@@ -3,7 +3,8 @@
  * (libsp.so).
  *
  * The library computes Brandes betweenness centrality over a source list on
- * a simple, undirected, unweighted graph held as int32 CSR, on one AMD GPU.
+ * a simple, undirected, unweighted graph held as int32 CSR, on one AMD GPU,
+ * and single-source shortest paths once the graph is given edge weights.
  * The operation is the paper's computeBC (Appendix, Fig. "BC computation in
  * StarPlat"): BC is zeroed, then for every source a level-synchronous
  * breadth-first pass counts shortest paths (sigma[w] += sigma[v] over BFS-DAG
@@ -203,6 +204,81 @@ sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes);
  * zero field.  Output buffers are not touched.  Synchronises the stream. */
 sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_sources,
                       sp_batch_config *out, sp_stream s);
+
+/* ------------------------------------------------------------------------
+ * Single-source shortest paths on a weighted graph (paper Section 2.2,
+ * Fig. "SSSP computation in StarPlat"; the pull form in the Appendix)
+ *
+ * dist[v] is the least total weight of a path from the source to v
+ * (dist[source] = 0; INT32_MAX where no path reaches v).  The paper computes
+ * it by rounds of relaxation: every vertex whose distance dropped in the last
+ * round offers dist + weight to its neighbours through an atomic Min (push),
+ * or every vertex takes the Min over such neighbours (pull), until a round
+ * lowers nothing.  The library runs those rounds on the device, choosing the
+ * direction per round; the result is the shortest-path distance, exact in
+ * int32 whatever the direction or scheduling.
+ * ------------------------------------------------------------------------ */
+
+/* Attach edge weights to an uploaded graph (replacing earlier ones).
+ *   weights  nnz int32 values aligned with the graph's col_idx: weights[e] is
+ *            the weight of CSR entry e.  Each must lie in [0, 2^31 - 2].  The
+ *            two entries of an undirected edge must carry the same weight
+ *            (pull rounds read a vertex's own row as its incoming edges).
+ *   flags    SP_PTR_DEVICE if `weights` is a device pointer (else host);
+ *            SP_VALIDATE to check on the host that the weights are symmetric.
+ *   s        stream used for the copies; the call synchronises it.
+ * The range of every weight is always checked (SP_ERR_INVALID_ARGUMENT).
+ * Without SP_VALIDATE symmetry is trusted; asymmetric weights give distances
+ * that depend on the direction chosen per round.  No sp_sssp call on the
+ * graph may be running.  Adds 8 bytes per CSR entry of device memory (the
+ * adjacency packed with its weights) plus 16 bytes per vertex of degree
+ * above 256. */
+sp_status sp_graph_set_weights(sp_graph g, const int32_t *weights, uint32_t flags, sp_stream s);
+
+/* Direction of the relaxation rounds. */
+#define SP_SSSP_AUTO 0 /* per round: pull when the frontier's adjacency entries
+                          times alpha exceed the graph's (never on graphs whose
+                          rows all hold at most 8 entries) */
+#define SP_SSSP_PUSH 1 /* every round pushes */
+#define SP_SSSP_PULL 2 /* every round pulls */
+
+typedef struct sp_sssp_config {
+    int32_t direction;    /* SP_SSSP_AUTO, SP_SSSP_PUSH or SP_SSSP_PULL */
+    int32_t block_size;   /* threads per workgroup: 128, 256 or 512 (0 = 256) */
+    double alpha;         /* automatic direction threshold, > 0 (0 = 2.0) */
+    int32_t chunk_rounds; /* k > 0: rounds are captured k at a time (rounded up to
+                             even) in a hipGraph and replayed, checking the device
+                             "done" flag after each replay; k < 0: |k| rounds per
+                             check launched directly; 0 = 8.  |k| <= 65536. */
+    int32_t reserved[3];  /* must be zero */
+} sp_sssp_config;
+
+typedef struct sp_sssp_stats {
+    int32_t rounds;         /* relaxation rounds run, the last one lowering nothing */
+    int32_t push_rounds;
+    int32_t pull_rounds;
+    int32_t reached;        /* vertices with a finite distance */
+    double device_ms;       /* HIP-event time from the first kernel to distances ready */
+    int32_t graph_launches; /* hipGraph launches used */
+    int32_t block_size;     /* configuration actually used */
+    double alpha;
+    int32_t direction;
+    int32_t chunk_rounds;
+} sp_sssp_stats;
+
+/* Distances from `source` to every vertex.
+ *   out_dist  device int32[V]: receives the distances (INT32_MAX where
+ *             unreached).  Written only when the call succeeds.
+ *   cfg       may be NULL (all defaults).
+ * Requires weights (sp_graph_set_weights), else SP_ERR_INVALID_ARGUMENT.
+ * A reachable vertex whose distance is INT32_MAX or more makes the call fail
+ * with SP_ERR_NOT_SUPPORTED (the distances do not fit in int32); longer
+ * detours that are not shortest paths do not.  Synchronises the stream. */
+sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_config *cfg,
+                  sp_stream s);
+
+/* Counters of the last sp_sssp call on the calling thread. */
+sp_status sp_sssp_get_last_stats(sp_sssp_stats *out);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support)

@@ -308,6 +308,87 @@ __global__ void k_src_export(int32_t n, const int32_t *dist, const double *sigma
     }
 }
 
+// ---------------------------------------------------------------------------
+// Weighted graphs (SSSP)
+// ---------------------------------------------------------------------------
+static thread_local sp_sssp_stats g_sssp_stats;
+
+// Pack each CSR entry with its weight; count weights outside [0, INT32_MAX - 1]
+// and track the largest.
+__global__ void k_pack_weights(const int32_t *__restrict__ ci, const int32_t *__restrict__ w,
+                               int64_t nnz, int2 *adjw, unsigned int *bad, int *maxw) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned int b = 0;
+    int m = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) {
+        const int32_t x = w[e];
+        if (x < 0 || x == INT32_MAX) ++b;
+        m = max(m, x);
+        adjw[e] = make_int2(ci[e], x);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+    if (b) atomicAdd(bad, b);
+    if (lane_id() == 0 && m > 0) atomicMax(maxw, m);
+}
+
+// Host check (SP_VALIDATE): the entry of v in row u and of u in row v carry
+// the same weight.  Rows must be sorted (binary search).
+static bool weights_symmetric(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *w) {
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const int32_t v = ci[e];
+            const int32_t *b = ci + rp[v], *z = ci + rp[v + 1];
+            const int32_t *f = std::lower_bound(b, z, u);
+            if (f == z || *f != u) {
+                set_error("edge (%d, %d) has no reverse entry (or row %d is unsorted)", u, v, v);
+                return false;
+            }
+            if (w[f - ci] != w[e]) {
+                set_error("edge {%d, %d} has weights %d and %d in its two entries", u, v, w[e], w[f - ci]);
+                return false;
+            }
+        }
+    return true;
+}
+
+static sp_status acquire_sssp_ws(sp_graph g, SsspWorkspace **out) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->sssp_pool.empty()) {
+            *out = g->sssp_pool.back();
+            g->sssp_pool.pop_back();
+            return SP_OK;
+        }
+    }
+    auto *ws = new (std::nothrow) SsspWorkspace;
+    if (!ws) return SP_ERR_OUT_OF_MEMORY;
+    sp_status st = sssp_ws_create(g, *ws);
+    if (st < 0) {
+        sssp_ws_destroy(*ws);
+        delete ws;
+        return st;
+    }
+    *out = ws;
+    return SP_OK;
+}
+
+static void release_sssp_ws(sp_graph g, SsspWorkspace *ws) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->sssp_pool.push_back(ws);
+}
+
+static void free_weights(sp_graph g) {
+    dev_free(g->adjw);
+    dev_free(g->hub_static);
+    dev_free(g->owner_static);
+    g->adjw = nullptr;
+    g->hub_static = nullptr;
+    g->owner_static = nullptr;
+    g->max_weight = 0;
+    g->bytes -= g->weight_bytes;
+    g->weight_bytes = 0;
+}
+
 }  // namespace sp
 
 using namespace sp;
@@ -454,6 +535,11 @@ sp_status sp_graph_release(sp_graph g) {
         batch_ws_destroy(*ws);
         delete ws;
     }
+    for (auto *ws : g->sssp_pool) {
+        sssp_ws_destroy(*ws);
+        delete ws;
+    }
+    free_weights(g);
     dev_free(g->row_ptr);
     dev_free(g->col_idx);
     delete g;
@@ -740,6 +826,170 @@ sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes) 
         return SP_ERR_INVALID_ARGUMENT;
     }
     *bytes = batch_ws_bytes(g, initial_qcap(g->n, batch_width), batch_width);
+    return SP_OK;
+}
+
+sp_status sp_graph_set_weights(sp_graph g, const int32_t *weights, uint32_t flags, sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || (g->nnz > 0 && !weights) || (flags & ~(SP_PTR_DEVICE | SP_VALIDATE))) {
+        set_error("sp_graph_set_weights: bad arguments");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    const bool on_dev = flags & SP_PTR_DEVICE;
+    const int64_t nnz = g->nnz;
+    if (flags & SP_VALIDATE) {
+        std::vector<int32_t> hr((size_t)g->n + 1), hc((size_t)nnz), hw;
+        const int32_t *w = weights;
+        SP_HIP(hipMemcpyAsync(hr.data(), g->row_ptr, hr.size() * 4, hipMemcpyDeviceToHost, st));
+        if (nnz) SP_HIP(hipMemcpyAsync(hc.data(), g->col_idx, hc.size() * 4, hipMemcpyDeviceToHost, st));
+        if (on_dev && nnz) {
+            hw.resize((size_t)nnz);
+            SP_HIP(hipMemcpyAsync(hw.data(), weights, hw.size() * 4, hipMemcpyDeviceToHost, st));
+            w = hw.data();
+        }
+        SP_HIP(hipStreamSynchronize(st));
+        if (!weights_symmetric(g->n, hr.data(), hc.data(), w)) return SP_ERR_INVALID_ARGUMENT;
+    }
+    // Hubs of the graph with their chunk ranges, in vertex order, and the hub
+    // of every chunk (pull rounds).
+    std::vector<HubEntry> hubs;
+    std::vector<int32_t> owners;
+    for (int32_t v = 0; v < g->n; ++v)
+        if (g->host_deg[v] > kHubDeg) {
+            const int32_t nch = (g->host_deg[v] + kHubChunk - 1) / kHubChunk;
+            hubs.push_back(HubEntry{v, 0, (int32_t)owners.size(), nch});
+            owners.insert(owners.end(), (size_t)nch, (int32_t)hubs.size() - 1);
+        }
+    int2 *adjw = nullptr;
+    HubEntry *hub_static = nullptr;
+    int32_t *owner_static = nullptr;
+    int32_t *wdev = nullptr;
+    unsigned int *bad = nullptr;  // bad[0]: count, bad[1]: largest weight (as int)
+    auto cleanup = [&](sp_status code) {
+        dev_free(adjw);
+        dev_free(hub_static);
+        dev_free(owner_static);
+        dev_free(wdev);
+        dev_free(bad);
+        return code;
+    };
+    const size_t adj_bytes = sizeof(int2) * (size_t)std::max<int64_t>(nnz, 1);
+    const size_t hub_bytes = sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1) +
+                             sizeof(int32_t) * std::max<size_t>(owners.size(), 1);
+    sp_status rc = dev_alloc((void **)&adjw, adj_bytes);
+    if (rc == SP_OK) rc = dev_alloc((void **)&hub_static, sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1));
+    if (rc == SP_OK) rc = dev_alloc((void **)&owner_static, sizeof(int32_t) * std::max<size_t>(owners.size(), 1));
+    if (rc == SP_OK) rc = dev_alloc((void **)&bad, 8);
+    if (rc == SP_OK && !on_dev && nnz) rc = dev_alloc((void **)&wdev, (size_t)nnz * 4);
+    if (rc != SP_OK) return cleanup(rc);
+    unsigned int h_bad[2] = {0, 0};
+    hipError_t e = hipMemsetAsync(bad, 0, 8, st);
+    if (e == hipSuccess && wdev) e = hipMemcpyAsync(wdev, weights, (size_t)nnz * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !hubs.empty())
+        e = hipMemcpyAsync(hub_static, hubs.data(), hubs.size() * sizeof(HubEntry), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !owners.empty())
+        e = hipMemcpyAsync(owner_static, owners.data(), owners.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && nnz) {
+        hipLaunchKernelGGL(k_pack_weights, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st,
+                           (const int32_t *)g->col_idx, (const int32_t *)(wdev ? wdev : weights), nnz,
+                           adjw, bad, (int *)(bad + 1));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h_bad, bad, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error("weight upload failed: %s", hipGetErrorString(e));
+        return cleanup(SP_ERR_DEVICE);
+    }
+    if (h_bad[0]) {
+        set_error("%u weights lie outside [0, 2^31 - 2]", h_bad[0]);
+        return cleanup(SP_ERR_INVALID_ARGUMENT);
+    }
+    dev_free(wdev);
+    dev_free(bad);
+    wdev = nullptr;
+    bad = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        free_weights(g);
+        g->adjw = adjw;
+        g->hub_static = hub_static;
+        g->owner_static = owner_static;
+        g->max_weight = (int32_t)h_bad[1];
+        g->weight_bytes = adj_bytes + hub_bytes;
+        g->bytes += g->weight_bytes;
+    }
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_config *cfg,
+                  sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || !out_dist || source < 0 || source >= g->n) {
+        set_error("sp_sssp: null graph/output or source out of range");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    if (!g->adjw) {
+        set_error("sp_sssp: the graph has no weights (sp_graph_set_weights)");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    SsspOpts o;
+    if (cfg) {
+        const bool bad = cfg->direction < SP_SSSP_AUTO || cfg->direction > SP_SSSP_PULL ||
+                         (cfg->block_size != 0 && cfg->block_size != 128 && cfg->block_size != 256 &&
+                          cfg->block_size != 512) ||
+                         !(cfg->alpha >= 0.0) || std::isinf(cfg->alpha) ||
+                         std::abs((int64_t)cfg->chunk_rounds) > 65536 || cfg->reserved[0] ||
+                         cfg->reserved[1] || cfg->reserved[2];
+        if (bad) {
+            set_error("sp_sssp: invalid configuration");
+            return SP_ERR_INVALID_ARGUMENT;
+        }
+        o.forced = cfg->direction == SP_SSSP_PUSH ? SSSP_PUSH : cfg->direction == SP_SSSP_PULL ? SSSP_PULL : -1;
+        if (cfg->block_size) o.block = cfg->block_size;
+        if (cfg->alpha > 0) o.alpha = cfg->alpha;
+        if (cfg->chunk_rounds) o.chunk_rounds = cfg->chunk_rounds;
+    }
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    SsspWorkspace *ws = nullptr;
+    SP_TRY(acquire_sssp_ws(g, &ws));
+    struct Rel {
+        sp_graph g;
+        SsspWorkspace *ws;
+        ~Rel() { release_sssp_ws(g, ws); }
+    } rel{g, ws};
+    SsspResult r;
+    SP_HIP(hipEventRecord(ws->ev0, st));
+    SP_TRY(sssp_run(g, *ws, source, out_dist, o, st, &r));
+    SP_HIP(hipEventRecord(ws->ev1, st));
+    SP_HIP(hipEventSynchronize(ws->ev1));
+    float ms = 0.f;
+    SP_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+    sp_sssp_stats &t = g_sssp_stats;
+    t = sp_sssp_stats{};
+    t.rounds = r.rounds;
+    t.push_rounds = r.push_rounds;
+    t.pull_rounds = r.pull_rounds;
+    t.reached = r.reached;
+    t.device_ms = ms;
+    t.graph_launches = r.graph_launches;
+    t.block_size = o.block;
+    t.alpha = o.alpha;
+    t.direction = o.forced == SSSP_PUSH ? SP_SSSP_PUSH : o.forced == SSSP_PULL ? SP_SSSP_PULL : SP_SSSP_AUTO;
+    t.chunk_rounds = o.chunk_rounds;
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_sssp_get_last_stats(sp_sssp_stats *out) {
+    if (!out) return SP_ERR_INVALID_ARGUMENT;
+    *out = g_sssp_stats;
     return SP_OK;
 }
 

@@ -40,6 +40,7 @@
 //                 whose source is the vertex itself.
 #include "common.h"
 #include "devutil.h"
+#include "capture.h"
 #include "levels.h"
 
 namespace sp {
@@ -508,13 +509,6 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
-// Coherent read of a counter other blocks updated with device-scope atomics
-// (relaxed: no cache invalidation is needed for the counters themselves).
-template <class T>
-__device__ __forceinline__ T ld_agent(const T *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // End of a forward level (one thread): close the new frontier, turn the hub
 // registrations into the next level's hub segment, decide the next
 // direction, or set `done`.
@@ -564,37 +558,6 @@ __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
     } else {
         if ((double)nf * c->beta < (double)c->n_vertices) c->mode = MODE_TOPDOWN;
     }
-}
-
-// True in exactly one block: the last of the first `nb` blocks (those that
-// had work; blockIdx.x < nb) to get here, or block 0 when nb is 0.  Every
-// thread of a block calls it after the block's last atomic update of the
-// control block; blocks without work return false at once, so only working
-// blocks touch the counter, which is left at zero for the next kernel.  The
-// chosen block reads only counters updated with device-scope atomics, so no
-// cache write-back is needed: each wave waits until its own atomics are
-// acknowledged (a barrier alone does not wait for them), then one thread
-// counts the block.
-__device__ __forceinline__ bool last_block(LevelCtl *c, int nb) {
-    __shared__ int s_last;
-    if (nb <= 0) return blockIdx.x == 0;
-    if ((int)blockIdx.x >= nb) return false;
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int prev = atomicAdd(&c->blocks_done_.v, 1);
-        s_last = prev == nb - 1;
-        if (s_last) atomicExch(&c->blocks_done_.v, 0);
-    }
-    __syncthreads();
-    return s_last != 0;
-}
-
-// Blocks of a grid-stride loop over `items` in steps of `per_block` that get
-// at least one item.
-__device__ __forceinline__ int working_blocks(int64_t items, int per_block) {
-    if (items <= 0) return 0;
-    return (int)min((int64_t)gridDim.x, (items + per_block - 1) / per_block);
 }
 
 // Path counts of the new entries [hi, tail).  Wave takes 64 entries, gives
@@ -1405,29 +1368,7 @@ template <class Enqueue>
 static sp_status replay_chunk(BatchWorkspace &ws, CapturedChunk &slot,
                               const std::array<long long, 12> &key, Enqueue enqueue,
                               hipStream_t s) {
-    if (!slot.exec || slot.key != key) {
-        if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
-        slot.exec = nullptr;
-        if (!ws.cap_stream) SP_HIP(hipStreamCreateWithFlags(&ws.cap_stream, hipStreamNonBlocking));
-        SP_HIP(hipStreamBeginCapture(ws.cap_stream, hipStreamCaptureModeThreadLocal));
-        enqueue(ws.cap_stream);
-        const hipError_t el = hipGetLastError();
-        hipGraph_t graph = nullptr;
-        const hipError_t ec = hipStreamEndCapture(ws.cap_stream, &graph);
-        hipError_t ei = hipSuccess;
-        if (el == hipSuccess && ec == hipSuccess)
-            ei = hipGraphInstantiate(&slot.exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (el != hipSuccess || ec != hipSuccess || ei != hipSuccess) {
-            slot.exec = nullptr;
-            set_error("capturing a level chunk failed: %s",
-                      hipGetErrorString(el != hipSuccess ? el : ec != hipSuccess ? ec : ei));
-            return SP_ERR_DEVICE;
-        }
-        slot.key = key;
-    }
-    SP_HIP(hipGraphLaunch(slot.exec, s));
-    return SP_OK;
+    return replay_captured(&ws.cap_stream, slot, key, enqueue, s);
 }
 
 // Forward levels.  With capture on (chunk_levels > 0) and kernel profiling

@@ -48,6 +48,8 @@ void dev_free(void *p);
 // ---------------------------------------------------------------------------
 struct BatchWorkspace;
 struct SourceWorkspace;
+struct SsspWorkspace;
+struct HubEntry;
 
 struct TuneEntry {
     bool valid = false;
@@ -73,6 +75,15 @@ struct sp_graph_s {
     sp::TuneEntry tuned;
     std::vector<sp::SourceWorkspace *> src_pool;
     std::vector<sp::BatchWorkspace *> batch_pool;
+    // Edge weights (sp_graph_set_weights), null until set: the adjacency
+    // packed as {neighbour, weight} per CSR entry, so one 8-byte load gives
+    // both, and every hub with its chunk range for the pull rounds.
+    int2 *adjw = nullptr;            // device, nnz (>= 1 element allocated)
+    sp::HubEntry *hub_static = nullptr;  // device, n_hubs (>= 1): in vertex order
+    int32_t *owner_static = nullptr;     // device, hub_chunks (>= 1): hub of each chunk
+    int32_t max_weight = 0;
+    size_t weight_bytes = 0;
+    std::vector<sp::SsspWorkspace *> sssp_pool;
 };
 
 namespace sp {
@@ -158,7 +169,7 @@ struct LevelCtl {
 enum ProfKind : int {
     P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
     P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_EXPAND, P_MS_DELTA, P_MS_DELTA_HUB,
-    P_MS_BC,
+    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL,
     P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
@@ -304,6 +315,76 @@ sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t
                     double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
                     BatchResult *res, const BatchExtract *ex = nullptr);
 
+
+// ---------------------------------------------------------------------------
+// Single-source shortest paths (sssp_path.hip)
+// ---------------------------------------------------------------------------
+enum : int32_t { SSSP_PUSH = 0, SSSP_PULL = 1 };
+
+// Round-loop control block of one SSSP run (device memory).  Round r expands
+// the frontier: the vertices whose distance dropped in round r - 1 (the
+// source in round 0).  They sit in queue[r & 1]; the hubs among them in
+// hubs[r & 1], their chunks' owners in owner[r & 1].  The last working block
+// of a round's kernel closes the round.
+struct SsspCtl {
+    // Everything a block needs to decide whether and how it takes part in a
+    // round, written by the closing block in one 64-bit store and read by
+    // every block in one 64-bit load, so no block sees half of a round's
+    // state: bits 0-30 frontier size, 31-54 its hubs' chunk count, 55 round
+    // parity, 56 pull round, 57 done.
+    unsigned long long state;
+    int32_t round;       // round being run (read by the round's working blocks)
+    int32_t done;        // host mirror of the done bit
+    int32_t n_vertices;
+    int32_t forced;      // -1: choose per round; else the mode of every round
+    int32_t push_rounds, pull_rounds;
+    int32_t static_chunks;  // chunks of every hub of the graph (pull rounds)
+    long long nnz;
+    double alpha;        // a round pulls when its frontier's entries * alpha > nnz
+    HotI32 tail_;        // entries of the next frontier
+    HotI32 overflow_;    // a candidate distance reached INT32_MAX (checked after the rounds)
+    HotI32 capacity_;    // 1: a queue, hub list or owner map would have overflowed (never
+                         //   expected: a vertex joins a frontier at most once per round);
+                         // 2 (after the rounds): a distance does not fit in int32
+    HotU64 next_deg_;    // adjacency entries of the next frontier
+    HotU64 hub_pack_;    // next frontier's hubs: (count << 40) | chunks
+    HotI32 blocks_done_; // working blocks of the current kernel that finished
+    HotU64 reached_;     // export: vertices with a finite distance
+};
+
+struct SsspWorkspace {
+    int device = -1;
+    int32_t n = 0;
+    int2 *ds = nullptr;              // V: {distance, stamp}; stamp = last round whose
+                                     //   frontier holds the vertex (-1: never)
+    int32_t *queue[2] = {nullptr, nullptr};  // V each: frontier by round parity
+    HubEntry *hubs[2] = {nullptr, nullptr};  // n_hubs + 1 each: frontier hubs by parity
+    int32_t *owner[2] = {nullptr, nullptr};  // hub_chunks + 1 each: hub index of each chunk
+    SsspCtl *ctl = nullptr;
+    SsspCtl *ctl_host = nullptr;     // pinned mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap_stream = nullptr;
+    CapturedChunk rounds_short, rounds_long;
+};
+sp_status sssp_ws_create(sp_graph g, SsspWorkspace &ws);
+void sssp_ws_destroy(SsspWorkspace &ws);
+
+struct SsspOpts {
+    int forced = -1;       // -1 auto, else SSSP_PUSH / SSSP_PULL
+    double alpha = 2.0;
+    int block = 256;
+    int chunk_rounds = 8;
+};
+struct SsspResult {
+    int32_t rounds = 0, push_rounds = 0, pull_rounds = 0;
+    int32_t reached = 0;
+    int32_t graph_launches = 0;
+    bool overflow = false;   // some distance does not fit in int32 (nothing exported)
+};
+// One source; writes the distance of every vertex (INT32_MAX where unreached)
+// to out_dist unless the result overflows.
+sp_status sssp_run(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t *out_dist, const SsspOpts &o,
+                   hipStream_t s, SsspResult *res);
 
 // Workspace pools and configuration shared by the entry points and the server.
 int64_t initial_qcap(int32_t n, int32_t width);

@@ -1,5 +1,6 @@
-// Device helpers shared by the per-source and batched level kernels: hub
-// registration on the level being built, the chunk-id lookup, and the
+// Device helpers shared by the level and round kernels: hub registration on
+// the level being built, the chunk-id lookup, coherent counter reads, the
+// last-block election that ends a level inside its last kernel, and the
 // profiling counter flush.
 #pragma once
 
@@ -37,6 +38,50 @@ __device__ __forceinline__ int32_t hub_find(const HubEntry *list, int32_t lo, in
         if (list[mid].chunk_base <= k) a = mid; else z = mid - 1;
     }
     return a;
+}
+
+// Coherent read of a counter other blocks updated with device-scope atomics
+// (relaxed: no cache invalidation is needed for the counters themselves).
+template <class T>
+__device__ __forceinline__ T ld_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True in exactly one of the `nb` blocks that call it with working = true
+// (a block-uniform flag): the last of them to get here.  Every thread of a
+// block calls it after the block's last atomic update of the control block;
+// blocks without work return false at once, so only working blocks touch the
+// counter, which is left at zero for the next kernel.  The chosen block reads
+// only counters updated with device-scope atomics, so no cache write-back is
+// needed: each wave waits until its own atomics are acknowledged (a barrier
+// alone does not wait for them), then one thread counts the block.
+__device__ __forceinline__ bool last_working_block(int32_t *blocks_done, bool working, int nb) {
+    __shared__ int s_last;
+    if (!working) return false;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int prev = atomicAdd(blocks_done, 1);
+        s_last = prev == nb - 1;
+        if (s_last) atomicExch(blocks_done, 0);
+    }
+    __syncthreads();
+    return s_last != 0;
+}
+
+// One-dimensional grids whose working blocks are the first `nb`
+// (blockIdx.x < nb); block 0 when nb is 0.
+template <class Ctl>
+__device__ __forceinline__ bool last_block(Ctl *c, int nb) {
+    if (nb <= 0) return blockIdx.x == 0;
+    return last_working_block(&c->blocks_done_.v, (int)blockIdx.x < nb, nb);
+}
+
+// Blocks of a grid-stride loop over `items` in steps of `per_block` that get
+// at least one item.
+__device__ __forceinline__ int working_blocks(int64_t items, int per_block) {
+    if (items <= 0) return 0;
+    return (int)min((int64_t)gridDim.x, (items + per_block - 1) / per_block);
 }
 
 template <int BS>

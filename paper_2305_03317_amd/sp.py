@@ -27,6 +27,9 @@ SP_ERR_TIMEOUT = -6
 SP_ERR_CANCELLED = -7
 SP_PTR_DEVICE = 1
 SP_VALIDATE = 2
+SP_SSSP_AUTO = 0
+SP_SSSP_PUSH = 1
+SP_SSSP_PULL = 2
 
 
 class sp_batch_config(ctypes.Structure):
@@ -44,6 +47,20 @@ class sp_stats(ctypes.Structure):
                 ("batch_width", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("chunk_levels", ctypes.c_int32), ("graph_launches", ctypes.c_int32)]
+
+
+class sp_sssp_config(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("block_size", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("chunk_rounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class sp_sssp_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("push_rounds", ctypes.c_int32),
+                ("pull_rounds", ctypes.c_int32), ("reached", ctypes.c_int32),
+                ("device_ms", ctypes.c_double), ("graph_launches", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("direction", ctypes.c_int32), ("chunk_rounds", ctypes.c_int32)]
 
 
 class sp_server_config(ctypes.Structure):
@@ -93,6 +110,9 @@ SIGNATURES = [
                               ctypes.POINTER(sp_batch_config), _VP]),
     ("sp_bc_workspace_bytes", _ST, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("sp_autotune", _ST, [_VP, _I32P, ctypes.c_int32, ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_graph_set_weights", _ST, [_VP, _VP, ctypes.c_uint32, _VP]),
+    ("sp_sssp", _ST, [_VP, ctypes.c_int32, _VP, ctypes.POINTER(sp_sssp_config), _VP]),
+    ("sp_sssp_get_last_stats", _ST, [ctypes.POINTER(sp_sssp_stats)]),
     ("sp_profile_enable", _ST, [ctypes.c_int32]),
     ("sp_profile_read", _ST, [ctypes.POINTER(sp_kernel_profile), ctypes.c_int32, _I32P]),
     ("sp_server_create", _ST, [ctypes.POINTER(sp_server_config), ctypes.POINTER(_VP)]),
@@ -304,6 +324,53 @@ def sp_batch_levels(g: Graph, sources, with_sigma=True, with_delta=True, config=
                                       _config(config), _stream(stream)), "sp_batch_levels")
     cut = lambda t: None if t is None else t[:, :g.n]
     return dist[:, :g.n], cut(sigma), cut(delta), st
+
+
+def sp_graph_set_weights(g: Graph, weights, validate: bool = False, stream=None):
+    """Attach int32 edge weights (one per CSR entry; numpy / host or CUDA tensor)."""
+    torch = _torch()
+    flags = SP_VALIDATE if validate else 0
+    if isinstance(weights, torch.Tensor) and weights.is_cuda:
+        w = weights.to(torch.int32).contiguous()
+        ptr = w.data_ptr()
+        flags |= SP_PTR_DEVICE
+    else:
+        w = np.ascontiguousarray(np.asarray(weights), dtype=np.int32)
+        if w.size == 0:
+            w = np.zeros(1, np.int32)
+        ptr = w.ctypes.data
+    if (w.numel() if hasattr(w, "numel") else w.size) < g.nnz:
+        raise ValueError("need one weight per CSR entry (%d)" % g.nnz)
+    _check(lib().sp_graph_set_weights(g.handle, ptr, flags, _stream(stream)), "sp_graph_set_weights")
+
+
+def _sssp_config(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, sp_sssp_config):
+        return ctypes.byref(cfg)
+    c = sp_sssp_config()
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    return ctypes.byref(c)
+
+
+def sp_sssp(g: Graph, source: int, out_dist=None, config=None, stream=None):
+    """int32 distances from `source` (INT32_MAX where unreached), a CUDA tensor [V]."""
+    torch = _torch()
+    if out_dist is None:
+        out_dist = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+    assert out_dist.is_cuda and out_dist.dtype == torch.int32 and out_dist.is_contiguous()
+    assert out_dist.numel() >= g.n
+    _check(lib().sp_sssp(g.handle, int(source), out_dist.data_ptr(), _sssp_config(config),
+                         _stream(stream)), "sp_sssp")
+    return out_dist[:g.n]
+
+
+def sp_sssp_get_last_stats() -> dict:
+    s = sp_sssp_stats()
+    _check(lib().sp_sssp_get_last_stats(ctypes.byref(s)), "sp_sssp_get_last_stats")
+    return _struct_dict(s)
 
 
 def sp_bc_workspace_bytes(g: Graph, batch_width: int) -> int:

@@ -106,3 +106,30 @@ def brute_bc(adj, sources, layered=False):
             if v != s:
                 bc[v] += delta[v]
     return bc
+
+
+def sssp_invariants(rp, ci, w, s, d, inf=2**31 - 1):
+    """Properties that make d the shortest-path distances from s, at any size
+    (vectorised): d[s] = 0; no edge out of a reached vertex can lower its
+    target; every reached vertex but s has a neighbour with d[u] + w = d[v]
+    (so d[v] is the length of a real path, by induction on d); a reached
+    vertex has only reached neighbours.  With positive weights these force d
+    to equal the true distances: the first two bound d from above by
+    induction along a shortest path, the third from below by induction on d
+    (with zero weights a zero cycle could hold a too-small value up)."""
+    import numpy as np
+    n = len(rp) - 1
+    d = np.asarray(d, np.int64)
+    assert d[s] == 0, "source distance %d" % d[s]
+    u = np.repeat(np.arange(n), np.diff(np.asarray(rp)))
+    v = np.asarray(ci, np.int64)
+    ww = np.asarray(w, np.int64)
+    ru = d[u] != inf
+    assert np.all(d[v][ru] != inf), "a reached vertex has an unreached neighbour"
+    assert np.all(d[v][ru] <= d[u][ru] + ww[ru]), "an edge can still be relaxed"
+    tight = ru & (d[u] + ww == d[v])
+    has = np.zeros(n, bool)
+    has[v[tight]] = True
+    reached = d != inf
+    reached[s] = False
+    assert np.all(has[reached]), "a reached vertex has no tight predecessor"

@@ -50,7 +50,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     import subprocess
     structs = {"sp_batch_config": sp.sp_batch_config, "sp_stats": sp.sp_stats,
                "sp_server_config": sp.sp_server_config, "sp_server_stats": sp.sp_server_stats,
-               "sp_kernel_profile": sp.sp_kernel_profile}
+               "sp_kernel_profile": sp.sp_kernel_profile, "sp_sssp_config": sp.sp_sssp_config,
+               "sp_sssp_stats": sp.sp_sssp_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
@@ -121,6 +122,14 @@ def test_server_calls_reject_bad_arguments_on_the_host():
     assert L.sp_profile_read(None, 4, ctypes.byref(n)) == sp.SP_ERR_INVALID_ARGUMENT
     assert L.sp_profile_enable(0) == sp.SP_OK
     assert L.sp_profile_enable(8) == sp.SP_ERR_INVALID_ARGUMENT
+
+
+def test_sssp_calls_reject_bad_arguments_on_the_host():
+    L = sp.lib()
+    assert L.sp_graph_set_weights(None, None, 0, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_sssp(None, 0, None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_sssp_get_last_stats(None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert {"SP_SSSP_AUTO", "SP_SSSP_PUSH", "SP_SSSP_PULL"} <= set(dir(sp))
 
 
 def test_header_constants_match_binding():

@@ -95,24 +95,7 @@ def bellman_ford_fixed_point(rp, ci, w, s):
 
 
 def check_invariants(rp, ci, w, s, d):
-    n = len(rp) - 1
-    d = np.asarray(d, np.int64)
-    assert d[s] == 0
-    u = np.repeat(np.arange(n), np.diff(rp))
-    v = ci.astype(np.int64)
-    ww = w.astype(np.int64)
-    reached_u = d[u] != INF
-    # no edge relaxes further
-    assert np.all(d[v][reached_u] <= d[u][reached_u] + ww[reached_u])
-    # unreached vertices have no reached neighbour
-    assert np.all(d[v][reached_u] != INF)
-    # every reached vertex but the source has a tight predecessor
-    tight = reached_u & (d[u] + ww == d[v])
-    has = np.zeros(n, bool)
-    has[v[tight]] = True
-    reached = d != INF
-    reached[s] = False
-    assert np.all(has[reached])
+    brute.sssp_invariants(rp, ci, w, s, d, INF)
 
 
 # --------------------------------------------------------------------------
