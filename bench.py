@@ -20,8 +20,10 @@ average launch time against 8 TB/s; traffic from the committed rocprofv3
 counter summary while the kernel sources are unchanged), forward_pass.
 Also: the per-source GPU path on a sample of the same sources (the batched
 vs per-source ratio), the CPU oracle on a bounded sample (cpu_baseline, which
-doubles as a parity check of this run), and the serving workload (eight
-resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS).
+doubles as a parity check of this run), the serving workload (eight
+resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS),
+and single-source shortest paths on the RMAT and road graphs with the paper's
+uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle).
 
 Prints one JSON line.
 """
@@ -64,6 +66,11 @@ BYTE_MODEL = {
     "src_sigma": dict(items=20, edges=8, pairs=8),
     "src_sigma_hub": dict(edges=8, pairs=8),
     "src_delta": dict(items=44, edges=8, pairs=16),
+    # SSSP rounds: items = frontier vertices (push: queue entry, row offsets,
+    # own distance) or all vertices (pull: row offsets), edges = adjacency
+    # entries (packed {neighbour, weight} plus the neighbour's {dist, stamp})
+    "sssp_push": dict(items=20, edges=16),
+    "sssp_pull": dict(items=8, edges=16),
 }
 FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_expand")
 
@@ -87,6 +94,78 @@ def load_traffic(workload):
         return None
     doc["path"] = os.path.relpath(path, ROOT)
     return doc
+
+
+def sssp_benchmark(sp, torch, workload, n_sources):
+    """Single-source shortest paths on a benchmark graph with the paper's
+    synthetic weights (uniform on [1, 100], Section 5), one source at a time:
+    wall time per source (distances in HBM when the call returns), then the
+    same sources with kernel events, then once with work counters; the
+    oracle's Dijkstra on the first source is the CPU baseline and a parity
+    check."""
+    import numpy as np
+    import oracle
+    from paper_2305_03317_amd import graphs
+    k = WORKLOADS[workload]
+    rp, ci, src, spec = graphs.workload(k)
+    w = graphs.weights(rp, ci, 3000 + k)
+    m = len(ci) // 2
+    g = sp.sp_graph_upload(rp, ci)
+    sp.sp_graph_set_weights(g, w)
+    out = torch.empty(len(rp) - 1, dtype=torch.int32, device="cuda")
+    srcs = [int(x) for x in src[:n_sources]]
+    sp.sp_sssp(g, srcs[0], out)  # warm: workspace and captured round chunks
+    times, rounds = [], []
+    for s in srcs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp.sp_sssp(g, s, out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        rounds.append(sp.sp_sssp_get_last_stats()["rounds"])
+        print("sssp %s source %d: %.2f ms, %d rounds" % (workload, s, times[-1] * 1e3, rounds[-1]),
+              file=sys.stderr, flush=True)
+    per_s = float(np.mean(times))
+    sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
+    for s in srcs:
+        sp.sp_sssp(g, s, out)
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
+    for s in srcs:
+        sp.sp_sssp(g, s, out)
+    counted = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    kernels = {}
+    for kname, p in prof.items():
+        c = counted.get(kname, {})
+        launches = max(p["launches"], 1)
+        alg = algorithmic_bytes(kname, c) * (p["launches"] / max(c.get("launches", 1), 1))
+        kernels[kname] = {"launches": p["launches"], "ms_per_source": round(p["total_ms"] / len(srcs), 3),
+                          "avg_launch_ms": round(p["total_ms"] / launches, 4),
+                          "edges_per_source": int(c.get("edges", 0) / len(srcs)),
+                          "GBps_algorithmic": round(alg / max(p["total_ms"], 1e-9) / 1e6, 1)}
+    dom = max(kernels.items(), key=lambda kv: kv[1]["ms_per_source"]) if kernels else None
+    roofline = None
+    if dom:
+        achieved = dom[1]["GBps_algorithmic"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
+                    "avg_launch_ms": dom[1]["avg_launch_ms"]}
+    t0 = time.perf_counter()
+    ref = oracle.sssp(rp, ci, w, srcs[0])
+    cpu_s = time.perf_counter() - t0
+    got = sp.sp_sssp(g, srcs[0], out).cpu().numpy()
+    g.release()
+    edges_scanned = sum(v["edges_per_source"] for v in kernels.values())
+    return {"workload": "%s, weights uniform [1,100] (seed %d)" % (spec["name"], 3000 + k),
+            "sources": len(srcs), "ms_per_source": round(per_s * 1e3, 3), "teps": m / per_s,
+            "unit": "TEPS (undirected edges / time per source)",
+            "rounds_mean": float(np.mean(rounds)), "entries_scanned_over_nnz": round(edges_scanned / len(ci), 2),
+            "kernels": kernels, "roofline": roofline,
+            "cpu_baseline": {"value": m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                             "sample": "Dijkstra from the first source, single-threaded C oracle, %.2f s" % cpu_s},
+            "parity": {"sources": 1, "bit_exact": bool(np.array_equal(got, ref))}}
 
 
 def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
@@ -188,6 +267,10 @@ def main():
                     help="sources timed through the CPU oracle (0 = skip)")
     ap.add_argument("--serving-requests", type=int, default=80,
                     help="requests per phase of the serving workload (0 = skip)")
+    ap.add_argument("--sssp-sources", default="rmat-22:16,road-4096:2",
+                    help="SSSP legs as workload:sources, comma-separated ('' = skip)")
+    ap.add_argument("--only-sssp", action="store_true",
+                    help="run only the SSSP legs and print their JSON object")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one elementwise kernel that reads and writes this many GiB "
                          "(a known-size kernel that calibrates hardware byte counters in a "
@@ -236,6 +319,13 @@ def main():
         rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
+    if args.only_sssp:
+        sssp = {}
+        for leg in filter(None, args.sssp_sources.split(",")):
+            wl, ns = leg.split(":")
+            sssp[wl] = sssp_benchmark(sp, torch, wl, int(ns))
+        print(json.dumps({"sssp": sssp}))
+        return
     k = WORKLOADS[args.workload]
 
     t0 = time.perf_counter()
@@ -401,6 +491,10 @@ def main():
 
     g.release()
     del out
+    sssp = {}
+    for leg in filter(None, args.sssp_sources.split(",")):
+        wl, ns = leg.split(":")
+        sssp[wl] = sssp_benchmark(sp, torch, wl, int(ns))
     serving = None
     if args.serving_requests > 0:
         serving = serving_benchmark(sp, torch, args.serving_requests)
@@ -441,6 +535,7 @@ def main():
         "cpu_baseline_parallel": cpu_par,
         "parity": parity,
         "serving": serving,
+        "sssp": sssp or None,
     }
     print(json.dumps(line))
 

@@ -371,7 +371,7 @@ void sssp_ws_destroy(SsspWorkspace &ws);
 
 struct SsspOpts {
     int forced = -1;       // -1 auto, else SSSP_PUSH / SSSP_PULL
-    double alpha = 2.0;
+    double alpha = 1.0;    // a frontier never holds more than every entry: no pull rounds
     int block = 256;
     int chunk_rounds = 8;
 };

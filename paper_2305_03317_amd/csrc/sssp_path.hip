@@ -522,8 +522,9 @@ static sp_status sssp_run_bs(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
     const bool hubs = g->n_hubs > 0;
-    // Automatic choice never pulls on sparse meshes (every row at most 8 long).
-    const bool may_pull = o.forced == SSSP_PULL || (o.forced < 0 && o.alpha > 0 && g->max_degree > 8);
+    // Automatic choice never pulls on sparse meshes (every row at most 8 long),
+    // nor when alpha <= 1 (a frontier's entries never exceed the graph's).
+    const bool may_pull = o.forced == SSSP_PULL || (o.forced < 0 && o.alpha > 1.0 && g->max_degree > 8);
     const bool may_push = o.forced != SSSP_PULL;
     const int forced = may_pull ? o.forced : SSSP_PUSH;
     hipLaunchKernelGGL(k_sssp_fill, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.ds, n);

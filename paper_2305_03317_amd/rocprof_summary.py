@@ -39,7 +39,7 @@ FAMILY = {
     "k_ms_sigma_hub": "ms_sigma_hub", "k_ms_delta": "ms_delta", "k_ms_delta_hub": "ms_delta_hub",
     "k_ms_expand": "ms_expand", "k_ms_bc": "ms_bc", "k_src_topdown": "src_topdown", "k_src_bottomup": "src_bottomup",
     "k_src_sigma": "src_sigma", "k_src_sigma_hub": "src_sigma_hub", "k_src_delta": "src_delta",
-    "k_src_delta_hub": "src_delta_hub",
+    "k_src_delta_hub": "src_delta_hub", "k_sssp_push": "sssp_push", "k_sssp_pull": "sssp_pull",
 }
 
 
