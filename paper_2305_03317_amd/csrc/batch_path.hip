@@ -715,8 +715,20 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
     unsigned long long *qmask, uint32_t *qvb, unsigned long long *seen, int32_t *claim,
     const uint4 *__restrict__ front_cur, uint4 *front_nxt, double *val, long long vcap,
     long long qcap, int32_t *level_off, int32_t *hub_off, int32_t *hub_lvl_chunks, long long hub_cap,
-    int32_t *chunk_off, long long owner_cap, unsigned long long *prof) {
-    if (c->done) return;
+    int32_t *chunk_off, long long owner_cap, int32_t parity, unsigned long long *prof) {
+    // This kernel ends its level in its last working block.  A block that
+    // starts only after that (the grid need not fit on the chip at once)
+    // must not take part in the next level: the launch carries its level's
+    // parity, the block reads done and level once (shared by the block), and
+    // the level's entry range comes from level_off, which no later level
+    // rewrites.
+    __shared__ int32_t s_ctl[2];
+    if (threadIdx.x == 0) {
+        s_ctl[0] = ld_agent(&c->done);
+        s_ctl[1] = ld_agent(&c->level);
+    }
+    __syncthreads();
+    if (s_ctl[0] || (s_ctl[1] & 1) != parity) return;
     const unsigned long long active = c->active;
     __shared__ int32_t s_own[kExpandDeg * BS], s_cnt[1], s_scan[BS / kWave + 1];
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
@@ -728,8 +740,8 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
         s_cnt[0] = 0;
     }
     __syncthreads();
-    const int32_t lo = c->lo, hi = c->hi;
-    const uint32_t lvl = (uint32_t)c->level;
+    const uint32_t lvl = (uint32_t)s_ctl[1];
+    const int32_t lo = level_off[lvl], hi = level_off[lvl + 1];
     const int32_t nl = (int32_t)lvl + 1;
     const int lane = lane_id();
     unsigned long long my_items = 0, my_edges = 0, my_pairs = 0, my_pull = 0, my_flag = 0, my_or = 0;
@@ -965,11 +977,21 @@ __global__ __launch_bounds__(BS, 6) void k_ms_delta(LevelCtl *c, int32_t step,
                                                  const unsigned long long *__restrict__ qmask,
                                                  const uint32_t *__restrict__ qvb, uint4 *f0,
                                                  uint4 *f1, double *val, double *dlt,
-                                                 unsigned long long *prof) {
+                                                 int32_t parity, unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
-    const int32_t lvl = c->bwd_level;  // the reverse sweep's level; 0 = finished
-    if (lvl < 1) return;
-    const bool deepest = lvl == c->bwd_last;
+    // The reverse sweep's level (0 = finished), read once by the block.  With
+    // `step` this kernel moves the sweep up in its last working block; the
+    // parity of the launch's step (levels swept before it) lets a block that
+    // starts after that return instead of sweeping the next level.
+    __shared__ int32_t s_ctl[2];
+    if (threadIdx.x == 0) {
+        s_ctl[0] = ld_agent(&c->bwd_level);
+        s_ctl[1] = c->bwd_last;
+    }
+    __syncthreads();
+    const int32_t lvl = s_ctl[0];
+    if (lvl < 1 || ((s_ctl[1] - lvl) & 1) != parity) return;
+    const bool deepest = lvl == s_ctl[1];
     const uint4 *__restrict__ front_rd = ((lvl + 1) & 1) ? f1 : f0;  // children's records
     uint4 *front_wr = (lvl & 1) ? f1 : f0;
     const int32_t lo = level_off[lvl], hi = level_off[lvl + 1];
@@ -1087,11 +1109,18 @@ __global__ void k_ms_delta_hub_fin(LevelCtl *c, const int32_t *__restrict__ hub_
                                    const unsigned long long *__restrict__ qmask,
                                    const uint32_t *__restrict__ qvb, double *val, double *dlt,
                                    const HubEntry *__restrict__ hub_list,
-                                   const double *__restrict__ partial) {
-    const int32_t lvl = c->bwd_level;
-    if (lvl < 1) return;
+                                   const double *__restrict__ partial, int32_t parity) {
+    // Ends the reverse level in its last working block: guarded as k_ms_delta.
+    __shared__ int32_t s_ctl[2];
+    if (threadIdx.x == 0) {
+        s_ctl[0] = ld_agent(&c->bwd_level);
+        s_ctl[1] = c->bwd_last;
+    }
+    __syncthreads();
+    const int32_t lvl = s_ctl[0];
+    if (lvl < 1 || ((s_ctl[1] - lvl) & 1) != parity) return;
     const int32_t hlo = hub_off[lvl];
-    const int32_t nh = lvl == c->bwd_last ? 0 : hub_off[lvl + 1] - hlo;  // deepest: done in k_ms_delta
+    const int32_t nh = lvl == s_ctl[1] ? 0 : hub_off[lvl + 1] - hlo;  // deepest: done in k_ms_delta
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -1319,7 +1348,7 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
                                (const uint4 *)fcur, fnxt, ws.val, (long long)ws.vcap,
                                (long long)ws.qcap, ws.level_off, ws.hub_off, ws.hub_lvl_chunks,
                                (long long)ws.hub_cap, ws.chunk_off, (long long)ws.owner_cap,
-                               prof_counters(P_MS_EXPAND));
+                               (int32_t)(l & 1), prof_counters(P_MS_EXPAND));
             continue;
         }
         {
@@ -1435,12 +1464,14 @@ static void enqueue_reverse(sp_graph g, BatchWorkspace &ws, int count, int grid_
                             bool hubs, hipStream_t s) {
     const int hub_fin_grid = grid_for((int64_t)g->n_hubs * kWave, 256, device_cu_count() * 8);
     for (int k = 0; k < count; ++k) {
+        // callers start every group at an even step of the sweep
+        const int32_t parity = k & 1;
         {
             ProfScope ps(P_MS_DELTA, s);
             hipLaunchKernelGGL(k_ms_delta<BS>, dim3(grid_d), dim3(BS), 0, s, ws.ctl, (int32_t)!hubs,
                                (const int32_t *)ws.level_off, g->row_ptr, g->col_idx, ws.queue,
                                ws.qmask, (const uint32_t *)ws.qvb, ws.front[0], ws.front[1], ws.val,
-                               ws.dlt, prof_counters(P_MS_DELTA));
+                               ws.dlt, parity, prof_counters(P_MS_DELTA));
         }
         if (hubs) {
             ProfScope ps(P_MS_DELTA_HUB, s);  // chunk and finishing kernels together
@@ -1457,7 +1488,7 @@ static void enqueue_reverse(sp_graph g, BatchWorkspace &ws, int count, int grid_
             hipLaunchKernelGGL(k_ms_delta_hub_fin, dim3(hub_fin_grid), dim3(256), 0, s, ws.ctl,
                                (const int32_t *)ws.hub_off, (const unsigned long long *)ws.qmask,
                                (const uint32_t *)ws.qvb, ws.val, ws.dlt,
-                               (const HubEntry *)ws.hub_list, (const double *)ws.partial);
+                               (const HubEntry *)ws.hub_list, (const double *)ws.partial, parity);
         }
     }
 }
