@@ -13,6 +13,8 @@ Contents
 * ``sssp``: single-source shortest paths on a weighted CSR (``sssp_oracle.c``,
   Dijkstra): the distances the paper's SSSP (Section 2.2, Fig. "SSSP
   computation in StarPlat"; pull form in the Appendix) converges to.
+* ``pagerank``: the paper's pull PageRank (Appendix, Fig. "PR computation
+  in StarPlat"), double buffered, in numpy float64 (``pagerank.py``).
 * ``csr_from_edges``: the CSR the paper's graph library stores (Section 2.3.1
   "Data Types": offsets plus concatenated neighbour lists), built from an edge
   list with plain numpy set operations.
@@ -29,6 +31,8 @@ import os
 import subprocess
 
 import numpy as np
+
+from .pagerank import pagerank  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "bc_oracle.c"), os.path.join(_HERE, "sssp_oracle.c")]
