@@ -4,7 +4,8 @@
  *
  * The library computes Brandes betweenness centrality over a source list on
  * a simple, undirected, unweighted graph held as int32 CSR, on one AMD GPU,
- * and single-source shortest paths once the graph is given edge weights.
+ * single-source shortest paths once the graph is given edge weights, and
+ * PageRank.
  * The operation is the paper's computeBC (Appendix, Fig. "BC computation in
  * StarPlat"): BC is zeroed, then for every source a level-synchronous
  * breadth-first pass counts shortest paths (sigma[w] += sigma[v] over BFS-DAG
@@ -281,6 +282,54 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
 
 /* Counters of the last sp_sssp call on the calling thread. */
 sp_status sp_sssp_get_last_stats(sp_sssp_stats *out);
+
+/* ------------------------------------------------------------------------
+ * PageRank (paper Appendix, Fig. "PR computation in StarPlat": pull form,
+ * double buffered)
+ *
+ * Every vertex starts at 1/N.  Each iteration computes, from the previous
+ * iteration's values,
+ *     pr'[v] = (1 - delta) / N + delta * sum over neighbours u of pr[u] / deg(u)
+ * and the run stops after the first iteration whose sum over vertices of
+ * |pr'[v] - pr[v]| is at most beta, or after max_iter iterations (at least
+ * one runs).  The paper writes the signed difference; its sum is zero on a
+ * graph without isolated vertices (the iteration keeps total mass), which
+ * would stop the loop at once, so the absolute difference is used.  Mass of
+ * vertices without neighbours is not redistributed.  The graph is undirected
+ * (a vertex's in-neighbours are its row).  All arithmetic is binary64; each
+ * vertex's sum is taken in an order fixed by its row, so results are
+ * reproducible.
+ * ------------------------------------------------------------------------ */
+
+typedef struct sp_pagerank_config {
+    int32_t block_size;  /* 128, 256 or 512 (0 = 256) */
+    int32_t chunk_iters; /* k > 0: iterations captured k at a time (rounded up to
+                            even) in a hipGraph, the device "done" flag checked
+                            after each replay; k < 0: |k| per check, launched
+                            directly; 0 = 8.  |k| <= 65536. */
+    int32_t reserved[4]; /* must be zero */
+} sp_pagerank_config;
+
+typedef struct sp_pagerank_stats {
+    int32_t iterations;     /* iterations run */
+    int32_t graph_launches; /* hipGraph launches used */
+    double diff;            /* sum of |change| in the last iteration (accurate to
+                               about 1e-15: block sums are added in fixed point) */
+    double device_ms;       /* HIP-event time of the call's device work */
+} sp_pagerank_stats;
+
+/* PageRank of every vertex.
+ *   beta      stopping threshold on the summed |change|, >= 0
+ *   delta     damping factor in [0, 1]
+ *   max_iter  >= 1
+ *   out_pr    device double[V]: receives the values of the last iteration.
+ *   cfg       may be NULL.
+ * Synchronises the stream. */
+sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, double *out_pr,
+                      const sp_pagerank_config *cfg, sp_stream s);
+
+/* Counters of the last sp_pagerank call on the calling thread. */
+sp_status sp_pagerank_get_last_stats(sp_pagerank_stats *out);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support)

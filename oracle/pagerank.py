@@ -47,8 +47,7 @@ def pagerank(row_ptr, col_idx, beta: float, delta: float, max_iter: int, iterati
         share = np.zeros(n)
         has = outdeg > 0
         share[has] = pr[has] / outdeg[has]
-        s = np.zeros(n)
-        np.add.at(s, ci, share[src_of_entry])
+        s = np.bincount(ci, weights=share[src_of_entry], minlength=n)
         val = (1.0 - delta) / n + delta * s
         diff = float(np.sum(np.abs(val - pr)))
         pr = val

@@ -377,16 +377,78 @@ static void release_sssp_ws(sp_graph g, SsspWorkspace *ws) {
     g->sssp_pool.push_back(ws);
 }
 
+static thread_local sp_pagerank_stats g_pr_stats;
+
+static sp_status acquire_pr_ws(sp_graph g, PrWorkspace **out) {
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (!g->pr_pool.empty()) {
+            *out = g->pr_pool.back();
+            g->pr_pool.pop_back();
+            return SP_OK;
+        }
+    }
+    auto *ws = new (std::nothrow) PrWorkspace;
+    if (!ws) return SP_ERR_OUT_OF_MEMORY;
+    sp_status st = pr_ws_create(g, *ws);
+    if (st < 0) {
+        delete ws;
+        return st;
+    }
+    *out = ws;
+    return SP_OK;
+}
+
+static void release_pr_ws(sp_graph g, PrWorkspace *ws) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->pr_pool.push_back(ws);
+}
+
 static void free_weights(sp_graph g) {
     dev_free(g->adjw);
-    dev_free(g->hub_static);
-    dev_free(g->owner_static);
     g->adjw = nullptr;
-    g->hub_static = nullptr;
-    g->owner_static = nullptr;
     g->max_weight = 0;
     g->bytes -= g->weight_bytes;
     g->weight_bytes = 0;
+}
+
+// Every hub of the graph with its chunk range, in vertex order, and the hub
+// of every chunk: built once per graph on first use (SSSP pull rounds,
+// PageRank), kept until the graph is released.
+sp_status ensure_static_hubs(sp_graph g, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->hub_static) return SP_OK;
+    std::vector<HubEntry> hubs;
+    std::vector<int32_t> owners;
+    for (int32_t v = 0; v < g->n; ++v)
+        if (g->host_deg[v] > kHubDeg) {
+            const int32_t nch = (g->host_deg[v] + kHubChunk - 1) / kHubChunk;
+            hubs.push_back(HubEntry{v, 0, (int32_t)owners.size(), nch});
+            owners.insert(owners.end(), (size_t)nch, (int32_t)hubs.size() - 1);
+        }
+    HubEntry *hub_static = nullptr;
+    int32_t *owner_static = nullptr;
+    const size_t hb = sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1);
+    const size_t ob = sizeof(int32_t) * std::max<size_t>(owners.size(), 1);
+    sp_status rc = dev_alloc((void **)&hub_static, hb);
+    if (rc == SP_OK) rc = dev_alloc((void **)&owner_static, ob);
+    hipError_t e = hipSuccess;
+    if (rc == SP_OK && !hubs.empty())
+        e = hipMemcpyAsync(hub_static, hubs.data(), hubs.size() * sizeof(HubEntry), hipMemcpyHostToDevice, st);
+    if (rc == SP_OK && e == hipSuccess && !owners.empty())
+        e = hipMemcpyAsync(owner_static, owners.data(), owners.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st);
+    if (rc == SP_OK && e == hipSuccess) e = hipStreamSynchronize(st);
+    if (rc != SP_OK || e != hipSuccess) {
+        dev_free(hub_static);
+        dev_free(owner_static);
+        if (e != hipSuccess) set_error("hub list upload failed: %s", hipGetErrorString(e));
+        return rc != SP_OK ? rc : SP_ERR_DEVICE;
+    }
+    g->hub_static = hub_static;
+    g->owner_static = owner_static;
+    g->bytes += hb + ob;
+    return SP_OK;
 }
 
 }  // namespace sp
@@ -539,7 +601,13 @@ sp_status sp_graph_release(sp_graph g) {
         sssp_ws_destroy(*ws);
         delete ws;
     }
+    for (auto *ws : g->pr_pool) {
+        pr_ws_destroy(*ws);
+        delete ws;
+    }
     free_weights(g);
+    dev_free(g->hub_static);
+    dev_free(g->owner_static);
     dev_free(g->row_ptr);
     dev_free(g->col_idx);
     delete g;
@@ -853,45 +921,24 @@ sp_status sp_graph_set_weights(sp_graph g, const int32_t *weights, uint32_t flag
         SP_HIP(hipStreamSynchronize(st));
         if (!weights_symmetric(g->n, hr.data(), hc.data(), w)) return SP_ERR_INVALID_ARGUMENT;
     }
-    // Hubs of the graph with their chunk ranges, in vertex order, and the hub
-    // of every chunk (pull rounds).
-    std::vector<HubEntry> hubs;
-    std::vector<int32_t> owners;
-    for (int32_t v = 0; v < g->n; ++v)
-        if (g->host_deg[v] > kHubDeg) {
-            const int32_t nch = (g->host_deg[v] + kHubChunk - 1) / kHubChunk;
-            hubs.push_back(HubEntry{v, 0, (int32_t)owners.size(), nch});
-            owners.insert(owners.end(), (size_t)nch, (int32_t)hubs.size() - 1);
-        }
+    SP_TRY(ensure_static_hubs(g, st));
     int2 *adjw = nullptr;
-    HubEntry *hub_static = nullptr;
-    int32_t *owner_static = nullptr;
     int32_t *wdev = nullptr;
     unsigned int *bad = nullptr;  // bad[0]: count, bad[1]: largest weight (as int)
     auto cleanup = [&](sp_status code) {
         dev_free(adjw);
-        dev_free(hub_static);
-        dev_free(owner_static);
         dev_free(wdev);
         dev_free(bad);
         return code;
     };
     const size_t adj_bytes = sizeof(int2) * (size_t)std::max<int64_t>(nnz, 1);
-    const size_t hub_bytes = sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1) +
-                             sizeof(int32_t) * std::max<size_t>(owners.size(), 1);
     sp_status rc = dev_alloc((void **)&adjw, adj_bytes);
-    if (rc == SP_OK) rc = dev_alloc((void **)&hub_static, sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1));
-    if (rc == SP_OK) rc = dev_alloc((void **)&owner_static, sizeof(int32_t) * std::max<size_t>(owners.size(), 1));
     if (rc == SP_OK) rc = dev_alloc((void **)&bad, 8);
     if (rc == SP_OK && !on_dev && nnz) rc = dev_alloc((void **)&wdev, (size_t)nnz * 4);
     if (rc != SP_OK) return cleanup(rc);
     unsigned int h_bad[2] = {0, 0};
     hipError_t e = hipMemsetAsync(bad, 0, 8, st);
     if (e == hipSuccess && wdev) e = hipMemcpyAsync(wdev, weights, (size_t)nnz * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !hubs.empty())
-        e = hipMemcpyAsync(hub_static, hubs.data(), hubs.size() * sizeof(HubEntry), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !owners.empty())
-        e = hipMemcpyAsync(owner_static, owners.data(), owners.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && nnz) {
         hipLaunchKernelGGL(k_pack_weights, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st,
                            (const int32_t *)g->col_idx, (const int32_t *)(wdev ? wdev : weights), nnz,
@@ -916,10 +963,8 @@ sp_status sp_graph_set_weights(sp_graph g, const int32_t *weights, uint32_t flag
         std::lock_guard<std::mutex> lk(g->mu);
         free_weights(g);
         g->adjw = adjw;
-        g->hub_static = hub_static;
-        g->owner_static = owner_static;
         g->max_weight = (int32_t)h_bad[1];
-        g->weight_bytes = adj_bytes + hub_bytes;
+        g->weight_bytes = adj_bytes;
         g->bytes += g->weight_bytes;
     }
     return SP_OK;
@@ -990,6 +1035,60 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
 sp_status sp_sssp_get_last_stats(sp_sssp_stats *out) {
     if (!out) return SP_ERR_INVALID_ARGUMENT;
     *out = g_sssp_stats;
+    return SP_OK;
+}
+
+sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, double *out_pr,
+                      const sp_pagerank_config *cfg, sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || (g->n > 0 && !out_pr) || !(beta >= 0.0) || std::isinf(beta) || !(delta >= 0.0 && delta <= 1.0) ||
+        max_iter < 1) {
+        set_error("sp_pagerank: null graph/output, beta < 0, delta outside [0, 1] or max_iter < 1");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    PrOpts o;
+    if (cfg) {
+        if ((cfg->block_size != 0 && cfg->block_size != 128 && cfg->block_size != 256 &&
+             cfg->block_size != 512) ||
+            std::abs((int64_t)cfg->chunk_iters) > 65536 || cfg->reserved[0] || cfg->reserved[1] ||
+            cfg->reserved[2] || cfg->reserved[3]) {
+            set_error("sp_pagerank: invalid configuration");
+            return SP_ERR_INVALID_ARGUMENT;
+        }
+        if (cfg->block_size) o.block = cfg->block_size;
+        if (cfg->chunk_iters) o.chunk_iters = cfg->chunk_iters;
+    }
+    g_pr_stats = sp_pagerank_stats{};
+    if (g->n == 0) return SP_OK;
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    SP_TRY(ensure_static_hubs(g, st));
+    PrWorkspace *ws = nullptr;
+    SP_TRY(acquire_pr_ws(g, &ws));
+    struct Rel {
+        sp_graph g;
+        PrWorkspace *ws;
+        ~Rel() { release_pr_ws(g, ws); }
+    } rel{g, ws};
+    PrResult r;
+    SP_HIP(hipEventRecord(ws->ev0, st));
+    SP_TRY(pr_run(g, *ws, beta, delta, max_iter, out_pr, o, st, &r));
+    SP_HIP(hipEventRecord(ws->ev1, st));
+    SP_HIP(hipEventSynchronize(ws->ev1));
+    float ms = 0.f;
+    SP_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+    g_pr_stats.iterations = r.iterations;
+    g_pr_stats.graph_launches = r.graph_launches;
+    g_pr_stats.diff = r.diff;
+    g_pr_stats.device_ms = ms;
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_pagerank_get_last_stats(sp_pagerank_stats *out) {
+    if (!out) return SP_ERR_INVALID_ARGUMENT;
+    *out = g_pr_stats;
     return SP_OK;
 }
 

@@ -49,6 +49,7 @@ void dev_free(void *p);
 struct BatchWorkspace;
 struct SourceWorkspace;
 struct SsspWorkspace;
+struct PrWorkspace;
 struct HubEntry;
 
 struct TuneEntry {
@@ -77,13 +78,16 @@ struct sp_graph_s {
     std::vector<sp::BatchWorkspace *> batch_pool;
     // Edge weights (sp_graph_set_weights), null until set: the adjacency
     // packed as {neighbour, weight} per CSR entry, so one 8-byte load gives
-    // both, and every hub with its chunk range for the pull rounds.
+    // both.
     int2 *adjw = nullptr;            // device, nnz (>= 1 element allocated)
-    sp::HubEntry *hub_static = nullptr;  // device, n_hubs (>= 1): in vertex order
-    int32_t *owner_static = nullptr;     // device, hub_chunks (>= 1): hub of each chunk
+    // Every hub with its chunk range, in vertex order, and the hub of each
+    // chunk; built on first use by the whole-graph kernels (ensure_static_hubs).
+    sp::HubEntry *hub_static = nullptr;  // device, n_hubs (>= 1)
+    int32_t *owner_static = nullptr;     // device, hub_chunks (>= 1)
     int32_t max_weight = 0;
     size_t weight_bytes = 0;
     std::vector<sp::SsspWorkspace *> sssp_pool;
+    std::vector<sp::PrWorkspace *> pr_pool;
 };
 
 namespace sp {
@@ -169,7 +173,7 @@ struct LevelCtl {
 enum ProfKind : int {
     P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
     P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_EXPAND, P_MS_DELTA, P_MS_DELTA_HUB,
-    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL,
+    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL, P_PR_PULL, P_PR_HUB,
     P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
@@ -385,6 +389,58 @@ struct SsspResult {
 // to out_dist unless the result overflows.
 sp_status sssp_run(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t *out_dist, const SsspOpts &o,
                    hipStream_t s, SsspResult *res);
+
+// ---------------------------------------------------------------------------
+// PageRank (pr_path.hip)
+// ---------------------------------------------------------------------------
+// Iteration control block.  `state` = iteration * 2 + done, written by the
+// closing block in one store and read once per block (a block that starts
+// after its iteration was closed sees another parity and returns).
+struct PrCtl {
+    int32_t state;
+    int32_t max_iter;
+    double beta;         // continue while diff > beta
+    double last_diff;    // diff of the last iteration run
+    HotU64 diff_;        // this iteration's sum of |change|, fixed point (2^-kPrDiffBits units)
+    HotI32 blocks_done_; // working blocks of the closing kernel that finished
+};
+// Each block rounds its sum of |change| to a multiple of 2^-60 and adds it
+// with an integer atomic: the total is the same whatever the order, so the
+// stopping decision is reproducible.  Its error is at most blocks x 2^-61
+// (under 2e-15 for 4096 blocks); the sum itself is at most 2 (the values
+// start at 1/N and each iteration's total is at most 1), below the 16 that
+// 64 bits hold at this scale.
+constexpr int kPrDiffBits = 60;
+
+struct PrWorkspace {
+    int device = -1;
+    double *pr[2] = {nullptr, nullptr};     // V each: PageRank by iteration parity
+    double *share[2] = {nullptr, nullptr};  // V each: pr / out-degree (0 without out-edges)
+    double *partial = nullptr;              // hub_chunks + 1: hub chunk sums
+    PrCtl *ctl = nullptr;
+    PrCtl *ctl_host = nullptr;              // pinned mirror
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap_stream = nullptr;
+    CapturedChunk iters;
+};
+sp_status pr_ws_create(sp_graph g, PrWorkspace &ws);
+void pr_ws_destroy(PrWorkspace &ws);
+
+struct PrOpts {
+    int block = 256;
+    int chunk_iters = 8;   // > 0: captured chunks; < 0: direct launches
+};
+struct PrResult {
+    int32_t iterations = 0;
+    double diff = 0.0;
+    int32_t graph_launches = 0;
+};
+// PageRank of every vertex into out_pr (device, V doubles).
+sp_status pr_run(sp_graph g, PrWorkspace &ws, double beta, double delta, int32_t max_iter,
+                 double *out_pr, const PrOpts &o, hipStream_t s, PrResult *res);
+
+// Builds g->hub_static / g->owner_static once (thread-safe).
+sp_status ensure_static_hubs(sp_graph g, hipStream_t s);
 
 // Workspace pools and configuration shared by the entry points and the server.
 int64_t initial_qcap(int32_t n, int32_t width);

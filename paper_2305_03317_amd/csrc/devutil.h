@@ -288,4 +288,34 @@ __device__ __forceinline__ bool wave_chunk_any(int32_t beg, int32_t deg, const W
     return ws.acc[lane] != 0.0;
 }
 
+// One chunk of a hub: lanes stride over its entries, each summing in order,
+// then a fixed xor tree; the chunk's sum goes to partial[k].  A finishing
+// kernel adds a hub's chunk sums in chunk order (the kernel boundary makes
+// them visible, so no fence is needed here).
+template <class Term>
+__device__ __forceinline__ void hub_chunk(int32_t k, int32_t beg, int32_t end, double *partial,
+                                          Term term) {
+    const int lane = lane_id();
+    double x = 0.0;
+    for (int32_t e = beg + lane; e < end; e += kWave) x += term(e);
+    x = wave_sum_f64(x);
+    if (lane == 0) partial[k] = x;
+}
+
+// Sum of partial[base .. base+n) in index order, eight loads in flight.
+__device__ __forceinline__ double sum_chunks(const double *__restrict__ partial, int32_t base,
+                                             int32_t n) {
+    double s = 0.0;
+    int32_t q = 0;
+    for (; q + 8 <= n; q += 8) {
+        double x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = partial[base + q + t];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += x[t];
+    }
+    for (; q < n; ++q) s += partial[base + q];
+    return s;
+}
+
 }  // namespace sp

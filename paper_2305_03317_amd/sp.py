@@ -63,6 +63,16 @@ class sp_sssp_stats(ctypes.Structure):
                 ("direction", ctypes.c_int32), ("chunk_rounds", ctypes.c_int32)]
 
 
+class sp_pagerank_config(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("chunk_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class sp_pagerank_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("graph_launches", ctypes.c_int32),
+                ("diff", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+
 class sp_server_config(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
@@ -113,6 +123,9 @@ SIGNATURES = [
     ("sp_graph_set_weights", _ST, [_VP, _VP, ctypes.c_uint32, _VP]),
     ("sp_sssp", _ST, [_VP, ctypes.c_int32, _VP, ctypes.POINTER(sp_sssp_config), _VP]),
     ("sp_sssp_get_last_stats", _ST, [ctypes.POINTER(sp_sssp_stats)]),
+    ("sp_pagerank", _ST, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _VP,
+                          ctypes.POINTER(sp_pagerank_config), _VP]),
+    ("sp_pagerank_get_last_stats", _ST, [ctypes.POINTER(sp_pagerank_stats)]),
     ("sp_profile_enable", _ST, [ctypes.c_int32]),
     ("sp_profile_read", _ST, [ctypes.POINTER(sp_kernel_profile), ctypes.c_int32, _I32P]),
     ("sp_server_create", _ST, [ctypes.POINTER(sp_server_config), ctypes.POINTER(_VP)]),
@@ -370,6 +383,25 @@ def sp_sssp(g: Graph, source: int, out_dist=None, config=None, stream=None):
 def sp_sssp_get_last_stats() -> dict:
     s = sp_sssp_stats()
     _check(lib().sp_sssp_get_last_stats(ctypes.byref(s)), "sp_sssp_get_last_stats")
+    return _struct_dict(s)
+
+
+def sp_pagerank(g: Graph, beta: float = 1e-6, delta: float = 0.85, max_iter: int = 100, out_pr=None,
+                config=None, stream=None):
+    """float64 PageRank of every vertex, a CUDA tensor [V]."""
+    out_pr = _out_f64(g, out_pr)
+    cfg = None
+    if config is not None:
+        c = config if isinstance(config, sp_pagerank_config) else sp_pagerank_config(**config)
+        cfg = ctypes.byref(c)
+    _check(lib().sp_pagerank(g.handle, float(beta), float(delta), int(max_iter), out_pr.data_ptr(), cfg,
+                             _stream(stream)), "sp_pagerank")
+    return out_pr[:g.n]
+
+
+def sp_pagerank_get_last_stats() -> dict:
+    s = sp_pagerank_stats()
+    _check(lib().sp_pagerank_get_last_stats(ctypes.byref(s)), "sp_pagerank_get_last_stats")
     return _struct_dict(s)
 
 

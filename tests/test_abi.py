@@ -51,7 +51,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     structs = {"sp_batch_config": sp.sp_batch_config, "sp_stats": sp.sp_stats,
                "sp_server_config": sp.sp_server_config, "sp_server_stats": sp.sp_server_stats,
                "sp_kernel_profile": sp.sp_kernel_profile, "sp_sssp_config": sp.sp_sssp_config,
-               "sp_sssp_stats": sp.sp_sssp_stats}
+               "sp_sssp_stats": sp.sp_sssp_stats, "sp_pagerank_config": sp.sp_pagerank_config,
+               "sp_pagerank_stats": sp.sp_pagerank_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
@@ -130,6 +131,8 @@ def test_sssp_calls_reject_bad_arguments_on_the_host():
     assert L.sp_sssp(None, 0, None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
     assert L.sp_sssp_get_last_stats(None) == sp.SP_ERR_INVALID_ARGUMENT
     assert {"SP_SSSP_AUTO", "SP_SSSP_PUSH", "SP_SSSP_PULL"} <= set(dir(sp))
+    assert L.sp_pagerank(None, 1e-6, 0.85, 10, None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_pagerank_get_last_stats(None) == sp.SP_ERR_INVALID_ARGUMENT
 
 
 def test_header_constants_match_binding():

@@ -156,7 +156,7 @@ MUTANTS = {
     "teleport_not_divided": ("(1.0 - delta) / n + delta * s", "(1.0 - delta) + delta * s"),
     "share_not_divided": ("share[has] = pr[has] / outdeg[has]", "share[has] = pr[has]"),
     "signed_difference": ("np.sum(np.abs(val - pr))", "np.sum(val - pr)"),
-    "gather_out_neighbours": ("np.add.at(s, ci, share[src_of_entry])", "np.add.at(s, src_of_entry, share[ci])"),
+    "gather_out_neighbours": ("np.bincount(ci, weights=share[src_of_entry]", "np.bincount(src_of_entry, weights=share[ci]"),
     "no_damping_on_sum": ("(1.0 - delta) / n + delta * s", "(1.0 - delta) / n + s"),
     "in_place_start": ("pr = np.full(n, 1.0 / n)", "pr = np.full(n, 1.0)"),
     "one_extra_iteration": ("elif not (diff > beta and it < max_iter):", "elif not (diff > beta and it <= max_iter):"),
