@@ -22,8 +22,10 @@ Also: the per-source GPU path on a sample of the same sources (the batched
 vs per-source ratio), the CPU oracle on a bounded sample (cpu_baseline, which
 doubles as a parity check of this run), the serving workload (eight
 resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS),
-and single-source shortest paths on the RMAT and road graphs with the paper's
-uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle).
+single-source shortest paths on the RMAT and road graphs with the paper's
+uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle),
+and PageRank on the same graphs (time per iteration, kernel roofline, numpy
+oracle).
 
 Prints one JSON line.
 """
@@ -71,6 +73,10 @@ BYTE_MODEL = {
     # entries (packed {neighbour, weight} plus the neighbour's {dist, stamp})
     "sssp_push": dict(items=20, edges=16),
     "sssp_pull": dict(items=8, edges=16),
+    # PageRank iteration: items = non-hub vertices (row offsets, own value
+    # read, value and share written), edges = adjacency entries (column id,
+    # neighbour's share); hub chunks count their entries the same way
+    "pr_pull": dict(items=28, edges=12),
 }
 FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_expand")
 
@@ -166,6 +172,68 @@ def sssp_benchmark(sp, torch, workload, n_sources):
             "cpu_baseline": {"value": m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
                              "sample": "Dijkstra from the first source, single-threaded C oracle, %.2f s" % cpu_s},
             "parity": {"sources": 1, "bit_exact": bool(np.array_equal(got, ref))}}
+
+
+def pagerank_benchmark(sp, torch, workload, iterations):
+    """PageRank (the paper's pull form, damping 0.85) on a benchmark graph:
+    a fixed number of iterations (beta = 0, so every run does exactly that
+    many), wall time with the graph resident; then the same run with kernel
+    events and once with work counters; the numpy oracle on the same
+    iterations is the CPU baseline and a parity check."""
+    import numpy as np
+    import oracle
+    from paper_2305_03317_amd import graphs
+    k = WORKLOADS[workload]
+    rp, ci, _, spec = graphs.workload(k)
+    g = sp.sp_graph_upload(rp, ci)
+    out = torch.empty(len(rp) - 1, dtype=torch.float64, device="cuda")
+    sp.sp_pagerank(g, 0.0, 0.85, iterations, out)  # warm: workspace, hub list, captured chunk
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp.sp_pagerank(g, 0.0, 0.85, iterations, out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    per_iter = float(np.min(times)) / iterations
+    sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
+    sp.sp_pagerank(g, 0.0, 0.85, iterations, out)
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
+    sp.sp_pagerank(g, 0.0, 0.85, iterations, out)
+    counted = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    kernels = {}
+    for kname, p in prof.items():
+        c = counted.get(kname, {})
+        launches = max(p["launches"], 1)
+        alg = algorithmic_bytes(kname, c)
+        kernels[kname] = {"launches": p["launches"], "ms_per_iteration": round(p["total_ms"] / iterations, 4),
+                          "avg_launch_ms": round(p["total_ms"] / launches, 4),
+                          "GBps_algorithmic": round(alg / max(p["total_ms"], 1e-9) / 1e6, 1)}
+    dom = max(kernels.items(), key=lambda kv: kv[1]["ms_per_iteration"]) if kernels else None
+    roofline = None
+    if dom:
+        achieved = dom[1]["GBps_algorithmic"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
+                    "avg_launch_ms": dom[1]["avg_launch_ms"]}
+    t0 = time.perf_counter()
+    ref, _, _ = oracle.pagerank(rp, ci, 0.0, 0.85, iterations, iterations=iterations)
+    cpu_s = time.perf_counter() - t0
+    got = out.cpu().numpy()
+    g.release()
+    m = len(ci) // 2
+    return {"workload": "%s, damping 0.85, %d iterations" % (spec["name"], iterations),
+            "ms_per_iteration": round(per_iter * 1e3, 4), "teps": len(ci) / per_iter,
+            "unit": "TEPS (adjacency entries gathered / time per iteration)", "undirected_edges": m,
+            "kernels": kernels, "roofline": roofline,
+            "cpu_baseline": {"value": len(ci) * iterations / cpu_s, "unit": "TEPS", "cores": 1,
+                             "kind": "oracle", "sample": "the same %d iterations, numpy oracle, %.1f s"
+                                                         % (iterations, cpu_s)},
+            "parity": {"max_rel_err": float(np.max(np.abs(got - ref) / ref)),
+                       "pass": bool(np.max(np.abs(got - ref) / ref) <= 1e-9)}}
 
 
 def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
@@ -269,8 +337,12 @@ def main():
                     help="requests per phase of the serving workload (0 = skip)")
     ap.add_argument("--sssp-sources", default="rmat-22:16,road-4096:2",
                     help="SSSP legs as workload:sources, comma-separated ('' = skip)")
+    ap.add_argument("--pagerank", default="rmat-22:20,road-4096:20",
+                    help="PageRank legs as workload:iterations, comma-separated ('' = skip)")
     ap.add_argument("--only-sssp", action="store_true",
                     help="run only the SSSP legs and print their JSON object")
+    ap.add_argument("--only-pagerank", action="store_true",
+                    help="run only the PageRank legs and print their JSON object")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one elementwise kernel that reads and writes this many GiB "
                          "(a known-size kernel that calibrates hardware byte counters in a "
@@ -319,12 +391,15 @@ def main():
         rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
-    if args.only_sssp:
-        sssp = {}
-        for leg in filter(None, args.sssp_sources.split(",")):
-            wl, ns = leg.split(":")
-            sssp[wl] = sssp_benchmark(sp, torch, wl, int(ns))
-        print(json.dumps({"sssp": sssp}))
+    if args.only_sssp or args.only_pagerank:
+        legs = {}
+        if args.only_sssp:
+            legs["sssp"] = {wl: sssp_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+                            (leg.split(":") for leg in filter(None, args.sssp_sources.split(",")))}
+        if args.only_pagerank:
+            legs["pagerank"] = {wl: pagerank_benchmark(sp, torch, wl, int(it)) for wl, it in
+                                (leg.split(":") for leg in filter(None, args.pagerank.split(",")))}
+        print(json.dumps(legs))
         return
     k = WORKLOADS[args.workload]
 
@@ -495,6 +570,10 @@ def main():
     for leg in filter(None, args.sssp_sources.split(",")):
         wl, ns = leg.split(":")
         sssp[wl] = sssp_benchmark(sp, torch, wl, int(ns))
+    pagerank = {}
+    for leg in filter(None, args.pagerank.split(",")):
+        wl, it = leg.split(":")
+        pagerank[wl] = pagerank_benchmark(sp, torch, wl, int(it))
     serving = None
     if args.serving_requests > 0:
         serving = serving_benchmark(sp, torch, args.serving_requests)
@@ -536,6 +615,7 @@ def main():
         "parity": parity,
         "serving": serving,
         "sssp": sssp or None,
+        "pagerank": pagerank or None,
     }
     print(json.dumps(line))
 
