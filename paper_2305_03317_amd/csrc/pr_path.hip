@@ -8,9 +8,11 @@
 //
 // Design: each iteration is one streaming pass over the CSR.  The producer of
 // a value also stores share = val / outdeg, so the gather reads one double
-// per adjacency entry.  A wave sums the rows of 64 consecutive vertices in
-// chunks of 8 aligned at the row start (wave_chunk_sum: the sum depends only
-// on the row, so results are reproducible); rows longer than kHubDeg are cut
+// per adjacency entry.  A wave takes 64 consecutive vertices: rows of at most
+// 8 entries are summed in row order by their own lane, longer ones by the
+// wave in chunks of 8 aligned at the row start (wave_chunk_sum); either way a
+// vertex's sum depends only on its row, so results are reproducible.  Rows
+// longer than kHubDeg are cut
 // into chunks of kHubChunk that waves reduce into partials, added in chunk
 // order by a finishing kernel.  The stopping test sums |val - pr| per block in
 // a fixed order and adds the block sums as fixed-point integers, so the total
@@ -23,6 +25,9 @@
 #include "levels.h"
 
 namespace sp {
+
+// Rows of at most this many entries are summed by their own lane.
+constexpr int kPrShortRow = 8;
 
 __device__ __forceinline__ unsigned long long diff_fixed(double x) {
     return (unsigned long long)__double2ll_rn(x * 0x1p60);
@@ -114,9 +119,24 @@ __global__ __launch_bounds__(BS) void k_pr_pull(PrCtl *c, const int32_t *__restr
                 beg = rp[v];
                 deg = rp[v + 1] - beg;
             }
-            const bool hub = deg > kHubDeg;
-            const double sum = wave_chunk_sum(beg, hub ? 0 : deg, ws,
-                                              [&](int32_t e, int32_t) { return sh[ci[e]]; });
+            const bool hub = deg > kHubDeg, shortrow = deg <= kPrShortRow;
+            // short rows: the lane's own row, all loads issued before the
+            // in-order sum; longer rows: the wave's chunked sum
+            double sum = 0.0;
+            if (shortrow) {
+                int32_t u[kPrShortRow];
+                double x[kPrShortRow];
+#pragma unroll
+                for (int j = 0; j < kPrShortRow; ++j) u[j] = j < deg ? ci[beg + j] : 0;
+#pragma unroll
+                for (int j = 0; j < kPrShortRow; ++j) x[j] = j < deg ? sh[u[j]] : 0.0;
+#pragma unroll
+                for (int j = 0; j < kPrShortRow; ++j)
+                    if (j < deg) sum += x[j];
+            }
+            const double chunked = wave_chunk_sum(beg, hub || shortrow ? 0 : deg, ws,
+                                                  [&](int32_t e, int32_t) { return sh[ci[e]]; });
+            if (!shortrow) sum = chunked;
             if (v < n && !hub) {
                 const double val = teleport + delta * sum;
                 my_diff += fabs(val - pr[v]);
