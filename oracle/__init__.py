@@ -15,6 +15,9 @@ Contents
   computation in StarPlat"; pull form in the Appendix) converges to.
 * ``pagerank``: the paper's pull PageRank (Appendix, Fig. "PR computation
   in StarPlat"), double buffered, in numpy float64 (``pagerank.py``).
+* ``triangles`` / ``triangles_at``: the paper's node-iterator triangle count
+  (Appendix, Fig. "TC computation in StarPlat"), and the count through one
+  vertex, in C (``tc_oracle.c``).
 * ``csr_from_edges``: the CSR the paper's graph library stores (Section 2.3.1
   "Data Types": offsets plus concatenated neighbour lists), built from an edge
   list with plain numpy set operations.
@@ -35,7 +38,8 @@ import numpy as np
 from .pagerank import pagerank  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "bc_oracle.c"), os.path.join(_HERE, "sssp_oracle.c")]
+_SRCS = [os.path.join(_HERE, "bc_oracle.c"), os.path.join(_HERE, "sssp_oracle.c"),
+         os.path.join(_HERE, "tc_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -67,6 +71,10 @@ def _load():
         lib.oracle_source_detail.restype = ctypes.c_int
         lib.oracle_sssp.argtypes = [ctypes.c_int32, i32p, i32p, i32p, ctypes.c_int32, i32p]
         lib.oracle_sssp.restype = ctypes.c_int
+        lib.oracle_tc.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_tc.restype = ctypes.c_int
+        lib.oracle_tc_vertex.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_tc_vertex.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -134,6 +142,30 @@ def sssp(row_ptr, col_idx, weights, source: int):
     if rc != 0:
         raise ValueError("oracle_sssp rejected its input (code %d)" % rc)
     return dist[:n]
+
+
+def triangles(row_ptr, col_idx) -> int:
+    """Number of triangles (each once) of a simple undirected CSR with sorted rows."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx if len(col_idx) else np.zeros(1, np.int32))
+    out = ctypes.c_int64(0)
+    rc = lib.oracle_tc(len(rp) - 1, rpp, cip, ctypes.byref(out))
+    if rc != 0:
+        raise ValueError("oracle_tc rejected its input (code %d)" % rc)
+    return int(out.value)
+
+
+def triangles_at(row_ptr, col_idx, v: int) -> int:
+    """Triangles through vertex v (adjacent pairs of its neighbours)."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx if len(col_idx) else np.zeros(1, np.int32))
+    out = ctypes.c_int64(0)
+    rc = lib.oracle_tc_vertex(len(rp) - 1, rpp, cip, int(v), ctypes.byref(out))
+    if rc != 0:
+        raise ValueError("oracle_tc_vertex rejected its input (code %d)" % rc)
+    return int(out.value)
 
 
 def sigma_flag(sigma_max: float) -> bool:
