@@ -4,8 +4,8 @@
  *
  * The library computes Brandes betweenness centrality over a source list on
  * a simple, undirected, unweighted graph held as int32 CSR, on one AMD GPU,
- * single-source shortest paths once the graph is given edge weights, and
- * PageRank.
+ * single-source shortest paths once the graph is given edge weights,
+ * PageRank and triangle counts.
  * The operation is the paper's computeBC (Appendix, Fig. "BC computation in
  * StarPlat"): BC is zeroed, then for every source a level-synchronous
  * breadth-first pass counts shortest paths (sigma[w] += sigma[v] over BFS-DAG
@@ -84,6 +84,11 @@ const char *sp_last_error(void);
 
 /* Library version as major * 10000 + minor * 100 + patch. */
 int32_t sp_version(void);
+
+/* First 8 bytes (little-endian) of the SHA-256 of this header file as the
+ * library was built from it.  A binding compares it with the header it was
+ * written against before exchanging any struct. */
+uint64_t sp_header_hash(void);
 
 /* ------------------------------------------------------------------------
  * Graphs (paper Section 2.3.1 "Data Types" and Section 3.1 "Graph
@@ -330,6 +335,35 @@ sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, d
 
 /* Counters of the last sp_pagerank call on the calling thread. */
 sp_status sp_pagerank_get_last_stats(sp_pagerank_stats *out);
+
+/* ------------------------------------------------------------------------
+ * Triangle counting (paper Appendix, Fig. "TC computation in StarPlat")
+ *
+ * The number of triangles of the graph, each counted once: the count the
+ * paper's node iterator produces (for every vertex v, the adjacent pairs
+ * (u, w) of neighbours with u < v < w).  The library counts every triangle
+ * once at its lowest edge under the (degree, id) order, which bounds the
+ * work by O(m^1.5); the number is the same.  The graph must be simple and
+ * undirected (each edge stored in both rows once, no self-loops), else
+ * SP_ERR_INVALID_ARGUMENT.  The oriented rows (8 bytes per undirected edge +
+ * 4 per vertex) are built on the first call and kept with the graph.
+ * ------------------------------------------------------------------------ */
+
+typedef struct sp_tc_stats {
+    int64_t triangles;
+    int64_t oriented_edges; /* entries of the oriented rows (undirected edges) */
+    double build_ms;        /* orienting the rows (0 when they were already built) */
+    double count_ms;        /* the counting kernel (HIP events) */
+} sp_tc_stats;
+
+/*   out_count       host: receives the number of triangles.
+ *   out_per_vertex  device uint64[V] (nullable): triangles through each vertex
+ *                   (they sum to three times the count).
+ * Synchronises the stream. */
+sp_status sp_triangle_count(sp_graph g, int64_t *out_count, uint64_t *out_per_vertex, sp_stream s);
+
+/* Counters of the last sp_triangle_count call on the calling thread. */
+sp_status sp_tc_get_last_stats(sp_tc_stats *out);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (measurement support)

@@ -75,6 +75,8 @@ def _load():
         lib.oracle_tc.restype = ctypes.c_int
         lib.oracle_tc_vertex.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
         lib.oracle_tc_vertex.restype = ctypes.c_int
+        lib.oracle_tc_each.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_tc_each.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -166,6 +168,19 @@ def triangles_at(row_ptr, col_idx, v: int) -> int:
     if rc != 0:
         raise ValueError("oracle_tc_vertex rejected its input (code %d)" % rc)
     return int(out.value)
+
+
+def triangles_each(row_ptr, col_idx):
+    """int64[V]: triangles through every vertex (one call)."""
+    lib = _load()
+    rp, rpp = _i32(row_ptr)
+    ci, cip = _i32(col_idx if len(col_idx) else np.zeros(1, np.int32))
+    n = len(rp) - 1
+    out = np.zeros(max(n, 1), np.int64)
+    rc = lib.oracle_tc_each(n, rpp, cip, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError("oracle_tc_each rejected its input (code %d)" % rc)
+    return out[:n]
 
 
 def sigma_flag(sigma_max: float) -> bool:

@@ -58,3 +58,11 @@ int oracle_tc_vertex(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, 
     *out = count;
     return 0;
 }
+
+/* oracle_tc_vertex for every vertex: out[v] for v in [0, n). */
+int oracle_tc_each(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int64_t *out) {
+    if (n < 0 || !row_ptr || (n > 0 && !out)) return 1;
+    for (int32_t v = 0; v < n; ++v)
+        if (oracle_tc_vertex(n, row_ptr, col_idx, v, out + v) != 0) return 1;
+    return 0;
+}

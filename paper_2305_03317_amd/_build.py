@@ -22,7 +22,8 @@ SP_LIB = os.path.join(HERE, "libsp.so")
 GRAPH_LIB = os.path.join(HERE, "libspgraph.so")
 
 HIP_SOURCES = ["api.hip", "source_path.hip", "batch_path.hip", "server.hip", "profile.hip", "autotune.hip",
-               "sssp_path.hip", "pr_path.hip"]
+               "sssp_path.hip", "pr_path.hip",
+               "tc_path.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -46,14 +47,25 @@ def build_graphgen() -> str:
     return GRAPH_LIB
 
 
+def header_hash() -> int:
+    """First 8 bytes of the sha256 of include/sp.h: compiled into the library
+    (sp_header_hash) and checked by the binding when it loads, so a library
+    built from another version of the header is refused instead of
+    exchanging structs of the wrong size."""
+    import hashlib
+    with open(os.path.join(ROOT, "include", "sp.h"), "rb") as f:
+        return int.from_bytes(hashlib.sha256(f.read()).digest()[:8], "little")
+
+
 def build_sp(jobs: int = 4) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     cmds = []
+    flags = HIP_FLAGS + ["-DSP_HEADER_HASH=%#xull" % header_hash()]
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmds.append([HIPCC, *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC, *flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(_run, cmds))
     tmp = SP_LIB + ".tmp%d" % os.getpid()

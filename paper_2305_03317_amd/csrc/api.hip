@@ -378,6 +378,7 @@ static void release_sssp_ws(sp_graph g, SsspWorkspace *ws) {
 }
 
 static thread_local sp_pagerank_stats g_pr_stats;
+static thread_local sp_tc_stats g_tc_stats;
 
 static sp_status acquire_pr_ws(sp_graph g, PrWorkspace **out) {
     {
@@ -487,6 +488,8 @@ const char *sp_status_string(sp_status s) {
 const char *sp_last_error(void) { return g_err; }
 
 int32_t sp_version(void) { return 100; }
+
+uint64_t sp_header_hash(void) { return SP_HEADER_HASH; }
 
 sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
                           const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out) {
@@ -606,6 +609,9 @@ sp_status sp_graph_release(sp_graph g) {
         delete ws;
     }
     free_weights(g);
+    dev_free(g->tc_orp);
+    dev_free(g->tc_oci);
+    dev_free(g->tc_osrc);
     dev_free(g->hub_static);
     dev_free(g->owner_static);
     dev_free(g->row_ptr);
@@ -1089,6 +1095,58 @@ sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, d
 sp_status sp_pagerank_get_last_stats(sp_pagerank_stats *out) {
     if (!out) return SP_ERR_INVALID_ARGUMENT;
     *out = g_pr_stats;
+    return SP_OK;
+}
+
+sp_status sp_triangle_count(sp_graph g, int64_t *out_count, uint64_t *out_per_vertex, sp_stream s) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!g || !out_count) {
+        set_error("sp_triangle_count: null graph or output");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    g_tc_stats = sp_tc_stats{};
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)s;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    unsigned long long *d_total = nullptr;
+    struct Cleanup {
+        hipEvent_t *ev[3];
+        unsigned long long **p;
+        ~Cleanup() {
+            for (auto *e : ev)
+                if (*e) (void)hipEventDestroy(*e);
+            dev_free(*p);
+        }
+    } cleanup{{&e0, &e1, &e2}, &d_total};
+    SP_HIP(hipEventCreate(&e0));
+    SP_HIP(hipEventCreate(&e1));
+    SP_HIP(hipEventCreate(&e2));
+    SP_TRY(dev_alloc((void **)&d_total, sizeof(unsigned long long)));
+    const bool built = g->tc_orp != nullptr;
+    SP_HIP(hipEventRecord(e0, st));
+    SP_TRY(ensure_oriented(g, st));
+    SP_HIP(hipEventRecord(e1, st));
+    SP_TRY(tc_run(g, d_total, (unsigned long long *)out_per_vertex, st));
+    SP_HIP(hipEventRecord(e2, st));
+    unsigned long long total = 0;
+    SP_HIP(hipMemcpyAsync(&total, d_total, sizeof(total), hipMemcpyDeviceToHost, st));
+    SP_HIP(hipStreamSynchronize(st));
+    float b_ms = 0.f, c_ms = 0.f;
+    SP_HIP(hipEventElapsedTime(&b_ms, e0, e1));
+    SP_HIP(hipEventElapsedTime(&c_ms, e1, e2));
+    *out_count = (int64_t)total;
+    g_tc_stats.triangles = (int64_t)total;
+    g_tc_stats.oriented_edges = g->tc_m;
+    g_tc_stats.build_ms = built ? 0.0 : b_ms;
+    g_tc_stats.count_ms = c_ms;
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_tc_get_last_stats(sp_tc_stats *out) {
+    if (!out) return SP_ERR_INVALID_ARGUMENT;
+    *out = g_tc_stats;
     return SP_OK;
 }
 

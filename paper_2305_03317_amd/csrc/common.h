@@ -84,6 +84,12 @@ struct sp_graph_s {
     // chunk; built on first use by the whole-graph kernels (ensure_static_hubs).
     sp::HubEntry *hub_static = nullptr;  // device, n_hubs (>= 1)
     int32_t *owner_static = nullptr;     // device, hub_chunks (>= 1)
+    // Triangle counting: rows oriented toward higher (degree, id) rank, built
+    // on first use (ensure_oriented): offsets, entries, and each entry's row.
+    int32_t *tc_orp = nullptr;       // device, n + 1
+    int32_t *tc_oci = nullptr;       // device, tc_m (>= 1)
+    int32_t *tc_osrc = nullptr;      // device, tc_m (>= 1)
+    int64_t tc_m = 0;
     int32_t max_weight = 0;
     size_t weight_bytes = 0;
     std::vector<sp::SsspWorkspace *> sssp_pool;
@@ -173,7 +179,7 @@ struct LevelCtl {
 enum ProfKind : int {
     P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
     P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_EXPAND, P_MS_DELTA, P_MS_DELTA_HUB,
-    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL, P_PR_PULL, P_PR_HUB,
+    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL, P_PR_PULL, P_PR_HUB, P_TC_COUNT,
     P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
@@ -438,6 +444,15 @@ struct PrResult {
 // PageRank of every vertex into out_pr (device, V doubles).
 sp_status pr_run(sp_graph g, PrWorkspace &ws, double beta, double delta, int32_t max_iter,
                  double *out_pr, const PrOpts &o, hipStream_t s, PrResult *res);
+
+// ---------------------------------------------------------------------------
+// Triangle counting (tc_path.hip)
+// ---------------------------------------------------------------------------
+// Builds the oriented rows once per graph (thread-safe).
+sp_status ensure_oriented(sp_graph g, hipStream_t s);
+// Adds the graph's triangle count to *d_total (device, zeroed here) and, when
+// per is not null, each vertex's triangle count to per[v] (zeroed here).
+sp_status tc_run(sp_graph g, unsigned long long *d_total, unsigned long long *per, hipStream_t s);
 
 // Builds g->hub_static / g->owner_static once (thread-safe).
 sp_status ensure_static_hubs(sp_graph g, hipStream_t s);

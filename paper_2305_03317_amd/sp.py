@@ -73,6 +73,11 @@ class sp_pagerank_stats(ctypes.Structure):
                 ("diff", ctypes.c_double), ("device_ms", ctypes.c_double)]
 
 
+class sp_tc_stats(ctypes.Structure):
+    _fields_ = [("triangles", ctypes.c_int64), ("oriented_edges", ctypes.c_int64),
+                ("build_ms", ctypes.c_double), ("count_ms", ctypes.c_double)]
+
+
 class sp_server_config(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_size_t), ("max_batch", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
@@ -108,6 +113,7 @@ SIGNATURES = [
     ("sp_status_string", ctypes.c_char_p, [_ST]),
     ("sp_last_error", ctypes.c_char_p, []),
     ("sp_version", ctypes.c_int32, []),
+    ("sp_header_hash", ctypes.c_uint64, []),
     ("sp_graph_upload", _ST, [ctypes.c_int32, ctypes.c_int64, _VP, _VP, ctypes.c_uint32, _VP,
                               ctypes.POINTER(_VP)]),
     ("sp_graph_release", _ST, [_VP]),
@@ -126,6 +132,8 @@ SIGNATURES = [
     ("sp_pagerank", _ST, [_VP, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _VP,
                           ctypes.POINTER(sp_pagerank_config), _VP]),
     ("sp_pagerank_get_last_stats", _ST, [ctypes.POINTER(sp_pagerank_stats)]),
+    ("sp_triangle_count", _ST, [_VP, ctypes.POINTER(ctypes.c_int64), _VP, _VP]),
+    ("sp_tc_get_last_stats", _ST, [ctypes.POINTER(sp_tc_stats)]),
     ("sp_profile_enable", _ST, [ctypes.c_int32]),
     ("sp_profile_read", _ST, [ctypes.POINTER(sp_kernel_profile), ctypes.c_int32, _I32P]),
     ("sp_server_create", _ST, [ctypes.POINTER(sp_server_config), ctypes.POINTER(_VP)]),
@@ -155,6 +163,10 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        from . import _build
+        if L.sp_header_hash() != _build.header_hash():
+            raise RuntimeError("libsp.so was built from another version of include/sp.h "
+                               "(rebuild with python -m paper_2305_03317_amd._build)")
         _lib = L
     return _lib
 
@@ -402,6 +414,22 @@ def sp_pagerank(g: Graph, beta: float = 1e-6, delta: float = 0.85, max_iter: int
 def sp_pagerank_get_last_stats() -> dict:
     s = sp_pagerank_stats()
     _check(lib().sp_pagerank_get_last_stats(ctypes.byref(s)), "sp_pagerank_get_last_stats")
+    return _struct_dict(s)
+
+
+def sp_triangle_count(g: Graph, per_vertex: bool = False, stream=None):
+    """(triangle count, per-vertex uint64 CUDA tensor [V] or None)."""
+    torch = _torch()
+    per = torch.empty(max(g.n, 1), dtype=torch.uint64, device="cuda") if per_vertex else None
+    out = ctypes.c_int64()
+    _check(lib().sp_triangle_count(g.handle, ctypes.byref(out), per.data_ptr() if per is not None else None,
+                                   _stream(stream)), "sp_triangle_count")
+    return out.value, (per[:g.n] if per is not None else None)
+
+
+def sp_tc_get_last_stats() -> dict:
+    s = sp_tc_stats()
+    _check(lib().sp_tc_get_last_stats(ctypes.byref(s)), "sp_tc_get_last_stats")
     return _struct_dict(s)
 
 

@@ -37,6 +37,13 @@ def test_binding_covers_every_declared_symbol():
     assert set(declared_functions()) == bound
 
 
+def test_library_was_built_from_this_header():
+    """A library built from another version of sp.h would exchange structs of
+    another size with the binding (and overwrite host memory)."""
+    from paper_2305_03317_amd import _build
+    assert sp.lib().sp_header_hash() == _build.header_hash()
+
+
 def test_status_strings_and_version():
     assert sp.sp_status_string(sp.SP_OK) == "ok"
     assert "1e300" in sp.sp_status_string(sp.SP_WARN_SIGMA_LARGE)
@@ -52,7 +59,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
                "sp_server_config": sp.sp_server_config, "sp_server_stats": sp.sp_server_stats,
                "sp_kernel_profile": sp.sp_kernel_profile, "sp_sssp_config": sp.sp_sssp_config,
                "sp_sssp_stats": sp.sp_sssp_stats, "sp_pagerank_config": sp.sp_pagerank_config,
-               "sp_pagerank_stats": sp.sp_pagerank_stats}
+               "sp_pagerank_stats": sp.sp_pagerank_stats, "sp_tc_stats": sp.sp_tc_stats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
@@ -133,6 +140,8 @@ def test_sssp_calls_reject_bad_arguments_on_the_host():
     assert {"SP_SSSP_AUTO", "SP_SSSP_PUSH", "SP_SSSP_PULL"} <= set(dir(sp))
     assert L.sp_pagerank(None, 1e-6, 0.85, 10, None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
     assert L.sp_pagerank_get_last_stats(None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_triangle_count(None, None, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_tc_get_last_stats(None) == sp.SP_ERR_INVALID_ARGUMENT
 
 
 def test_header_constants_match_binding():

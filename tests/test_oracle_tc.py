@@ -83,6 +83,8 @@ def test_networkx_per_vertex(oracle_mod):
     assert oracle_mod.triangles(rp, ci) == sum(t.values()) // 3
     for v in range(0, len(rp) - 1, 7):
         assert oracle_mod.triangles_at(rp, ci, v) == t[v]
+    each = oracle_mod.triangles_each(rp, ci)
+    assert list(each) == [t[v] for v in range(len(rp) - 1)]
 
 
 def test_rejects_bad_input(oracle_mod):
@@ -136,6 +138,9 @@ class _Variant:
 
     def triangles_at(self, rp, ci, v):
         return self._call(self.lib.oracle_tc_vertex, rp, ci, int(v))
+
+    def triangles_each(self, rp, ci):
+        return [self.triangles_at(rp, ci, v) for v in range(len(rp) - 1)]
 
 
 def battery_passes(m) -> bool:
