@@ -24,8 +24,8 @@ doubles as a parity check of this run), the serving workload (eight
 resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS),
 single-source shortest paths on the RMAT and road graphs with the paper's
 uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle),
-and PageRank on the same graphs (time per iteration, kernel roofline, numpy
-oracle).
+PageRank on the same graphs (time per iteration, kernel roofline, numpy
+oracle), and the triangle count of the RMAT graph.
 
 Prints one JSON line.
 """
@@ -77,6 +77,10 @@ BYTE_MODEL = {
     # read, value and share written), edges = adjacency entries (column id,
     # neighbour's share); hub chunks count their entries the same way
     "pr_pull": dict(items=28, edges=12),
+    # triangle count: edges = list elements walked (one 4-byte id each); the
+    # per-entry reads (row id, neighbour id, four offsets) are added
+    # separately from the oriented-entry count
+    "tc_count": dict(edges=4),
 }
 FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_expand")
 
@@ -236,6 +240,70 @@ def pagerank_benchmark(sp, torch, workload, iterations):
                        "pass": bool(np.max(np.abs(got - ref) / ref) <= 1e-9)}}
 
 
+def tc_benchmark(sp, torch, workload):
+    """Triangle count of a benchmark graph: the first call builds the
+    oriented rows (kept with the graph), later calls only count.  The
+    oracle's node iterator is quadratic in hub degree, so the CPU baseline
+    runs it on the same recipe at RMAT scale 16 (and the GPU beside it)."""
+    import numpy as np
+    import oracle
+    from paper_2305_03317_amd import graphs
+    k = WORKLOADS[workload]
+    rp, ci, _, spec = graphs.workload(k)
+    m = len(ci) // 2
+    g = sp.sp_graph_upload(rp, ci)
+    count, _ = sp.sp_triangle_count(g)
+    build_ms = sp.sp_tc_get_last_stats()["build_ms"]
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        again, _ = sp.sp_triangle_count(g)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        assert again == count
+    count_s = float(np.min(times))
+    sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
+    sp.sp_triangle_count(g)
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
+    sp.sp_triangle_count(g)
+    counted = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    p, c = prof.get("tc_count"), counted.get("tc_count", {})
+    roofline = None
+    if p:
+        alg = algorithmic_bytes("tc_count", c) + 24 * m
+        achieved = alg / (p["total_ms"] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "tc_count",
+                    "avg_launch_ms": round(p["total_ms"] / max(p["launches"], 1), 4),
+                    "list_elements_walked": int(c.get("edges", 0))}
+    g.release()
+    srp, sci = graphs.rmat(16, 16, graphs.RMAT_ABC, 1000 + k)
+    sg = sp.sp_graph_upload(srp, sci)
+    sp.sp_triangle_count(sg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    small, _ = sp.sp_triangle_count(sg)
+    torch.cuda.synchronize()
+    small_s = time.perf_counter() - t0
+    sg.release()
+    t0 = time.perf_counter()
+    ref = oracle.triangles(srp, sci)
+    cpu_s = time.perf_counter() - t0
+    sm = len(sci) // 2
+    return {"workload": spec["name"], "triangles": count, "count_ms": round(count_s * 1e3, 3),
+            "build_ms": round(build_ms, 3), "teps": m / count_s,
+            "unit": "TEPS (undirected edges / count time)", "roofline": roofline,
+            "rmat16_gpu_teps": sm / small_s,
+            "cpu_baseline": {"value": sm / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                             "sample": "node iterator on RMAT scale 16 of the same recipe (seed %d), "
+                                       "single-threaded C oracle, %.1f s" % (1000 + k, cpu_s)},
+            "parity": {"graph": "rmat-16", "gpu": small, "oracle": ref, "pass": small == ref}}
+
+
 def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
     """Serving workload: eight resident graphs, seeded requests (graph uniform,
     1..512 sources log-uniform), continuous batching by the library's server.
@@ -339,6 +407,10 @@ def main():
                     help="SSSP legs as workload:sources, comma-separated ('' = skip)")
     ap.add_argument("--pagerank", default="rmat-22:20,road-4096:20",
                     help="PageRank legs as workload:iterations, comma-separated ('' = skip)")
+    ap.add_argument("--tc", default="rmat-22",
+                    help="triangle-count workloads, comma-separated ('' = skip)")
+    ap.add_argument("--only-tc", action="store_true",
+                    help="run only the triangle-count legs and print their JSON object")
     ap.add_argument("--only-sssp", action="store_true",
                     help="run only the SSSP legs and print their JSON object")
     ap.add_argument("--only-pagerank", action="store_true",
@@ -391,8 +463,10 @@ def main():
         rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
-    if args.only_sssp or args.only_pagerank:
+    if args.only_sssp or args.only_pagerank or args.only_tc:
         legs = {}
+        if args.only_tc:
+            legs["triangles"] = {wl: tc_benchmark(sp, torch, wl) for wl in filter(None, args.tc.split(","))}
         if args.only_sssp:
             legs["sssp"] = {wl: sssp_benchmark(sp, torch, wl, int(ns)) for wl, ns in
                             (leg.split(":") for leg in filter(None, args.sssp_sources.split(",")))}
@@ -574,6 +648,7 @@ def main():
     for leg in filter(None, args.pagerank.split(",")):
         wl, it = leg.split(":")
         pagerank[wl] = pagerank_benchmark(sp, torch, wl, int(it))
+    triangles = {wl: tc_benchmark(sp, torch, wl) for wl in filter(None, args.tc.split(","))}
     serving = None
     if args.serving_requests > 0:
         serving = serving_benchmark(sp, torch, args.serving_requests)
@@ -616,6 +691,7 @@ def main():
         "serving": serving,
         "sssp": sssp or None,
         "pagerank": pagerank or None,
+        "triangles": triangles or None,
     }
     print(json.dumps(line))
 

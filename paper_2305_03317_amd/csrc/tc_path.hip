@@ -15,10 +15,11 @@
 // Kernels: the oriented rows are built once per graph (out-degree by rank,
 // a two-level scan, a filtering copy that also records each oriented entry's
 // row; rows longer than kHubDeg are counted and copied by a block each), then
-// one lane per oriented entry (v, u) walks the shorter of N+(v)
-// and N+(u) and binary-searches each element in the longer one, the search
-// window shrinking as the walk moves up (both are sorted).  Lane counts are
-// summed per block in a fixed order and added with one 64-bit atomic.
+// each oriented entry (v, u) intersects N+(v) and N+(u) (both sorted) by
+// binary-searching the elements of the shorter list in the longer one: by
+// its own lane when the shorter list is short, else by the whole wave.
+// Lane counts are summed per block in a fixed order and added with one
+// 64-bit atomic.
 #include "common.h"
 #include "devutil.h"
 #include "levels.h"
@@ -178,8 +179,16 @@ __device__ __forceinline__ int32_t lower_bound(const int32_t *__restrict__ a, in
     return lo;
 }
 
-// One lane per oriented entry (v, u): |N+(v) & N+(u)|.  With `per` the three
-// vertices of every triangle found get one count each.
+// |N+(v) & N+(u)| for the oriented entries of a wave (64 consecutive
+// entries, one per lane).  An entry whose shorter list has at most
+// kTcLaneWork elements is intersected by its own lane, which walks the
+// shorter list and binary-searches each element in the longer one, the
+// window shrinking as the walk moves up.  Longer ones are taken by the whole
+// wave in turn: lane j searches elements j, j + 64, ... of the shorter list
+// in the whole longer one.  With `per` the three vertices of every triangle
+// found get one count each.
+constexpr int32_t kTcLaneWork = 32;
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_tc_count(const int32_t *__restrict__ orp,
                                                  const int32_t *__restrict__ oci,
@@ -187,28 +196,57 @@ __global__ __launch_bounds__(BS) void k_tc_count(const int32_t *__restrict__ orp
                                                  unsigned long long *total,
                                                  unsigned long long *per, unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
+    const int lane = lane_id();
     unsigned long long mine = 0, probes = 0;
-    const int64_t stride = (int64_t)gridDim.x * BS;
-    for (int64_t e = (int64_t)blockIdx.x * BS + threadIdx.x; e < m; e += stride) {
-        const int32_t v = osrc[e], u = oci[e];
-        int32_t sb = orp[v], se = orp[v + 1], lb = orp[u], le = orp[u + 1];
-        if (se - sb > le - lb) {  // walk the shorter list
-            int32_t t = sb; sb = lb; lb = t;
-            t = se; se = le; le = t;
+    auto hit = [&](int32_t v, int32_t u, int32_t w) {
+        ++mine;
+        if (per) {
+            atomicAdd(&per[v], 1ull);
+            atomicAdd(&per[u], 1ull);
+            atomicAdd(&per[w], 1ull);
         }
-        int32_t pos = lb;
-        for (int32_t i = sb; i < se && pos < le; ++i) {
-            const int32_t w = oci[i];
-            pos = lower_bound(oci, pos, le, w);
-            ++probes;
-            if (pos < le && oci[pos] == w) {
-                ++mine;
-                if (per) {
-                    atomicAdd(&per[v], 1ull);
-                    atomicAdd(&per[u], 1ull);
-                    atomicAdd(&per[w], 1ull);
+    };
+    const int64_t stride = (int64_t)gridDim.x * BS;
+    for (int64_t e0 = (int64_t)blockIdx.x * BS + threadIdx.x - lane; e0 < m; e0 += stride) {
+        const int64_t e = e0 + lane;
+        int32_t v = 0, u = 0, sb = 0, se = 0, lb = 0, le = 0;
+        if (e < m) {
+            v = osrc[e];
+            u = oci[e];
+            sb = orp[v];
+            se = orp[v + 1];
+            lb = orp[u];
+            le = orp[u + 1];
+            if (se - sb > le - lb) {  // walk the shorter list
+                int32_t t = sb; sb = lb; lb = t;
+                t = se; se = le; le = t;
+            }
+        }
+        const bool alone = se - sb <= kTcLaneWork;
+        if (alone) {
+            int32_t pos = lb;
+            for (int32_t i = sb; i < se && pos < le; ++i) {
+                const int32_t w = oci[i];
+                pos = lower_bound(oci, pos, le, w);
+                ++probes;
+                if (pos < le && oci[pos] == w) {
+                    hit(v, u, w);
+                    ++pos;
                 }
-                ++pos;
+            }
+        }
+        unsigned long long big = __ballot(!alone);
+        while (big) {
+            const int src = __ffsll((long long)big) - 1;
+            big &= big - 1;
+            const int32_t bv = __shfl(v, src, kWave), bu = __shfl(u, src, kWave);
+            const int32_t bsb = __shfl(sb, src, kWave), bse = __shfl(se, src, kWave);
+            const int32_t blb = __shfl(lb, src, kWave), ble = __shfl(le, src, kWave);
+            for (int32_t i = bsb + lane; i < bse; i += kWave) {
+                const int32_t w = oci[i];
+                const int32_t pos = lower_bound(oci, blb, ble, w);
+                ++probes;
+                if (pos < ble && oci[pos] == w) hit(bv, bu, w);
             }
         }
     }
