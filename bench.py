@@ -173,6 +173,7 @@ def sssp_benchmark(sp, torch, workload, n_sources):
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
                     "avg_launch_ms": dom[1]["avg_launch_ms"]}
+        attach_traffic(roofline, "sssp_" + workload)
     t0 = time.perf_counter()
     ref = oracle.sssp(rp, ci, w, srcs[0])
     cpu_s = time.perf_counter() - t0
@@ -234,6 +235,7 @@ def pagerank_benchmark(sp, torch, workload, iterations):
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
                     "avg_launch_ms": dom[1]["avg_launch_ms"]}
+        attach_traffic(roofline, "pagerank_" + workload)
     t0 = time.perf_counter()
     ref, _, _ = oracle.pagerank(rp, ci, 0.0, 0.85, iterations, iterations=iterations)
     cpu_s = time.perf_counter() - t0
@@ -291,6 +293,7 @@ def tc_benchmark(sp, torch, workload):
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "tc_count",
                     "avg_launch_ms": round(p["total_ms"] / max(p["launches"], 1), 4),
                     "list_elements_walked": int(c.get("edges", 0))}
+        attach_traffic(roofline, "tc_" + workload)
     g.release()
     srp, sci = graphs.rmat(16, 16, graphs.RMAT_ABC, 1000 + k)
     sg = sp.sp_graph_upload(srp, sci)
@@ -313,6 +316,20 @@ def tc_benchmark(sp, torch, workload):
                              "sample": "node iterator on RMAT scale 16 of the same recipe (seed %d), "
                                        "single-threaded C oracle, %.1f s" % (1000 + k, cpu_s)},
             "parity": {"graph": "rmat-16", "gpu": small, "oracle": ref, "pass": small == ref}}
+
+
+def attach_traffic(roofline, profile_name):
+    """roofline["traffic"]: calibrated HBM bytes per launch of its kernel from
+    the committed counter summary `profile_name`, while the kernel sources
+    are unchanged (else it stays null)."""
+    if not roofline:
+        return roofline
+    doc = load_traffic(profile_name)
+    fam = doc["families"].get(roofline["kernel"]) if doc else None
+    if fam:
+        roofline["traffic"] = round(fam["traffic_bytes_per_launch"])
+        roofline["traffic_source"] = doc["path"]
+    return roofline
 
 
 def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):

@@ -40,6 +40,7 @@ FAMILY = {
     "k_ms_expand": "ms_expand", "k_ms_bc": "ms_bc", "k_src_topdown": "src_topdown", "k_src_bottomup": "src_bottomup",
     "k_src_sigma": "src_sigma", "k_src_sigma_hub": "src_sigma_hub", "k_src_delta": "src_delta",
     "k_src_delta_hub": "src_delta_hub", "k_sssp_push": "sssp_push", "k_sssp_pull": "sssp_pull",
+    "k_pr_pull": "pr_pull", "k_pr_hub_fin": "pr_hub", "k_tc_count": "tc_count",
 }
 
 
