@@ -253,7 +253,7 @@ def pagerank_benchmark(sp, torch, workload, iterations):
                        "pass": bool(np.max(np.abs(got - ref) / ref) <= 1e-9)}}
 
 
-def tc_benchmark(sp, torch, workload):
+def tc_benchmark(sp, torch, workload, small_scale=16):
     """Triangle count of a benchmark graph: the first call builds the
     oriented rows (kept with the graph), later calls only count.  The
     oracle's node iterator is quadratic in hub degree, so the CPU baseline
@@ -295,7 +295,12 @@ def tc_benchmark(sp, torch, workload):
                     "list_elements_walked": int(c.get("edges", 0))}
         attach_traffic(roofline, "tc_" + workload)
     g.release()
-    srp, sci = graphs.rmat(16, 16, graphs.RMAT_ABC, 1000 + k)
+    out = {"workload": spec["name"], "triangles": count, "count_ms": round(count_s * 1e3, 3),
+           "build_ms": round(build_ms, 3), "teps": m / count_s,
+           "unit": "TEPS (undirected edges / count time)", "roofline": roofline}
+    if small_scale <= 0:
+        return out
+    srp, sci = graphs.rmat(small_scale, 16, graphs.RMAT_ABC, 1000 + k)
     sg = sp.sp_graph_upload(srp, sci)
     sp.sp_triangle_count(sg)
     torch.cuda.synchronize()
@@ -308,14 +313,12 @@ def tc_benchmark(sp, torch, workload):
     ref = oracle.triangles(srp, sci)
     cpu_s = time.perf_counter() - t0
     sm = len(sci) // 2
-    return {"workload": spec["name"], "triangles": count, "count_ms": round(count_s * 1e3, 3),
-            "build_ms": round(build_ms, 3), "teps": m / count_s,
-            "unit": "TEPS (undirected edges / count time)", "roofline": roofline,
-            "rmat16_gpu_teps": sm / small_s,
-            "cpu_baseline": {"value": sm / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
-                             "sample": "node iterator on RMAT scale 16 of the same recipe (seed %d), "
-                                       "single-threaded C oracle, %.1f s" % (1000 + k, cpu_s)},
-            "parity": {"graph": "rmat-16", "gpu": small, "oracle": ref, "pass": small == ref}}
+    out.update({"small_gpu_teps": sm / small_s,
+                "cpu_baseline": {"value": sm / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                                 "sample": "node iterator on RMAT scale %d of the same recipe (seed %d), "
+                                           "single-threaded C oracle, %.1f s" % (small_scale, 1000 + k, cpu_s)},
+                "parity": {"graph": "rmat-%d" % small_scale, "gpu": small, "oracle": ref, "pass": small == ref}})
+    return out
 
 
 def attach_traffic(roofline, profile_name):
@@ -437,6 +440,8 @@ def main():
                     help="PageRank legs as workload:iterations, comma-separated ('' = skip)")
     ap.add_argument("--tc", default="rmat-22",
                     help="triangle-count workloads, comma-separated ('' = skip)")
+    ap.add_argument("--tc-small-scale", type=int, default=16,
+                    help="RMAT scale of the triangle-count CPU baseline and parity graph (0 = skip)")
     ap.add_argument("--only-tc", action="store_true",
                     help="run only the triangle-count legs and print their JSON object")
     ap.add_argument("--only-sssp", action="store_true",
@@ -494,7 +499,8 @@ def main():
     if args.only_sssp or args.only_pagerank or args.only_tc:
         legs = {}
         if args.only_tc:
-            legs["triangles"] = {wl: tc_benchmark(sp, torch, wl) for wl in filter(None, args.tc.split(","))}
+            legs["triangles"] = {wl: tc_benchmark(sp, torch, wl, args.tc_small_scale)
+                                 for wl in filter(None, args.tc.split(","))}
         if args.only_sssp:
             legs["sssp"] = {wl: sssp_benchmark(sp, torch, wl, int(ns)) for wl, ns in
                             (leg.split(":") for leg in filter(None, args.sssp_sources.split(",")))}
@@ -676,7 +682,7 @@ def main():
     for leg in filter(None, args.pagerank.split(",")):
         wl, it = leg.split(":")
         pagerank[wl] = pagerank_benchmark(sp, torch, wl, int(it))
-    triangles = {wl: tc_benchmark(sp, torch, wl) for wl in filter(None, args.tc.split(","))}
+    triangles = {wl: tc_benchmark(sp, torch, wl, args.tc_small_scale) for wl in filter(None, args.tc.split(","))}
     serving = None
     if args.serving_requests > 0:
         serving = serving_benchmark(sp, torch, args.serving_requests)

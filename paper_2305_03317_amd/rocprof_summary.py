@@ -153,8 +153,12 @@ def main():
         per = f_avg * cf + w_avg * cw
         tot = sum(fv) * cf + sum(wv) * cw
         lines.append("| %s | %d | %.2f | %.2f | %.2f | %.2f |" % (k, nd, f_avg / 2**20, w_avg / 2**20, per / 1e6, tot / 1e9))
-        fam[FAMILY[base_name(k)]] = dict(kernel=k, dispatches=nd, fetch_bytes_per_launch=f_avg * cf,
-                                         write_bytes_per_launch=w_avg * cw, traffic_bytes_per_launch=per)
+        # several instances of a family (block sizes tried by the autotuner):
+        # keep the one launched most, the configuration the timed steps use
+        f = FAMILY[base_name(k)]
+        if f not in fam or nd > fam[f]["dispatches"]:
+            fam[f] = dict(kernel=k, dispatches=nd, fetch_bytes_per_launch=f_avg * cf,
+                          write_bytes_per_launch=w_avg * cw, traffic_bytes_per_launch=per)
     os.makedirs(os.path.dirname(os.path.abspath(a.md)), exist_ok=True)
     with open(a.md, "w") as f:
         f.write("\n".join(lines) + "\n")
