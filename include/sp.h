@@ -115,6 +115,21 @@ uint64_t sp_header_hash(void);
 sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
                           const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out);
 
+/* Copy a directed graph: row u of the CSR lists the heads of u's out-edges.
+ * Same arguments as sp_graph_upload; the offsets and ids are always checked
+ * on the host (the reversed rows of incoming edges are built there and
+ * uploaded too), SP_VALIDATE adds sorted, duplicate-free rows without
+ * self-loops.  Betweenness centrality then follows edge directions (paper
+ * Section 2.3.1: the graph type offers neighbors and nodes_to; Brandes on a
+ * directed graph counts shortest directed paths): sp_bc and sp_bfs_levels
+ * run the per-source path, reading parents from the incoming rows and
+ * children from the outgoing ones; sp_bc_batch runs that same path.  The
+ * batched multi-source calls (sp_batch_levels, sp_autotune), the server,
+ * edge weights / SSSP, PageRank and triangle counting need an undirected
+ * graph and return SP_ERR_NOT_SUPPORTED. */
+sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out);
+
 /* Free the graph's device memory.  The caller must ensure no call using the
  * graph is still running.  NULL is accepted (no-op). */
 sp_status sp_graph_release(sp_graph g);

@@ -377,6 +377,11 @@ static void release_sssp_ws(sp_graph g, SsspWorkspace *ws) {
     g->sssp_pool.push_back(ws);
 }
 
+sp_status undirected_only(const char *what) {
+    set_error("%s: not available for directed graphs", what);
+    return SP_ERR_NOT_SUPPORTED;
+}
+
 static thread_local sp_pagerank_stats g_pr_stats;
 static thread_local sp_tc_stats g_tc_stats;
 
@@ -581,7 +586,82 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
         }
     }
     g->max_degree = md;
+    g->rp_in = g->row_ptr;
+    g->ci_in = g->col_idx;
     g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
+    *out = g;
+    return SP_OK;
+    SP_GUARD_END
+}
+
+sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
+                                   const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out) {
+    SP_GUARD_BEGIN
+    clear_error();
+    if (!out || n_vertices < 0 || n_vertices == INT32_MAX || nnz < 0 || nnz >= INT32_MAX || !row_ptr ||
+        (nnz > 0 && !col_idx) || (flags & ~(SP_PTR_DEVICE | SP_VALIDATE))) {
+        set_error("sp_graph_upload_directed: bad arguments");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    int dev = 0;
+    SP_TRY(check_device(&dev));
+    hipStream_t st = (hipStream_t)s;
+    // host copies: the reversed rows are built on the host
+    std::vector<int32_t> hr((size_t)n_vertices + 1), hc((size_t)nnz);
+    if (flags & SP_PTR_DEVICE) {
+        SP_HIP(hipMemcpyAsync(hr.data(), row_ptr, hr.size() * 4, hipMemcpyDeviceToHost, st));
+        if (nnz) SP_HIP(hipMemcpyAsync(hc.data(), col_idx, hc.size() * 4, hipMemcpyDeviceToHost, st));
+        SP_HIP(hipStreamSynchronize(st));
+    } else {
+        std::memcpy(hr.data(), row_ptr, hr.size() * 4);
+        if (nnz) std::memcpy(hc.data(), col_idx, hc.size() * 4);
+    }
+    // offsets and ids are always checked here (the reversal indexes by them)
+    bool ok = hr[0] == 0 && (int64_t)hr[n_vertices] == nnz;
+    for (int32_t v = 0; ok && v < n_vertices; ++v) ok = hr[v] <= hr[v + 1];
+    for (int64_t e = 0; ok && e < nnz; ++e) ok = hc[e] >= 0 && hc[e] < n_vertices;
+    if (ok && (flags & SP_VALIDATE))  // sorted, duplicate-free rows without self-loops
+        for (int32_t v = 0; ok && v < n_vertices; ++v)
+            for (int32_t e = hr[v]; ok && e < hr[v + 1]; ++e)
+                ok = hc[e] != v && (e == hr[v] || hc[e - 1] < hc[e]);
+    if (!ok) {
+        set_error("directed CSR is malformed (offsets, ids%s)",
+                  (flags & SP_VALIDATE) ? ", row order, duplicates or self-loops" : "");
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    std::vector<int32_t> ir((size_t)n_vertices + 1, 0), ic((size_t)std::max<int64_t>(nnz, 1));
+    for (int64_t e = 0; e < nnz; ++e) ir[hc[e] + 1]++;
+    for (int32_t v = 0; v < n_vertices; ++v) ir[v + 1] += ir[v];
+    {
+        std::vector<int32_t> pos(ir.begin(), ir.end() - 1);
+        for (int32_t u = 0; u < n_vertices; ++u)  // sources ascending: reversed rows come out sorted
+            for (int32_t e = hr[u]; e < hr[u + 1]; ++e) ic[pos[hc[e]]++] = u;
+    }
+    sp_graph g = nullptr;
+    SP_TRY(sp_graph_upload(n_vertices, nnz, hr.data(), hc.data(), 0, s, &g));
+    int32_t *rp_in = nullptr, *ci_in = nullptr;
+    sp_status rc = dev_alloc((void **)&rp_in, ir.size() * 4);
+    if (rc == SP_OK) rc = dev_alloc((void **)&ci_in, ic.size() * 4);
+    hipError_t e = hipSuccess;
+    if (rc == SP_OK) e = hipMemcpyAsync(rp_in, ir.data(), ir.size() * 4, hipMemcpyHostToDevice, st);
+    if (rc == SP_OK && e == hipSuccess) e = hipMemcpyAsync(ci_in, ic.data(), ic.size() * 4, hipMemcpyHostToDevice, st);
+    if (rc == SP_OK && e == hipSuccess) e = hipStreamSynchronize(st);
+    if (rc != SP_OK || e != hipSuccess) {
+        dev_free(rp_in);
+        dev_free(ci_in);
+        sp_graph_release(g);
+        if (e != hipSuccess) set_error("directed graph upload failed: %s", hipGetErrorString(e));
+        return rc != SP_OK ? rc : SP_ERR_DEVICE;
+    }
+    int32_t md = g->max_degree;
+    for (int32_t v = 0; v < n_vertices; ++v) md = std::max(md, ir[v + 1] - ir[v]);
+    g->rp_in = rp_in;
+    g->ci_in = ci_in;
+    g->directed = true;
+    g->max_degree = md;
+    g->n_hubs = 0;  // rows are never cut into hub chunks on directed graphs
+    g->hub_chunks = 0;
+    g->bytes += ir.size() * 4 + ic.size() * 4;
     *out = g;
     return SP_OK;
     SP_GUARD_END
@@ -609,6 +689,10 @@ sp_status sp_graph_release(sp_graph g) {
         delete ws;
     }
     free_weights(g);
+    if (g->directed) {
+        dev_free(g->rp_in);
+        dev_free(g->ci_in);
+    }
     dev_free(g->tc_orp);
     dev_free(g->tc_oci);
     dev_free(g->tc_osrc);
@@ -764,6 +848,8 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
     }
     SP_TRY(check_sources(g, sources, n_sources));
     SP_TRY(check_batch_cfg(cfg));
+    // Directed graphs run the per-source path (one BFS pass per source).
+    if (g->directed) return sp_bc(g, sources, n_sources, out_bc, s);
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;
     int32_t width = 64;
@@ -870,6 +956,7 @@ sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources,
         set_error("sp_batch_levels: null graph/output or n_sources outside 1..64");
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (g->directed) return undirected_only("sp_batch_levels");
     SP_TRY(check_sources(g, sources, n_sources));
     SP_TRY(check_batch_cfg(cfg));
     DeviceGuard dg(g->device);
@@ -910,6 +997,7 @@ sp_status sp_graph_set_weights(sp_graph g, const int32_t *weights, uint32_t flag
         set_error("sp_graph_set_weights: bad arguments");
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (g->directed) return undirected_only("sp_graph_set_weights");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;
     const bool on_dev = flags & SP_PTR_DEVICE;
@@ -1053,6 +1141,7 @@ sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, d
         set_error("sp_pagerank: null graph/output, beta < 0, delta outside [0, 1] or max_iter < 1");
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (g->directed) return undirected_only("sp_pagerank");
     PrOpts o;
     if (cfg) {
         if ((cfg->block_size != 0 && cfg->block_size != 128 && cfg->block_size != 256 &&
@@ -1105,6 +1194,7 @@ sp_status sp_triangle_count(sp_graph g, int64_t *out_count, uint64_t *out_per_ve
         set_error("sp_triangle_count: null graph or output");
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (g->directed) return undirected_only("sp_triangle_count");
     g_tc_stats = sp_tc_stats{};
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;

@@ -65,6 +65,11 @@ struct sp_graph_s {
     int64_t nnz = 0;
     int32_t *row_ptr = nullptr;  // device, n + 1
     int32_t *col_idx = nullptr;  // device, nnz (>= 1 element allocated)
+    // Rows of incoming edges: the same arrays as row_ptr/col_idx for an
+    // undirected graph, the reversed graph's for a directed one.
+    int32_t *rp_in = nullptr;
+    int32_t *ci_in = nullptr;
+    bool directed = false;
     int32_t max_degree = 0;
     int32_t n_hubs = 0;          // vertices of degree > kHubDeg
     int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
@@ -453,6 +458,10 @@ sp_status ensure_oriented(sp_graph g, hipStream_t s);
 // Adds the graph's triangle count to *d_total (device, zeroed here) and, when
 // per is not null, each vertex's triangle count to per[v] (zeroed here).
 sp_status tc_run(sp_graph g, unsigned long long *d_total, unsigned long long *per, hipStream_t s);
+
+// SP_ERR_NOT_SUPPORTED with a message, for entry points that need an
+// undirected graph.
+sp_status undirected_only(const char *what);
 
 // Builds g->hub_static / g->owner_static once (thread-safe).
 sp_status ensure_static_hubs(sp_graph g, hipStream_t s);

@@ -66,7 +66,7 @@ sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
 __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *queue,
                            int32_t *level_off, HubEntry *hub_list, int32_t *hub_off,
                            int32_t *hub_lvl_chunks, const int32_t *rp, int32_t src, int32_t n,
-                           long long nnz, double alpha, double beta) {
+                           long long nnz, double alpha, double beta, int32_t hub_deg) {
     const int32_t deg = rp[src + 1] - rp[src];
     c->level = 0;
     c->lo = 0;
@@ -87,7 +87,7 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     c->n_vertices = n;
     c->topdown_levels = 0;
     c->bottomup_levels = 0;
-    const bool hub = deg > kHubDeg;
+    const bool hub = deg > hub_deg;
     const int32_t nch = hub ? (deg + kHubChunk - 1) / kHubChunk : 0;
     if (hub) hub_list[0] = HubEntry{src, 0, 0, nch};
     c->hub_pack_.v = 0;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(BS) void k_src_topdown(LevelCtl *c, const int32_t *
                                                     const int32_t *__restrict__ ci, int32_t *dist,
                                                     int32_t *queue,
                                                     const HubEntry *__restrict__ hub_list,
-                                                    unsigned long long *prof) {
+                                                    unsigned long long *prof, int32_t hub_deg) {
     if (c->done || c->mode != MODE_TOPDOWN) return;
     __shared__ int32_t s_beg[BS], s_off[BS], s_scan[BS / kWave + 1];
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(BS) void k_src_topdown(LevelCtl *c, const int32_t *
                 const int32_t v = queue[i];
                 beg = rp[v];
                 deg = rp[v + 1] - beg;
-                if (deg > kHubDeg) deg = 0;  // chunks handled by blockIdx.y == 1
+                if (deg > hub_deg) deg = 0;  // chunks handled by blockIdx.y == 1
                 ++my_items;
                 my_edges += deg;
             }
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
                                                   const int32_t *__restrict__ queue,
                                                   const int32_t *__restrict__ dist, double *sigma,
                                                   HubEntry *hub_list, long long hub_cap,
-                                                  unsigned long long *prof) {
+                                                  unsigned long long *prof, int32_t hub_deg) {
     if (c->done) return;
     __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
     __shared__ double s_acc[BS];
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
             beg = rp[w];
             deg = rp[w + 1] - beg;
         }
-        const bool hub = deg > kHubDeg;
+        const bool hub = deg > hub_deg;
         const double s = wave_chunk_sum(beg, hub ? 0 : deg, ws, [&](int32_t e, int32_t) {
             const int32_t u = ci[e];
             if (dist[u] != lvl) return 0.0;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(BS) void k_src_delta(const int32_t *__restrict__ le
                                                   const int32_t *__restrict__ queue,
                                                   const int32_t *__restrict__ dist,
                                                   const double *__restrict__ sigma, double *delta,
-                                                  double *bc, unsigned long long *prof) {
+                                                  double *bc, unsigned long long *prof, int32_t hub_deg) {
     __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
     __shared__ double s_acc[BS], s_val[BS];
     __shared__ unsigned long long s_red[1];
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(BS) void k_src_delta(const int32_t *__restrict__ le
             deg = rp[v + 1] - beg;
             sv = sigma[v];
         }
-        const bool hub = deg > kHubDeg;
+        const bool hub = deg > hub_deg;
         ws.val[lane] = sv;
         const double acc = wave_chunk_sum(beg, hub ? 0 : deg, ws, [&](int32_t e, int32_t a) {
             const int32_t w = ci[e];
@@ -483,12 +483,16 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
     const bool hubs = g->n_hubs > 0;
+    // Directed graphs keep every row whole (no hub chunks): parents are read
+    // from the reversed rows and children from the forward ones, whose
+    // lengths differ, so one hub list cannot serve both passes.
+    const int32_t hub_deg = g->directed ? INT32_MAX : kHubDeg;
     const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
     SP_TRY(launch_fill_i32(ws.dist, n, -1, s));
     hipLaunchKernelGGL(k_src_init, dim3(1), dim3(1), 0, s, ws.ctl, ws.dist, ws.sigma, ws.queue,
                        ws.level_off, ws.hub_list, ws.hub_off, ws.hub_lvl_chunks,
                        (const int32_t *)g->row_ptr, src, n, (long long)g->nnz,
-                       may_pull ? o.alpha : 0.0, o.beta);  // alpha 0: never switch to bottom-up
+                       may_pull ? o.alpha : 0.0, o.beta, hub_deg);  // alpha 0: never switch to bottom-up
     SP_HIP(hipGetLastError());
     int32_t enqueued = 0;
     for (;;) {
@@ -498,18 +502,18 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                 ProfScope ps(P_SRC_TOPDOWN, s);
                 hipLaunchKernelGGL(k_src_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s,
                                    ws.ctl, g->row_ptr, g->col_idx, ws.dist, ws.queue,
-                                   (const HubEntry *)ws.hub_list, prof_counters(P_SRC_TOPDOWN));
+                                   (const HubEntry *)ws.hub_list, prof_counters(P_SRC_TOPDOWN), hub_deg);
             }
             if (may_pull) {
                 ProfScope ps(P_SRC_BOTTOMUP, s);
-                hipLaunchKernelGGL(k_src_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                                   g->col_idx, ws.dist, ws.queue, prof_counters(P_SRC_BOTTOMUP));
+                hipLaunchKernelGGL(k_src_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->rp_in,
+                                   g->ci_in, ws.dist, ws.queue, prof_counters(P_SRC_BOTTOMUP));
             }
             {
                 ProfScope ps(P_SRC_SIGMA, s);
-                hipLaunchKernelGGL(k_src_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                                   g->col_idx, ws.queue, ws.dist, ws.sigma, ws.hub_list,
-                                   (long long)g->n_hubs + 1, prof_counters(P_SRC_SIGMA));
+                hipLaunchKernelGGL(k_src_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->rp_in,
+                                   g->ci_in, ws.queue, ws.dist, ws.sigma, ws.hub_list,
+                                   (long long)g->n_hubs + 1, prof_counters(P_SRC_SIGMA), hub_deg);
             }
             hipLaunchKernelGGL(k_src_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks);
@@ -549,7 +553,7 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                 ProfScope ps(P_SRC_DELTA, s);
                 hipLaunchKernelGGL(k_src_delta<BS>, dim3(grid_for((int64_t)cnt, BS, maxb)), dim3(BS), 0, s,
                                    ws.level_off, l, g->row_ptr, g->col_idx, ws.queue, ws.dist,
-                                   ws.sigma, ws.delta, bc, prof_counters(P_SRC_DELTA));
+                                   ws.sigma, ws.delta, bc, prof_counters(P_SRC_DELTA), hub_deg);
             }
             if (hubs && hchunks[l] > 0) {
                 ProfScope ps(P_SRC_DELTA_HUB, s);

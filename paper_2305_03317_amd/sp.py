@@ -116,6 +116,8 @@ SIGNATURES = [
     ("sp_header_hash", ctypes.c_uint64, []),
     ("sp_graph_upload", _ST, [ctypes.c_int32, ctypes.c_int64, _VP, _VP, ctypes.c_uint32, _VP,
                               ctypes.POINTER(_VP)]),
+    ("sp_graph_upload_directed", _ST, [ctypes.c_int32, ctypes.c_int64, _VP, _VP, ctypes.c_uint32, _VP,
+                                       ctypes.POINTER(_VP)]),
     ("sp_graph_release", _ST, [_VP]),
     ("sp_graph_info", _ST, [_VP, _I32P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]),
     ("sp_bc", _ST, [_VP, _I32P, ctypes.c_int32, _VP, _VP]),
@@ -235,8 +237,9 @@ class Graph:
             pass
 
 
-def sp_graph_upload(row_ptr, col_idx, validate: bool = False, stream=None) -> Graph:
-    """Upload CSR arrays (numpy / host or CUDA torch tensors) to the device."""
+def sp_graph_upload(row_ptr, col_idx, validate: bool = False, stream=None, directed: bool = False) -> Graph:
+    """Upload CSR arrays (numpy / host or CUDA torch tensors) to the device;
+    directed=True treats row u as u's out-edges (sp_graph_upload_directed)."""
     torch = _torch()
     flags = SP_VALIDATE if validate else 0
     keep = []
@@ -259,8 +262,8 @@ def sp_graph_upload(row_ptr, col_idx, validate: bool = False, stream=None) -> Gr
         rp_ptr, ci_ptr = rp.ctypes.data, ci.ctypes.data
         n = rp.size - 1
     h = ctypes.c_void_p()
-    _check(lib().sp_graph_upload(n, nnz, rp_ptr, ci_ptr, flags, _stream(stream), ctypes.byref(h)),
-           "sp_graph_upload")
+    up = lib().sp_graph_upload_directed if directed else lib().sp_graph_upload
+    _check(up(n, nnz, rp_ptr, ci_ptr, flags, _stream(stream), ctypes.byref(h)), "sp_graph_upload")
     return Graph(h, n, nnz)
 
 

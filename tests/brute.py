@@ -133,3 +133,17 @@ def sssp_invariants(rp, ci, w, s, d, inf=2**31 - 1):
     reached = d != inf
     reached[s] = False
     assert np.all(has[reached]), "a reached vertex has no tight predecessor"
+
+
+def directed_csr(n, src, dst):
+    """CSR of a simple directed graph (rows = out-edges, sorted, duplicates
+    and self-loops dropped) from an edge list."""
+    import numpy as np
+    s = np.asarray(src, np.int64)
+    d = np.asarray(dst, np.int64)
+    keep = s != d
+    key = np.unique(s[keep] * n + d[keep])
+    s, d = key // n, key % n
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, s + 1, 1)
+    return np.cumsum(rp).astype(np.int32), d.astype(np.int32)
