@@ -25,7 +25,8 @@ resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS),
 single-source shortest paths on the RMAT and road graphs with the paper's
 uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle),
 PageRank on the same graphs (time per iteration, kernel roofline, numpy
-oracle), and the triangle count of the RMAT graph.
+oracle), the triangle count of the RMAT graph, and BC on a directed version
+of it (per-source path).
 
 Prints one JSON line.
 """
@@ -335,6 +336,66 @@ def attach_traffic(roofline, profile_name):
     return roofline
 
 
+def directed_benchmark(sp, torch, workload, n_sources):
+    """Betweenness centrality on a directed graph: the workload graph with
+    each undirected edge kept as one arc in a seeded direction, the first
+    n_sources of its sources, through the per-source path (the batched path
+    needs undirected graphs).  Kernel roofline as for the main line; the
+    oracle on two sources is the CPU baseline and a parity check."""
+    import numpy as np
+    import oracle
+    from paper_2305_03317_amd import graphs
+    k = WORKLOADS[workload]
+    urp, uci, src, spec = workload_graph(k)
+    rp, ci = graphs.directed_from(urp, uci, 4000 + k)
+    arcs = len(ci)
+    g = sp.sp_graph_upload(rp, ci, directed=True)
+    srcs = src[:n_sources]
+    out = torch.empty(len(rp) - 1, dtype=torch.float64, device="cuda")
+    sp.sp_bc(g, srcs[:1], out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = sp.sp_bc(g, srcs, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = sp.sp_get_last_stats()
+    sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
+    sp.sp_bc(g, srcs, out)
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
+    sp.sp_bc(g, srcs, out)
+    counted = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    kernels = {}
+    for kname, p in prof.items():
+        c = counted.get(kname, {})
+        kernels[kname] = {"launches": p["launches"], "ms": round(p["total_ms"], 3),
+                          "GBps_algorithmic": round(algorithmic_bytes(kname, c) / max(p["total_ms"], 1e-9) / 1e6, 1)}
+    dom = max(kernels.items(), key=lambda kv: kv[1]["ms"]) if kernels else None
+    roofline = None
+    if dom:
+        roofline = {"bound": "hbm", "achieved": dom[1]["GBps_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(dom[1]["GBps_algorithmic"] / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": dom[0], "avg_launch_ms": round(dom[1]["ms"] / max(dom[1]["launches"], 1), 4)}
+    t0 = time.perf_counter()
+    ref = oracle.bc(rp, ci, srcs[:2])
+    cpu_s = time.perf_counter() - t0
+    got, _ = sp.sp_bc(g, srcs[:2], out)
+    got = got.cpu().numpy()
+    g.release()
+    nz = ref != 0
+    rel = float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
+    return {"workload": "%s, each edge one arc (seed %d)" % (spec["name"], 4000 + k), "arcs": arcs,
+            "sources": len(srcs), "ms_per_source": round(wall * 1e3 / len(srcs), 3),
+            "teps": len(srcs) * arcs / wall, "unit": "TEPS (sources x arcs / time)", "status": st,
+            "levels_max": stats["max_levels"], "kernels": kernels, "roofline": roofline,
+            "cpu_baseline": {"value": 2 * arcs / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                             "sample": "first 2 sources, single-threaded C oracle, %.2f s" % cpu_s},
+            "parity": {"sources": 2, "max_rel_err": rel, "zero_exact": bool(np.all(got[~nz] == 0)),
+                       "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}}
+
+
 def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
     """Serving workload: eight resident graphs, seeded requests (graph uniform,
     1..512 sources log-uniform), continuous batching by the library's server.
@@ -444,6 +505,10 @@ def main():
                     help="RMAT scale of the triangle-count CPU baseline and parity graph (0 = skip)")
     ap.add_argument("--only-tc", action="store_true",
                     help="run only the triangle-count legs and print their JSON object")
+    ap.add_argument("--directed", default="rmat-22:64",
+                    help="directed BC legs as workload:sources, comma-separated ('' = skip)")
+    ap.add_argument("--only-directed", action="store_true",
+                    help="run only the directed BC legs and print their JSON object")
     ap.add_argument("--only-sssp", action="store_true",
                     help="run only the SSSP legs and print their JSON object")
     ap.add_argument("--only-pagerank", action="store_true",
@@ -496,8 +561,11 @@ def main():
         rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
-    if args.only_sssp or args.only_pagerank or args.only_tc:
+    if args.only_sssp or args.only_pagerank or args.only_tc or args.only_directed:
         legs = {}
+        if args.only_directed:
+            legs["directed_bc"] = {wl: directed_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+                                   (leg.split(":") for leg in filter(None, args.directed.split(",")))}
         if args.only_tc:
             legs["triangles"] = {wl: tc_benchmark(sp, torch, wl, args.tc_small_scale)
                                  for wl in filter(None, args.tc.split(","))}
@@ -683,6 +751,8 @@ def main():
         wl, it = leg.split(":")
         pagerank[wl] = pagerank_benchmark(sp, torch, wl, int(it))
     triangles = {wl: tc_benchmark(sp, torch, wl, args.tc_small_scale) for wl in filter(None, args.tc.split(","))}
+    directed = {wl: directed_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+                (leg.split(":") for leg in filter(None, args.directed.split(",")))}
     serving = None
     if args.serving_requests > 0:
         serving = serving_benchmark(sp, torch, args.serving_requests)
@@ -726,6 +796,7 @@ def main():
         "sssp": sssp or None,
         "pagerank": pagerank or None,
         "triangles": triangles or None,
+        "directed_bc": directed or None,
     }
     print(json.dumps(line))
 

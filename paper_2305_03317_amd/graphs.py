@@ -120,6 +120,24 @@ def weights(row_ptr, col_idx, seed: int, lo: int = 1, hi: int = 100):
     return out[:len(ci)]
 
 
+def directed_from(row_ptr, col_idx, seed: int):
+    """Directed CSR (rows = out-edges, sorted) that keeps each undirected edge
+    {u, w} of a symmetric CSR as one arc, u -> w or w -> u by a seeded coin."""
+    rp = np.asarray(row_ptr, np.int64)
+    ci = np.asarray(col_idx, np.int64)
+    n = len(rp) - 1
+    u = np.repeat(np.arange(n), np.diff(rp))
+    keep = u < ci
+    a, b = u[keep], ci[keep]
+    flip = np.random.default_rng(seed).random(len(a)) < 0.5
+    src, dst = np.where(flip, b, a), np.where(flip, a, b)
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    out_rp = np.zeros(n + 1, np.int64)
+    np.add.at(out_rp, src + 1, 1)
+    return np.cumsum(out_rp).astype(np.int32), dst.astype(np.int32)
+
+
 WORKLOADS = {
     1: dict(name="uniform-4096", kind="uniform", n=4096, m=32768, n_sources=16, min_degree=0),
     2: dict(name="rmat-20", kind="rmat", scale=20, n_sources=256, min_degree=1),
