@@ -273,7 +273,8 @@ typedef struct sp_sssp_config {
                              even) in a hipGraph and replayed, checking the device
                              "done" flag after each replay; k < 0: |k| rounds per
                              check launched directly; 0 = 8.  |k| <= 65536. */
-    int32_t reserved[3];  /* must be zero */
+    int32_t max_blocks;   /* workgroups per round kernel, >= 0 (0 = automatic) */
+    int32_t reserved[2];  /* must be zero */
 } sp_sssp_config;
 
 typedef struct sp_sssp_stats {

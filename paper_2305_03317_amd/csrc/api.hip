@@ -1083,8 +1083,8 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
                          (cfg->block_size != 0 && cfg->block_size != 128 && cfg->block_size != 256 &&
                           cfg->block_size != 512) ||
                          !(cfg->alpha >= 0.0) || std::isinf(cfg->alpha) ||
-                         std::abs((int64_t)cfg->chunk_rounds) > 65536 || cfg->reserved[0] ||
-                         cfg->reserved[1] || cfg->reserved[2];
+                         std::abs((int64_t)cfg->chunk_rounds) > 65536 || cfg->max_blocks < 0 ||
+                         cfg->reserved[0] || cfg->reserved[1];
         if (bad) {
             set_error("sp_sssp: invalid configuration");
             return SP_ERR_INVALID_ARGUMENT;
@@ -1093,6 +1093,7 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
         if (cfg->block_size) o.block = cfg->block_size;
         if (cfg->alpha > 0) o.alpha = cfg->alpha;
         if (cfg->chunk_rounds) o.chunk_rounds = cfg->chunk_rounds;
+        o.max_blocks = cfg->max_blocks;
     }
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;

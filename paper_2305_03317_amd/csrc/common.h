@@ -389,6 +389,7 @@ struct SsspOpts {
     double alpha = 1.0;    // a frontier never holds more than every entry: no pull rounds
     int block = 256;
     int chunk_rounds = 8;
+    int max_blocks = 0;    // 0: automatic
 };
 struct SsspResult {
     int32_t rounds = 0, push_rounds = 0, pull_rounds = 0;

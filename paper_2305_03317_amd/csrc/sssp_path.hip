@@ -519,7 +519,7 @@ template <int BS>
 static sp_status sssp_run_bs(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t *out_dist,
                              const SsspOpts &o, hipStream_t s, SsspResult *res) {
     const int32_t n = g->n;
-    const int maxb = device_cu_count() * 8;
+    const int maxb = o.max_blocks > 0 ? o.max_blocks : device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
     const bool hubs = g->n_hubs > 0;
     // Automatic choice never pulls on sparse meshes (every row at most 8 long),

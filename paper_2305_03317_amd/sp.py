@@ -52,7 +52,7 @@ class sp_stats(ctypes.Structure):
 class sp_sssp_config(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("chunk_rounds", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("max_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class sp_sssp_stats(ctypes.Structure):

@@ -64,7 +64,8 @@ def test_small_graphs_all_modes(sp, mode):
 
 @pytest.mark.parametrize("cfg", [{"chunk_rounds": -3}, {"chunk_rounds": 3}, {"chunk_rounds": 1},
                                  {"block_size": 128}, {"block_size": 512},
-                                 {"alpha": 1e6}, {"alpha": 1e-3, "chunk_rounds": -2}])
+                                 {"alpha": 1e6}, {"alpha": 1e-3, "chunk_rounds": -2},
+                                 {"max_blocks": 3}, {"max_blocks": 1, "block_size": 512}])
 def test_launch_configurations(sp, cfg):
     rp, ci = graphs.rmat(12, 16, seed=13)
     w = graphs.weights(rp, ci, 14)
@@ -146,6 +147,8 @@ def test_errors(sp):
         sp.sp_sssp(g, 0, config={"block_size": 64})
     with pytest.raises(sp.SpError):
         sp.sp_sssp(g, 0, config={"direction": 3})
+    with pytest.raises(sp.SpError):
+        sp.sp_sssp(g, 0, config={"max_blocks": -1})
     # still usable after errors
     sp.sp_graph_set_weights(g, np.array([5, 5, 6, 6], np.int32))
     assert list(run(sp, g, 0)) == [0, 5, 11]
