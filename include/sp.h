@@ -274,7 +274,11 @@ typedef struct sp_sssp_config {
                              "done" flag after each replay; k < 0: |k| rounds per
                              check launched directly; 0 = 8.  |k| <= 65536. */
     int32_t max_blocks;   /* workgroups per round kernel, >= 0 (0 = automatic) */
-    int32_t reserved[2];  /* must be zero */
+    int32_t local_hops;   /* push rounds: a workgroup also follows its own lowerings for
+                             this many more hops inside the round (1, 2, 4 or 8; -1 =
+                             none; 0 = automatic: 4 on graphs whose rows all hold at
+                             most 8 entries, else none).  The distances do not change. */
+    int32_t reserved[1];  /* must be zero */
 } sp_sssp_config;
 
 typedef struct sp_sssp_stats {
@@ -288,6 +292,7 @@ typedef struct sp_sssp_stats {
     double alpha;
     int32_t direction;
     int32_t chunk_rounds;
+    int32_t local_hops;
 } sp_sssp_stats;
 
 /* Distances from `source` to every vertex.

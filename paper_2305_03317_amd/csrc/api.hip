@@ -1084,7 +1084,9 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
                           cfg->block_size != 512) ||
                          !(cfg->alpha >= 0.0) || std::isinf(cfg->alpha) ||
                          std::abs((int64_t)cfg->chunk_rounds) > 65536 || cfg->max_blocks < 0 ||
-                         cfg->reserved[0] || cfg->reserved[1];
+                         (cfg->local_hops != -1 && cfg->local_hops != 0 && cfg->local_hops != 1 &&
+                          cfg->local_hops != 2 && cfg->local_hops != 4 && cfg->local_hops != 8) ||
+                         cfg->reserved[0];
         if (bad) {
             set_error("sp_sssp: invalid configuration");
             return SP_ERR_INVALID_ARGUMENT;
@@ -1094,6 +1096,7 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
         if (cfg->alpha > 0) o.alpha = cfg->alpha;
         if (cfg->chunk_rounds) o.chunk_rounds = cfg->chunk_rounds;
         o.max_blocks = cfg->max_blocks;
+        o.local_hops = cfg->local_hops;
     }
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;
@@ -1123,6 +1126,7 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
     t.alpha = o.alpha;
     t.direction = o.forced == SSSP_PUSH ? SP_SSSP_PUSH : o.forced == SSSP_PULL ? SP_SSSP_PULL : SP_SSSP_AUTO;
     t.chunk_rounds = o.chunk_rounds;
+    t.local_hops = sssp_local_hops(g, o.local_hops);
     return SP_OK;
     SP_GUARD_END
 }

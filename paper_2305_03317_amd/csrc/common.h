@@ -390,7 +390,10 @@ struct SsspOpts {
     int block = 256;
     int chunk_rounds = 8;
     int max_blocks = 0;    // 0: automatic
+    int local_hops = 0;    // 0: automatic, < 0: none, else hops per round (1, 2, 4, 8)
 };
+// Local hops a run uses (sssp_path.hip).
+int sssp_local_hops(sp_graph g, int requested);
 struct SsspResult {
     int32_t rounds = 0, push_rounds = 0, pull_rounds = 0;
     int32_t reached = 0;

@@ -61,12 +61,17 @@ __device__ __forceinline__ int32_t candidate(int32_t d, int32_t w, bool &ovf) {
 // vertex and round: the first whose atomicMin lowered u's distance in this
 // round; it puts u into the next frontier.  A stale plain read can only be
 // too large, so skipping on it is safe.
-__device__ __forceinline__ bool relax_push(int2 *ds, int32_t u, int32_t nd, int32_t r) {
+__device__ __forceinline__ bool relax_push(int2 *ds, int32_t u, int32_t nd, int32_t r, bool &lowered) {
+    lowered = false;
     if (nd >= ds[u].x) return false;
     const int32_t old = atomicMin(&ds[u].x, nd);
     if (nd >= old) return false;
+    lowered = true;
     return atomicMax(&ds[u].y, r + 1) < r + 1;
 }
+
+// Entries of a block's local frontier (see k_sssp_push).
+constexpr int kLocalCap = 512;
 
 // The round state word (SsspCtl::state).
 struct RoundState {
@@ -211,7 +216,17 @@ __global__ void k_sssp_init(SsspCtl *c, const int32_t *__restrict__ rp, int2 *ds
 // excluded), scans their row lengths and walks the concatenated rows BS
 // entries at a time, one entry per lane.  blockIdx.y == 1: blocks take the
 // chunks of the frontier's hubs.
-template <int BS>
+//
+// With HOPS > 0 (graphs of short rows, where rounds are many and small) a
+// block also follows its own lowerings for up to HOPS more hops inside the
+// round: every vertex it lowered goes, with the distance it wrote, into an
+// LDS list, and the list is expanded the same way.  Every lowering still
+// puts its vertex into the next frontier (first lowering in the round) or
+// finds it there already, so the next round expands it with its current
+// distance whatever happened locally; the local hops only add relaxations
+// from valid path lengths, and the improvements travel up to HOPS + 1 edges
+// per round instead of one.
+template <int BS, int HOPS>
 __global__ __launch_bounds__(BS) void k_sssp_push(SsspCtl *c, const int32_t *__restrict__ rp,
                                                   const int2 *__restrict__ adj, int2 *ds,
                                                   int32_t *q0, int32_t *q1, HubEntry *h0,
@@ -220,8 +235,10 @@ __global__ __launch_bounds__(BS) void k_sssp_push(SsspCtl *c, const int32_t *__r
                                                   int32_t parity, unsigned long long *prof) {
     const RoundState st = read_state(c);
     if (st.done || st.pull || st.parity != parity) return;
+    constexpr int kLists = HOPS > 0 ? 2 : 1, kCap = HOPS > 0 ? kLocalCap : 1;
     __shared__ int32_t s_beg[BS], s_off[BS], s_d[BS], s_scan[BS / kWave + 1];
     __shared__ int32_t s_qbuf[4 * BS], s_meta[2];
+    __shared__ int32_t s_lv[kLists][kCap], s_ld[kLists][kCap], s_ln[2];
     __shared__ unsigned long long s_red[1];
     const int32_t r = c->round, cnt = st.cnt, nch = st.chunks;
     const int32_t *qc = parity ? q1 : q0;
@@ -236,6 +253,40 @@ __global__ __launch_bounds__(BS) void k_sssp_push(SsspCtl *c, const int32_t *__r
     bool ovf = false;
     const int nb0 = working_blocks(cnt, BS);
     const int nb1 = (int)min((int64_t)gridDim.x, (int64_t)nch);
+    // Expands the rows held by the block's threads (row start, length, the
+    // distance to extend): scan, walk one entry per lane, relax; lowered
+    // vertices go to local list `dst` when dst >= 0.  All threads call it.
+    auto walk = [&](int32_t beg, int32_t deg, int32_t d, int dst) {
+        int32_t total;
+        const int32_t off = block_excl_scan<BS>(deg, s_scan, &total);
+        s_beg[threadIdx.x] = beg;
+        s_off[threadIdx.x] = off;
+        s_d[threadIdx.x] = d;
+        __syncthreads();
+        for (int32_t k0 = 0; k0 < total; k0 += BS) {
+            const int32_t k = k0 + threadIdx.x;
+            bool take = false;
+            int32_t u = 0;
+            if (k < total) {
+                const int32_t a = owner_of<BS>(s_off, k);
+                const int2 e = adj[s_beg[a] + (k - s_off[a])];
+                u = e.x;
+                const int32_t nd = candidate(s_d[a], e.y, ovf);
+                bool lowered;
+                take = relax_push(ds, u, nd, r, lowered);
+                if (take) joined(c, rp, hn, on, hub_cap, chunk_cap, u, my_deg);
+                if (HOPS > 0 && dst >= 0 && lowered) {
+                    const int32_t at = atomicAdd(&s_ln[dst], 1);
+                    if (at < kCap) {
+                        s_lv[dst][at] = u;
+                        s_ld[dst][at] = nd;
+                    }
+                }
+            }
+            q.stage(take, u, &c->tail_.v, qn, n, &c->capacity_.v);
+        }
+        __syncthreads();
+    };
     bool working;
     if (blockIdx.y == 0) {
         working = (int)blockIdx.x < nb0;
@@ -251,26 +302,30 @@ __global__ __launch_bounds__(BS) void k_sssp_push(SsspCtl *c, const int32_t *__r
                 ++my_items;
                 my_edges += (unsigned long long)deg;
             }
-            int32_t total;
-            const int32_t off = block_excl_scan<BS>(deg, s_scan, &total);
-            s_beg[threadIdx.x] = beg;
-            s_off[threadIdx.x] = off;
-            s_d[threadIdx.x] = d;
-            __syncthreads();
-            for (int32_t k0 = 0; k0 < total; k0 += BS) {
-                const int32_t k = k0 + threadIdx.x;
-                bool take = false;
-                int32_t u = 0;
-                if (k < total) {
-                    const int32_t a = owner_of<BS>(s_off, k);
-                    const int2 e = adj[s_beg[a] + (k - s_off[a])];
-                    u = e.x;
-                    take = relax_push(ds, u, candidate(s_d[a], e.y, ovf), r);
-                    if (take) joined(c, rp, hn, on, hub_cap, chunk_cap, u, my_deg);
+            if (HOPS > 0 && threadIdx.x == 0) s_ln[0] = 0;  // seen after the scan's barrier
+            walk(beg, deg, d, HOPS > 0 ? 0 : -1);
+            int cur = 0;
+            for (int hop = 0; hop < HOPS; ++hop) {
+                const int32_t ln = min(s_ln[cur], kCap);
+                if (ln == 0) break;
+                const int nxt = cur ^ 1;
+                if (threadIdx.x == 0) s_ln[nxt] = 0;
+                for (int32_t lb = 0; lb < ln; lb += BS) {
+                    const int32_t j = lb + threadIdx.x;
+                    int32_t lbeg = 0, ldeg = 0, ld = 0;
+                    if (j < ln) {
+                        const int32_t v = s_lv[cur][j];
+                        ld = s_ld[cur][j];
+                        lbeg = rp[v];
+                        ldeg = rp[v + 1] - lbeg;
+                        if (ldeg > kHubDeg) ldeg = 0;  // already in the next frontier
+                        ++my_items;
+                        my_edges += (unsigned long long)ldeg;
+                    }
+                    walk(lbeg, ldeg, ld, hop + 1 < HOPS ? nxt : -1);
                 }
-                q.stage(take, u, &c->tail_.v, qn, n, &c->capacity_.v);
+                cur = nxt;
             }
-            __syncthreads();
         }
     } else {
         working = (int)blockIdx.x < nb1;
@@ -287,7 +342,8 @@ __global__ __launch_bounds__(BS) void k_sssp_push(SsspCtl *c, const int32_t *__r
                 if (e < end) {
                     const int2 x = adj[e];
                     u = x.x;
-                    take = relax_push(ds, u, candidate(d, x.y, ovf), r);
+                    bool lowered;
+                    take = relax_push(ds, u, candidate(d, x.y, ovf), r, lowered);
                     if (take) joined(c, rp, hn, on, hub_cap, chunk_cap, u, my_deg);
                 }
                 q.stage(take, u, &c->tail_.v, qn, n, &c->capacity_.v);
@@ -491,7 +547,7 @@ void sssp_ws_destroy(SsspWorkspace &ws) {
 // control block is at a round of that parity.  A block of round r's kernel
 // that starts after the round was closed therefore sees round r + 1 and
 // returns, instead of taking part in a round that is not its own.
-template <int BS>
+template <int BS, int HOPS>
 static void enqueue_rounds(sp_graph g, SsspWorkspace &ws, int rounds, int grid, bool hubs,
                            bool may_pull, bool may_push, hipStream_t s) {
     const int32_t hub_cap = g->n_hubs + 1, chunk_cap = (int32_t)g->hub_chunks + 1, n = g->n;
@@ -499,7 +555,7 @@ static void enqueue_rounds(sp_graph g, SsspWorkspace &ws, int rounds, int grid, 
         const int32_t parity = k & 1;
         if (may_push) {
             ProfScope ps(P_SSSP_PUSH, s);
-            hipLaunchKernelGGL(k_sssp_push<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
+            hipLaunchKernelGGL((k_sssp_push<BS, HOPS>), dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
                                (const int32_t *)g->row_ptr, (const int2 *)g->adjw, ws.ds, ws.queue[0],
                                ws.queue[1], ws.hubs[0], ws.hubs[1], ws.owner[0], ws.owner[1],
                                hub_cap, chunk_cap, n, parity, prof_counters(P_SSSP_PUSH));
@@ -515,7 +571,7 @@ static void enqueue_rounds(sp_graph g, SsspWorkspace &ws, int rounds, int grid, 
     }
 }
 
-template <int BS>
+template <int BS, int HOPS>
 static sp_status sssp_run_bs(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t *out_dist,
                              const SsspOpts &o, hipStream_t s, SsspResult *res) {
     const int32_t n = g->n;
@@ -540,17 +596,17 @@ static sp_status sssp_run_bs(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t
         const int chunk = (base + (base & 1)) * (deep ? 4 : 1);  // even: parity holds
         if (capture) {
             const std::array<long long, 12> key = {
-                BS, grid, hubs, may_pull, may_push, chunk, (long long)(intptr_t)ws.ds,
+                BS * 16 + HOPS, grid, hubs, may_pull, may_push, chunk, (long long)(intptr_t)ws.ds,
                 (long long)(intptr_t)g->adjw, (long long)(intptr_t)g->hub_static,
                 (long long)(intptr_t)g->owner_static, (long long)(intptr_t)ws.ctl, g->n_hubs};
             SP_TRY(replay_captured(&ws.cap_stream, deep ? ws.rounds_long : ws.rounds_short, key,
                                    [&](hipStream_t cs) {
-                                       enqueue_rounds<BS>(g, ws, chunk, grid, hubs, may_pull, may_push, cs);
+                                       enqueue_rounds<BS, HOPS>(g, ws, chunk, grid, hubs, may_pull, may_push, cs);
                                    },
                                    s));
             ++graph_launches;
         } else {
-            enqueue_rounds<BS>(g, ws, chunk, grid, hubs, may_pull, may_push, s);
+            enqueue_rounds<BS, HOPS>(g, ws, chunk, grid, hubs, may_pull, may_push, s);
             SP_HIP(hipGetLastError());
         }
         enqueued += chunk;
@@ -601,12 +657,32 @@ static sp_status sssp_run_bs(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t
     return SP_OK;
 }
 
+template <int HOPS>
+static sp_status sssp_run_hops(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t *out_dist,
+                               const SsspOpts &o, hipStream_t s, SsspResult *res) {
+    switch (o.block) {
+        case 128: return sssp_run_bs<128, HOPS>(g, ws, src, out_dist, o, s, res);
+        case 512: return sssp_run_bs<512, HOPS>(g, ws, src, out_dist, o, s, res);
+        default: return sssp_run_bs<256, HOPS>(g, ws, src, out_dist, o, s, res);
+    }
+}
+
+int sssp_local_hops(sp_graph g, int requested) {
+    if (requested < 0) return 0;
+    if (requested > 0) return requested;
+    // automatic: graphs of short rows only (many small rounds); hub rows
+    // never go through the local lists
+    return (g->max_degree <= 8 && g->n_hubs == 0) ? 4 : 0;
+}
+
 sp_status sssp_run(sp_graph g, SsspWorkspace &ws, int32_t src, int32_t *out_dist, const SsspOpts &o,
                    hipStream_t s, SsspResult *res) {
-    switch (o.block) {
-        case 128: return sssp_run_bs<128>(g, ws, src, out_dist, o, s, res);
-        case 512: return sssp_run_bs<512>(g, ws, src, out_dist, o, s, res);
-        default: return sssp_run_bs<256>(g, ws, src, out_dist, o, s, res);
+    switch (sssp_local_hops(g, o.local_hops)) {
+        case 0: return sssp_run_hops<0>(g, ws, src, out_dist, o, s, res);
+        case 1: return sssp_run_hops<1>(g, ws, src, out_dist, o, s, res);
+        case 2: return sssp_run_hops<2>(g, ws, src, out_dist, o, s, res);
+        case 4: return sssp_run_hops<4>(g, ws, src, out_dist, o, s, res);
+        default: return sssp_run_hops<8>(g, ws, src, out_dist, o, s, res);
     }
 }
 

@@ -52,7 +52,8 @@ class sp_stats(ctypes.Structure):
 class sp_sssp_config(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("chunk_rounds", ctypes.c_int32),
-                ("max_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("max_blocks", ctypes.c_int32), ("local_hops", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class sp_sssp_stats(ctypes.Structure):
@@ -60,7 +61,8 @@ class sp_sssp_stats(ctypes.Structure):
                 ("pull_rounds", ctypes.c_int32), ("reached", ctypes.c_int32),
                 ("device_ms", ctypes.c_double), ("graph_launches", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("direction", ctypes.c_int32), ("chunk_rounds", ctypes.c_int32)]
+                ("direction", ctypes.c_int32), ("chunk_rounds", ctypes.c_int32),
+                ("local_hops", ctypes.c_int32)]
 
 
 class sp_pagerank_config(ctypes.Structure):

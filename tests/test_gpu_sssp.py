@@ -65,7 +65,9 @@ def test_small_graphs_all_modes(sp, mode):
 @pytest.mark.parametrize("cfg", [{"chunk_rounds": -3}, {"chunk_rounds": 3}, {"chunk_rounds": 1},
                                  {"block_size": 128}, {"block_size": 512},
                                  {"alpha": 1e6}, {"alpha": 1e-3, "chunk_rounds": -2},
-                                 {"max_blocks": 3}, {"max_blocks": 1, "block_size": 512}])
+                                 {"max_blocks": 3}, {"max_blocks": 1, "block_size": 512},
+                                 {"local_hops": 1}, {"local_hops": 8, "chunk_rounds": -3},
+                                 {"local_hops": 2, "block_size": 128}])
 def test_launch_configurations(sp, cfg):
     rp, ci = graphs.rmat(12, 16, seed=13)
     w = graphs.weights(rp, ci, 14)
@@ -75,6 +77,21 @@ def test_launch_configurations(sp, cfg):
         assert np.array_equal(run(sp, g, s, cfg), oracle.sssp(rp, ci, w, int(s)))
     st = sp.sp_sssp_get_last_stats()
     assert st["rounds"] == st["push_rounds"] + st["pull_rounds"] and st["rounds"] >= 2
+
+
+@pytest.mark.parametrize("hops", [-1, 1, 2, 4, 8])
+def test_local_hops_on_meshes(sp, hops):
+    # road-like graphs (rows of at most 8 entries) use local hops by default
+    rp, ci = graphs.road(120, 0.02, seed=22)
+    w = graphs.weights(rp, ci, 23)
+    g = weighted(sp, rp, ci, w)
+    for s in graphs.sources(rp, 3, 24, min_degree=1):
+        got = run(sp, g, s, {"local_hops": hops})
+        assert np.array_equal(got, oracle.sssp(rp, ci, w, int(s))), (hops, int(s))
+    st = sp.sp_sssp_get_last_stats()
+    assert st["local_hops"] == (0 if hops < 0 else hops)
+    run(sp, g, 0)
+    assert sp.sp_sssp_get_last_stats()["local_hops"] == 4
 
 
 def test_unit_weights_match_bfs_levels(sp):
@@ -149,6 +166,8 @@ def test_errors(sp):
         sp.sp_sssp(g, 0, config={"direction": 3})
     with pytest.raises(sp.SpError):
         sp.sp_sssp(g, 0, config={"max_blocks": -1})
+    with pytest.raises(sp.SpError):
+        sp.sp_sssp(g, 0, config={"local_hops": 3})
     # still usable after errors
     sp.sp_graph_set_weights(g, np.array([5, 5, 6, 6], np.int32))
     assert list(run(sp, g, 0)) == [0, 5, 11]
