@@ -275,9 +275,10 @@ typedef struct sp_sssp_config {
                              check launched directly; 0 = 8.  |k| <= 65536. */
     int32_t max_blocks;   /* workgroups per round kernel, >= 0 (0 = automatic) */
     int32_t local_hops;   /* push rounds: a workgroup also follows its own lowerings for
-                             this many more hops inside the round (1, 2, 4 or 8; -1 =
-                             none; 0 = automatic: 4 on graphs whose rows all hold at
-                             most 8 entries, else none).  The distances do not change. */
+                             this many more hops inside the round (a power of two up
+                             to 128; -1 = none; 0 = automatic: 32 on graphs whose rows
+                             all hold at most 8 entries, else none).  The distances do
+                             not change. */
     int32_t reserved[1];  /* must be zero */
 } sp_sssp_config;
 

@@ -1084,8 +1084,8 @@ sp_status sp_sssp(sp_graph g, int32_t source, int32_t *out_dist, const sp_sssp_c
                           cfg->block_size != 512) ||
                          !(cfg->alpha >= 0.0) || std::isinf(cfg->alpha) ||
                          std::abs((int64_t)cfg->chunk_rounds) > 65536 || cfg->max_blocks < 0 ||
-                         (cfg->local_hops != -1 && cfg->local_hops != 0 && cfg->local_hops != 1 &&
-                          cfg->local_hops != 2 && cfg->local_hops != 4 && cfg->local_hops != 8) ||
+                         (cfg->local_hops < -1 || cfg->local_hops > 128 ||
+                          (cfg->local_hops > 0 && (cfg->local_hops & (cfg->local_hops - 1)))) ||
                          cfg->reserved[0];
         if (bad) {
             set_error("sp_sssp: invalid configuration");

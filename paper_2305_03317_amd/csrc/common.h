@@ -390,7 +390,7 @@ struct SsspOpts {
     int block = 256;
     int chunk_rounds = 8;
     int max_blocks = 0;    // 0: automatic
-    int local_hops = 0;    // 0: automatic, < 0: none, else hops per round (1, 2, 4, 8)
+    int local_hops = 0;    // 0: automatic, < 0: none, else hops per round (a power of two <= 128)
 };
 // Local hops a run uses (sssp_path.hip).
 int sssp_local_hops(sp_graph g, int requested);

@@ -79,7 +79,7 @@ def test_launch_configurations(sp, cfg):
     assert st["rounds"] == st["push_rounds"] + st["pull_rounds"] and st["rounds"] >= 2
 
 
-@pytest.mark.parametrize("hops", [-1, 1, 2, 4, 8])
+@pytest.mark.parametrize("hops", [-1, 1, 2, 8, 32, 128])
 def test_local_hops_on_meshes(sp, hops):
     # road-like graphs (rows of at most 8 entries) use local hops by default
     rp, ci = graphs.road(120, 0.02, seed=22)
@@ -91,7 +91,7 @@ def test_local_hops_on_meshes(sp, hops):
     st = sp.sp_sssp_get_last_stats()
     assert st["local_hops"] == (0 if hops < 0 else hops)
     run(sp, g, 0)
-    assert sp.sp_sssp_get_last_stats()["local_hops"] == 4
+    assert sp.sp_sssp_get_last_stats()["local_hops"] == 32
 
 
 def test_unit_weights_match_bfs_levels(sp):
@@ -168,6 +168,8 @@ def test_errors(sp):
         sp.sp_sssp(g, 0, config={"max_blocks": -1})
     with pytest.raises(sp.SpError):
         sp.sp_sssp(g, 0, config={"local_hops": 3})
+    with pytest.raises(sp.SpError):
+        sp.sp_sssp(g, 0, config={"local_hops": 256})
     # still usable after errors
     sp.sp_graph_set_weights(g, np.array([5, 5, 6, 6], np.int32))
     assert list(run(sp, g, 0)) == [0, 5, 11]
