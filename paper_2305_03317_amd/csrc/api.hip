@@ -588,6 +588,8 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     g->max_degree = md;
     g->rp_in = g->row_ptr;
     g->ci_in = g->col_idx;
+    g->n_hubs_in = g->n_hubs;
+    g->hub_chunks_in = g->hub_chunks;
     g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
     *out = g;
     return SP_OK;
@@ -654,13 +656,22 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
         return rc != SP_OK ? rc : SP_ERR_DEVICE;
     }
     int32_t md = g->max_degree;
-    for (int32_t v = 0; v < n_vertices; ++v) md = std::max(md, ir[v + 1] - ir[v]);
+    int32_t nh_in = 0;
+    int64_t nch_in = 0;
+    for (int32_t v = 0; v < n_vertices; ++v) {
+        const int32_t d = ir[v + 1] - ir[v];
+        md = std::max(md, d);
+        if (d > kHubDeg) {
+            ++nh_in;
+            nch_in += (d + kHubChunk - 1) / kHubChunk;
+        }
+    }
     g->rp_in = rp_in;
     g->ci_in = ci_in;
     g->directed = true;
     g->max_degree = md;
-    g->n_hubs = 0;  // rows are never cut into hub chunks on directed graphs
-    g->hub_chunks = 0;
+    g->n_hubs_in = nh_in;  // n_hubs / hub_chunks count the outgoing rows
+    g->hub_chunks_in = nch_in;
     g->bytes += ir.size() * 4 + ic.size() * 4;
     *out = g;
     return SP_OK;

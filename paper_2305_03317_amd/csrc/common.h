@@ -73,6 +73,8 @@ struct sp_graph_s {
     int32_t max_degree = 0;
     int32_t n_hubs = 0;          // vertices of degree > kHubDeg
     int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
+    int32_t n_hubs_in = 0;       // the same for incoming rows (= n_hubs when undirected)
+    int64_t hub_chunks_in = 0;
     size_t bytes = 0;
     std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
     std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
@@ -176,6 +178,12 @@ struct LevelCtl {
     HotU64 nlive_;           // batched: slots of the next frontier (accumulating)
     HotI32 blocks_done_;     // batched: blocks of the current kernel that finished (last one
                              // ends the level); zero between kernels
+    // Per-source path on a directed graph: the level's vertices whose
+    // incoming row is longer than kHubDeg (their path counts are chunked),
+    // listed afresh each level: [0, in_hub_n) with in_hub_nchunks chunks;
+    // in_hub_pack_ accumulates the level being built as (count << 40) | chunks.
+    int32_t in_hub_n, in_hub_nchunks;
+    HotU64 in_hub_pack_;
 };
 
 
@@ -218,10 +226,11 @@ struct SourceWorkspace {
     int32_t *level_off = nullptr;  // device, levels + 2
     int32_t level_cap = 0;
     HubEntry *hub_list = nullptr;  // device, n_hubs + 1 (a hub occurs once per source)
+    HubEntry *in_hub_list = nullptr;  // device, n_hubs_in + 1 (directed graphs)
     int32_t *hub_off = nullptr;    // device, levels + 2: hub segment of each level
     int32_t *hub_lvl_chunks = nullptr;  // device, levels + 1: chunk count of each level
     unsigned int *hub_cnt = nullptr;    // device, n_hubs + 1: finished chunks per hub
-    double *partial = nullptr;     // device, hub_chunks + 1
+    double *partial = nullptr;     // device, max(hub_chunks, hub_chunks_in) + 1
     LevelCtl *ctl = nullptr;       // device
     LevelCtl *ctl_host = nullptr;  // pinned mirror
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

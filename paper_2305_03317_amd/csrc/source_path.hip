@@ -63,6 +63,16 @@ sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+// Directed graphs: register a vertex of the level being built whose incoming
+// row is longer than the hub threshold (list rebuilt every level).
+__device__ __forceinline__ void in_hub_register(LevelCtl *c, HubEntry *list, long long cap, int32_t v,
+                                                int32_t entry, int32_t deg) {
+    const int32_t nch = (deg + kHubChunk - 1) / kHubChunk;
+    const unsigned long long old = atomicAdd(&c->in_hub_pack_.v, (1ull << 40) | (unsigned long long)nch);
+    const int32_t idx = (int32_t)(old >> 40);
+    if (idx < cap) list[idx] = HubEntry{v, entry, (int32_t)(old & ((1ull << 40) - 1)), nch};
+}
+
 __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *queue,
                            int32_t *level_off, HubEntry *hub_list, int32_t *hub_off,
                            int32_t *hub_lvl_chunks, const int32_t *rp, int32_t src, int32_t n,
@@ -91,6 +101,9 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     const int32_t nch = hub ? (deg + kHubChunk - 1) / kHubChunk : 0;
     if (hub) hub_list[0] = HubEntry{src, 0, 0, nch};
     c->hub_pack_.v = 0;
+    c->in_hub_n = 0;
+    c->in_hub_nchunks = 0;
+    c->in_hub_pack_.v = 0;
     c->hub_lo = 0;
     c->hub_hi = hub ? 1 : 0;
     c->hub_nchunks = nch;
@@ -224,7 +237,9 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
                                                   const int32_t *__restrict__ queue,
                                                   const int32_t *__restrict__ dist, double *sigma,
                                                   HubEntry *hub_list, long long hub_cap,
-                                                  unsigned long long *prof, int32_t hub_deg) {
+                                                  unsigned long long *prof, int32_t hub_deg,
+                                                  const int32_t *__restrict__ rp_out,
+                                                  HubEntry *in_list, long long in_cap) {
     if (c->done) return;
     __shared__ int32_t s_coff[BS], s_beg[BS], s_deg[BS];
     __shared__ double s_acc[BS];
@@ -255,9 +270,16 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
         if (w >= 0) {
             my_deg += (unsigned long long)deg;
             ++my_items;
-            if (hub) {
+            if (in_list) {
+                // directed: rows walked by discovery and delta are the
+                // outgoing ones; the chunked path counts use in_list
+                const int32_t dout = rp_out[w + 1] - rp_out[w];
+                if (dout > hub_deg) hub_register(c, hub_list, hub_cap, w, i, dout);
+                if (hub) in_hub_register(c, in_list, in_cap, w, i, deg);
+            } else if (hub) {
                 hub_register(c, hub_list, hub_cap, w, i, deg);
-            } else {
+            }
+            if (!hub) {
                 my_scan += (unsigned long long)deg;
                 sigma[w] = s;
                 my_max = fmax(my_max, s);
@@ -291,6 +313,10 @@ __global__ void k_src_advance(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
     c->hub_pack_.v = 0;
     hub_off[nl + 1] = c->hub_hi;
     hub_lvl_chunks[nl] = c->hub_nchunks;
+    const unsigned long long ip = c->in_hub_pack_.v;
+    c->in_hub_n = (int32_t)(ip >> 40);
+    c->in_hub_nchunks = (int32_t)(ip & ((1ull << 40) - 1));
+    c->in_hub_pack_.v = 0;
     c->front_deg = c->next_deg_.v;
     c->unset_deg -= c->next_deg_.v;
     c->next_deg_.v = 0;
@@ -312,9 +338,11 @@ __global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t
                                                       const int32_t *__restrict__ dist,
                                                       double *sigma, const HubEntry *hub_list,
                                                       unsigned int *hub_cnt, double *partial,
-                                                      unsigned long long *prof) {
+                                                      unsigned long long *prof, int32_t use_in) {
     if (c->done) return;
-    const int32_t hlo = c->hub_lo, hhi = c->hub_hi, nch = c->hub_nchunks, pl = c->level - 1;
+    // undirected: the level's hub segment; directed: the incoming-row list
+    const int32_t hlo = use_in ? 0 : c->hub_lo, hhi = use_in ? c->in_hub_n : c->hub_hi;
+    const int32_t nch = use_in ? c->in_hub_nchunks : c->hub_nchunks, pl = c->level - 1;
     const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
     for (int64_t k = wave0; k < nch; k += nwaves) {
@@ -333,9 +361,9 @@ __global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t
 
 // Path counts of the current level's hubs from their chunk sums (a thread per hub).
 __global__ void k_src_sigma_hub_fin(LevelCtl *c, double *sigma, const HubEntry *__restrict__ hub_list,
-                                    const double *__restrict__ partial) {
+                                    const double *__restrict__ partial, int32_t use_in) {
     if (c->done) return;
-    const int32_t hlo = c->hub_lo, hhi = c->hub_hi;
+    const int32_t hlo = use_in ? 0 : c->hub_lo, hhi = use_in ? c->in_hub_n : c->hub_hi;
     for (int64_t j = hlo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hhi;
          j += (int64_t)gridDim.x * blockDim.x) {
         const HubEntry h = hub_list[j];
@@ -447,8 +475,10 @@ sp_status source_ws_create(sp_graph g, SourceWorkspace &ws) {
     SP_TRY(dev_alloc((void **)&ws.hub_off, (size_t)ws.level_cap * sizeof(int32_t)));
     SP_TRY(dev_alloc((void **)&ws.hub_lvl_chunks, (size_t)ws.level_cap * sizeof(int32_t)));
     SP_TRY(dev_alloc((void **)&ws.hub_list, ((size_t)g->n_hubs + 1) * sizeof(HubEntry)));
+    SP_TRY(dev_alloc((void **)&ws.in_hub_list, ((size_t)g->n_hubs_in + 1) * sizeof(HubEntry)));
     SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
-    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->hub_chunks + 1) * sizeof(double)));
+    SP_TRY(dev_alloc((void **)&ws.partial,
+                     ((size_t)std::max(g->hub_chunks, g->hub_chunks_in) + 1) * sizeof(double)));
     SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
     SP_HIP(hipHostMalloc((void **)&ws.ctl_host, sizeof(LevelCtl), hipHostMallocDefault));
@@ -466,6 +496,7 @@ void source_ws_destroy(SourceWorkspace &ws) {
     dev_free(ws.hub_off);
     dev_free(ws.hub_lvl_chunks);
     dev_free(ws.hub_list);
+    dev_free(ws.in_hub_list);
     dev_free(ws.hub_cnt);
     dev_free(ws.partial);
     dev_free(ws.ctl);
@@ -482,11 +513,14 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
     const int32_t n = g->n;
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
+    // Hub rows: discovery and the reverse pass walk outgoing rows, the path
+    // counts incoming ones.  On an undirected graph they are the same rows and
+    // one hub list serves all passes; a directed graph keeps a second list of
+    // the level's long incoming rows for the path counts.
     const bool hubs = g->n_hubs > 0;
-    // Directed graphs keep every row whole (no hub chunks): parents are read
-    // from the reversed rows and children from the forward ones, whose
-    // lengths differ, so one hub list cannot serve both passes.
-    const int32_t hub_deg = g->directed ? INT32_MAX : kHubDeg;
+    const bool hubs_in = g->n_hubs_in > 0;
+    const bool directed = g->directed;
+    const int32_t hub_deg = kHubDeg;
     const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
     SP_TRY(launch_fill_i32(ws.dist, n, -1, s));
     hipLaunchKernelGGL(k_src_init, dim3(1), dim3(1), 0, s, ws.ctl, ws.dist, ws.sigma, ws.queue,
@@ -513,19 +547,21 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                 ProfScope ps(P_SRC_SIGMA, s);
                 hipLaunchKernelGGL(k_src_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->rp_in,
                                    g->ci_in, ws.queue, ws.dist, ws.sigma, ws.hub_list,
-                                   (long long)g->n_hubs + 1, prof_counters(P_SRC_SIGMA), hub_deg);
+                                   (long long)g->n_hubs + 1, prof_counters(P_SRC_SIGMA), hub_deg,
+                                   (const int32_t *)g->row_ptr, directed ? ws.in_hub_list : nullptr,
+                                   (long long)g->n_hubs_in + 1);
             }
             hipLaunchKernelGGL(k_src_advance, dim3(1), dim3(1), 0, s, ws.ctl, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks);
-            if (hubs) {
+            if (hubs_in) {
                 ProfScope ps(P_SRC_SIGMA_HUB, s);
-                hipLaunchKernelGGL(k_src_sigma_hub<BS>, dim3(grid_for((int64_t)g->hub_chunks * kWave, BS, maxb)),
-                                   dim3(BS), 0, s, ws.ctl, g->row_ptr, g->col_idx, ws.dist, ws.sigma,
-                                   (const HubEntry *)ws.hub_list, ws.hub_cnt, ws.partial,
-                                   prof_counters(P_SRC_SIGMA_HUB));
-                hipLaunchKernelGGL(k_src_sigma_hub_fin, dim3(grid_for(g->n_hubs, 256, maxb)), dim3(256), 0, s,
-                                   ws.ctl, ws.sigma, (const HubEntry *)ws.hub_list,
-                                   (const double *)ws.partial);
+                const HubEntry *plist = directed ? ws.in_hub_list : ws.hub_list;
+                hipLaunchKernelGGL(k_src_sigma_hub<BS>,
+                                   dim3(grid_for((int64_t)g->hub_chunks_in * kWave, BS, maxb)), dim3(BS), 0, s,
+                                   ws.ctl, g->rp_in, g->ci_in, ws.dist, ws.sigma, plist, ws.hub_cnt,
+                                   ws.partial, prof_counters(P_SRC_SIGMA_HUB), (int32_t)directed);
+                hipLaunchKernelGGL(k_src_sigma_hub_fin, dim3(grid_for(g->n_hubs_in, 256, maxb)), dim3(256), 0,
+                                   s, ws.ctl, ws.sigma, plist, (const double *)ws.partial, (int32_t)directed);
             }
         }
         SP_HIP(hipGetLastError());
