@@ -378,6 +378,7 @@ def directed_benchmark(sp, torch, workload, n_sources):
         roofline = {"bound": "hbm", "achieved": dom[1]["GBps_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(dom[1]["GBps_algorithmic"] / HBM_PEAK_GBS, 4), "traffic": None,
                     "kernel": dom[0], "avg_launch_ms": round(dom[1]["ms"] / max(dom[1]["launches"], 1), 4)}
+        attach_traffic(roofline, "directed_" + workload)
     t0 = time.perf_counter()
     ref = oracle.bc(rp, ci, srcs[:2])
     cpu_s = time.perf_counter() - t0
