@@ -418,9 +418,39 @@ static void free_weights(sp_graph g) {
     g->weight_bytes = 0;
 }
 
+// Upload a hub list and its chunk owner map; on success the device copies go
+// to *hub_out / *owner_out and their bytes are added to the graph's size.
+static sp_status upload_hub_layout(sp_graph g, const std::vector<HubEntry> &hubs,
+                                   const std::vector<int32_t> &owners, hipStream_t st,
+                                   HubEntry **hub_out, int32_t **owner_out) {
+    HubEntry *hub_dev = nullptr;
+    int32_t *owner_dev = nullptr;
+    const size_t hb = sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1);
+    const size_t ob = sizeof(int32_t) * std::max<size_t>(owners.size(), 1);
+    sp_status rc = dev_alloc((void **)&hub_dev, hb);
+    if (rc == SP_OK) rc = dev_alloc((void **)&owner_dev, ob);
+    hipError_t e = hipSuccess;
+    if (rc == SP_OK && !hubs.empty())
+        e = hipMemcpyAsync(hub_dev, hubs.data(), hubs.size() * sizeof(HubEntry), hipMemcpyHostToDevice, st);
+    if (rc == SP_OK && e == hipSuccess && !owners.empty())
+        e = hipMemcpyAsync(owner_dev, owners.data(), owners.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st);
+    if (rc == SP_OK && e == hipSuccess) e = hipStreamSynchronize(st);
+    if (rc != SP_OK || e != hipSuccess) {
+        dev_free(hub_dev);
+        dev_free(owner_dev);
+        if (e != hipSuccess) set_error("hub list upload failed: %s", hipGetErrorString(e));
+        return rc != SP_OK ? rc : SP_ERR_DEVICE;
+    }
+    *hub_out = hub_dev;
+    *owner_out = owner_dev;
+    g->bytes += hb + ob;
+    return SP_OK;
+}
+
 // Every hub of the graph with its chunk range, in vertex order, and the hub
 // of every chunk: built once per graph on first use (SSSP pull rounds,
-// PageRank), kept until the graph is released.
+// triangle counting), kept until the graph is released.
 sp_status ensure_static_hubs(sp_graph g, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g->mu);
     if (g->hub_static) return SP_OK;
@@ -432,28 +462,25 @@ sp_status ensure_static_hubs(sp_graph g, hipStream_t st) {
             hubs.push_back(HubEntry{v, 0, (int32_t)owners.size(), nch});
             owners.insert(owners.end(), (size_t)nch, (int32_t)hubs.size() - 1);
         }
-    HubEntry *hub_static = nullptr;
-    int32_t *owner_static = nullptr;
-    const size_t hb = sizeof(HubEntry) * std::max<size_t>(hubs.size(), 1);
-    const size_t ob = sizeof(int32_t) * std::max<size_t>(owners.size(), 1);
-    sp_status rc = dev_alloc((void **)&hub_static, hb);
-    if (rc == SP_OK) rc = dev_alloc((void **)&owner_static, ob);
-    hipError_t e = hipSuccess;
-    if (rc == SP_OK && !hubs.empty())
-        e = hipMemcpyAsync(hub_static, hubs.data(), hubs.size() * sizeof(HubEntry), hipMemcpyHostToDevice, st);
-    if (rc == SP_OK && e == hipSuccess && !owners.empty())
-        e = hipMemcpyAsync(owner_static, owners.data(), owners.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, st);
-    if (rc == SP_OK && e == hipSuccess) e = hipStreamSynchronize(st);
-    if (rc != SP_OK || e != hipSuccess) {
-        dev_free(hub_static);
-        dev_free(owner_static);
-        if (e != hipSuccess) set_error("hub list upload failed: %s", hipGetErrorString(e));
-        return rc != SP_OK ? rc : SP_ERR_DEVICE;
-    }
-    g->hub_static = hub_static;
-    g->owner_static = owner_static;
-    g->bytes += hb + ob;
+    return upload_hub_layout(g, hubs, owners, st, &g->hub_static, &g->owner_static);
+}
+
+// PageRank's hub layout: every hub cut by row eighths into 8m near-equal
+// pieces of at most kHubChunk entries (split_piece), m = ceil(deg / (8 *
+// kHubChunk)); every hub's first chunk id is a multiple of 8.
+sp_status ensure_pr_hubs(sp_graph g, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->pr_hubs) return SP_OK;
+    std::vector<HubEntry> hubs;
+    std::vector<int32_t> owners;
+    for (int32_t v = 0; v < g->n; ++v)
+        if (g->host_deg[v] > kHubDeg) {
+            const int32_t nch = kXcds * ((g->host_deg[v] + kXcds * kHubChunk - 1) / (kXcds * kHubChunk));
+            hubs.push_back(HubEntry{v, 0, (int32_t)owners.size(), nch});
+            owners.insert(owners.end(), (size_t)nch, (int32_t)hubs.size() - 1);
+        }
+    SP_TRY(upload_hub_layout(g, hubs, owners, st, &g->pr_hubs, &g->pr_owner));
+    g->pr_chunks = (int64_t)owners.size();
     return SP_OK;
 }
 
@@ -583,6 +610,7 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
         if (d > kHubDeg) {
             g->n_hubs++;
             g->hub_chunks += (d + kHubChunk - 1) / kHubChunk;
+            g->ms_hub_chunks += ms_hub_span(d);
         }
     }
     g->max_degree = md;
@@ -709,6 +737,8 @@ sp_status sp_graph_release(sp_graph g) {
     dev_free(g->tc_osrc);
     dev_free(g->hub_static);
     dev_free(g->owner_static);
+    dev_free(g->pr_hubs);
+    dev_free(g->pr_owner);
     dev_free(g->row_ptr);
     dev_free(g->col_idx);
     delete g;
@@ -1174,7 +1204,7 @@ sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, d
     if (g->n == 0) return SP_OK;
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;
-    SP_TRY(ensure_static_hubs(g, st));
+    SP_TRY(ensure_pr_hubs(g, st));
     PrWorkspace *ws = nullptr;
     SP_TRY(acquire_pr_ws(g, &ws));
     struct Rel {

@@ -130,6 +130,44 @@ __device__ __forceinline__ void window_acc(uint4 fu, unsigned long long m, uint3
 
 __device__ __forceinline__ uint4 no_front() { return make_uint4(0u, 0u, kNoTag, 0u); }
 
+// Hub registration for the batched path's chunking (ms_hub_nchunks): reserves
+// ms_hub_span(deg) chunk ids and aligns a split hub's first id to a multiple
+// of kXcds; every reserved id, the alignment slack included, records the hub
+// in `owner`, and ms_chunk_range turns the slack ids away.  Overflows of the
+// list or the owner map are reported by `advance`, as for the other paths.
+__device__ __forceinline__ void ms_hub_register(LevelCtl *c, HubEntry *list, long long cap,
+                                                int32_t v, int32_t entry, int32_t deg,
+                                                int32_t *owner, long long owner_cap) {
+    const int32_t nch = ms_hub_nchunks(deg), span = ms_hub_span(deg);
+    const unsigned long long old = atomicAdd(&c->hub_pack_.v, (1ull << 40) | (unsigned long long)span);
+    const int32_t idx = (int32_t)(old >> 40);
+    const int32_t at = (int32_t)(old & ((1ull << 40) - 1));
+    const int32_t base = nch >= kXcds ? (at + kXcds - 1) & ~(kXcds - 1) : at;
+    if ((long long)c->hub_next + idx < cap) list[c->hub_next + idx] = HubEntry{v, entry, base, nch};
+    for (int32_t q = 0; q < span; ++q) {
+        const long long p = (long long)c->chunk_next + at + q;
+        if (p < owner_cap) owner[p] = c->hub_next + idx;
+    }
+}
+
+// Adjacency range [beg, end) of level-local chunk id k of hub h; false for an
+// alignment slack id.  Hubs of fewer than kXcds chunks: consecutive kHubChunk
+// pieces; split hubs: split_piece.
+__device__ __forceinline__ bool ms_chunk_range(const HubEntry &h, int64_t k,
+                                               const int32_t *__restrict__ rp, int32_t &beg,
+                                               int32_t &end) {
+    const int32_t t = (int32_t)k - h.chunk_base;
+    if (t < 0 || t >= h.nchunks) return false;
+    const int32_t rb = rp[h.v];
+    if (h.nchunks < kXcds) {
+        beg = rb + t * kHubChunk;
+        end = min(rp[h.v + 1], beg + kHubChunk);
+    } else {
+        split_piece(rb, rp[h.v + 1] - rb, h.nchunks, t, beg, end);
+    }
+    return true;
+}
+
 // dense_sum given the records `f` of the first window (entries [beg, beg+kWave)).
 __device__ __forceinline__ double dense_sum_from(uint4 f, int32_t beg, int32_t end,
                                                  unsigned long long m, uint32_t tag,
@@ -292,11 +330,12 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
             fdeg += (unsigned long long)d;
             pairs += (unsigned long long)__popcll(qmask[i]);
             if (qmask[i] == active) settled += (unsigned long long)d;
-            if (d > kHubDeg) {
-                const int32_t k = (d + kHubChunk - 1) / kHubChunk;
-                for (int32_t q = 0; q < k; ++q) owner[nch + q] = nh;  // at most kSlots hubs
-                hub_list[nh++] = HubEntry{v, i, nch, k};
-                nch += k;
+            if (d > kHubDeg) {  // at most kSlots hubs; split hubs start at a multiple of kXcds
+                const int32_t k = ms_hub_nchunks(d);
+                const int32_t base = k >= kXcds ? (nch + kXcds - 1) & ~(kXcds - 1) : nch;
+                for (int32_t q = nch; q < base + k; ++q) owner[q] = nh;
+                hub_list[nh++] = HubEntry{v, i, base, k};
+                nch = base + k;
             }
         }
         c->level = 0;
@@ -404,11 +443,13 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
         }
     } else {
         const int32_t nch = c->hub_nchunks, obase = chunk_off[c->level];
+        // block k takes chunk id k: with a grid that is a multiple of kXcds,
+        // XCD x gets the ids congruent to x, as in the hub sum kernels
         for (int32_t k = blockIdx.x; k < nch; k += gridDim.x) {
             const HubEntry h = hub_list[owner[obase + k]];
+            int32_t beg, end;
+            if (!ms_chunk_range(h, k, rp, beg, end)) continue;
             const unsigned long long fm = qmask[h.entry];
-            const int32_t beg = rp[h.v] + (k - h.chunk_base) * kHubChunk;
-            const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
             my_edges += (threadIdx.x == 0) ? (unsigned long long)(end - beg) : 0ull;
             for (int32_t e0 = beg; e0 < end; e0 += BS) {
                 const int32_t e = e0 + threadIdx.x;
@@ -640,7 +681,7 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                        }
                        my_flag |= __ballot(mine && sigma_is_large(acc));
                    });
-        if (hub) hub_register(c, hub_list, hub_cap, w, i, deg, owner, owner_cap);
+        if (hub) ms_hub_register(c, hub_list, hub_cap, w, i, deg, owner, owner_cap);
         if (sparse || dense) my_scan += (unsigned long long)deg;  // hubs: k_ms_sigma_hub
         if (valid) {
             qmask[i] = m;
@@ -887,6 +928,23 @@ __device__ __forceinline__ double sum_rows(const double *__restrict__ partial, i
     return s;
 }
 
+// A hub's chunk rows added in row order (split_id for a split hub).
+__device__ __forceinline__ double sum_hub_rows(const double *__restrict__ partial,
+                                               const HubEntry &h) {
+    if (h.nchunks < kXcds) return sum_rows(partial, h.chunk_base, h.nchunks);
+    const int lane = lane_id();
+    double s = 0.0;
+    for (int32_t r = 0; r < h.nchunks; r += 8) {  // nchunks is a multiple of 8
+        double x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            x[t] = partial[(int64_t)(h.chunk_base + split_id(h.nchunks, r + t)) * kSlots + lane];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += x[t];
+    }
+    return s;
+}
+
 // Path counts of the current level's hubs (after advance), chunk by chunk.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t *__restrict__ rp,
@@ -903,20 +961,17 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
     const int32_t nch = c->hub_nchunks, obase = chunk_off[c->level];
     const uint32_t pl = (uint32_t)c->level - 1;
     const int lane = lane_id();
-    const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
-    unsigned long long my_dag = 0, my_edges = 0, my_flag = 0;
-    double my_max = 0.0;
-    for (int64_t k = wave0; k < nch; k += nwaves) {
+    unsigned long long my_dag = 0, my_edges = 0;
+    for_xcd_chunks<BS>(nch, [&](int64_t k) {
         const HubEntry h = hub_list[owner[obase + k]];
+        int32_t beg, end;
+        if (!ms_chunk_range(h, k, rp, beg, end)) return;
         const unsigned long long m = qmask[h.entry];
-        const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
-        const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
-        partial[(int64_t)k * kSlots + lane] = dense_sum(beg, end, m, pl, ci, front_par, val, pr);
+        partial[k * kSlots + lane] = dense_sum(beg, end, m, pl, ci, front_par, val, pr);
         if (lane == 0) my_dag += pr;
-    }
+    });
     if (prof) {
         block_add_u64<BS>(my_edges, s_red, prof + 1);
         __syncthreads();
@@ -940,7 +995,7 @@ __global__ void k_ms_sigma_hub_fin(LevelCtl *c, const unsigned long long *__rest
     for (int64_t j = hlo + wave0; j < hhi; j += nwaves) {
         const HubEntry h = hub_list[j];
         const unsigned long long m = qmask[h.entry];
-        const double s = sum_rows(partial, h.chunk_base, h.nchunks);
+        const double s = sum_hub_rows(partial, h);
         const bool mine = (m >> lane) & 1ull;
         if (mine) {
             val[qvb[h.entry] + rank_in(m, lane)] = s;
@@ -1082,19 +1137,17 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
     const int32_t obase = chunk_off[lvl];
     const uint32_t nl = (uint32_t)lvl + 1;
     const int lane = lane_id();
-    const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
     unsigned long long my_edges = 0, my_pairs = 0;
-    for (int64_t k = wave0; k < nch; k += nwaves) {
+    for_xcd_chunks<BS>(nch, [&](int64_t k) {
         const HubEntry h = hub_list[owner[obase + k]];
+        int32_t beg, end;
+        if (!ms_chunk_range(h, k, rp, beg, end)) return;
         const unsigned long long m = qmask[h.entry];
-        const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
-        const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
-        partial[(int64_t)k * kSlots + lane] = dense_sum(beg, end, m, nl, ci, front_rd, val, pr);
+        partial[k * kSlots + lane] = dense_sum(beg, end, m, nl, ci, front_rd, val, pr);
         if (lane == 0) my_pairs += pr;
-    }
+    });
     if (prof) {
         block_add_u64<BS>(my_edges, s_red, prof + 1);
         __syncthreads();
@@ -1127,7 +1180,7 @@ __global__ void k_ms_delta_hub_fin(LevelCtl *c, const int32_t *__restrict__ hub_
     for (int64_t j = wave0; j < nh; j += nwaves) {
         const HubEntry h = hub_list[hlo + j];
         const unsigned long long m = qmask[h.entry];
-        const double s = sum_rows(partial, h.chunk_base, h.nchunks);
+        const double s = sum_hub_rows(partial, h);
         if ((m >> lane) & 1ull)
             finish_slot(s, val + qvb[h.entry] + rank_in(m, lane), dlt + (int64_t)h.v * kSlots + lane);
     }
@@ -1225,7 +1278,14 @@ __global__ void k_ms_extract(const int32_t *__restrict__ queue,
 // ---------------------------------------------------------------------------
 static int64_t hub_capacity(sp_graph g) { return (int64_t)g->n_hubs * kSlots + kSlots; }
 // A hub has at most one entry per slot, so at most kSlots entries per pass.
-static int64_t owner_capacity(sp_graph g) { return g->hub_chunks * kSlots + kSlots; }
+static int64_t owner_capacity(sp_graph g) { return g->ms_hub_chunks * kSlots + kSlots; }
+
+// Grids of the hub chunk kernels: a multiple of kXcds blocks (at least kXcds,
+// at most max_blocks when that is a multiple), so that every XCD holds blocks.
+static int xcd_grid(int grid, int max_blocks) {
+    const int g = (std::max(grid, kXcds) + kXcds - 1) / kXcds * kXcds;
+    return g <= max_blocks ? g : std::max(kXcds, max_blocks / kXcds * kXcds);
+}
 
 static int64_t value_capacity(sp_graph g, int32_t width) {
     return (int64_t)std::max(g->n, 1) * width + kSlots;
@@ -1237,7 +1297,7 @@ size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
            (size_t)qcap * 16 + (V + 2) * 12 + kSlots * 4 +
            (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
            (size_t)owner_capacity(g) * 4 + (V + 2) * 4 +
-           ((size_t)g->hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
+           ((size_t)g->ms_hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
 }
 
 sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws) {
@@ -1270,7 +1330,7 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
     SP_TRY(dev_alloc((void **)&ws.hub_lvl_chunks, (size_t)ws.level_cap * 4));
     SP_TRY(dev_alloc((void **)&ws.hub_list, (size_t)ws.hub_cap * sizeof(HubEntry)));
     SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * 4));
-    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->hub_chunks + 1) * kSlots * 8));
+    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->ms_hub_chunks + 1) * kSlots * 8));
     SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * 4));
     SP_TRY(dev_alloc((void **)&ws.slot_src, kSlots * 4));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
@@ -1413,7 +1473,7 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
     const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
-    const int hub_grid = grid_for((int64_t)g->hub_chunks * kWave, BS, maxb);
+    const int hub_grid = xcd_grid(grid_for((int64_t)g->ms_hub_chunks * kWave, BS, maxb), maxb);
     hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.seen, ws.nxt,
                        ws.front[0], ws.front[1], n);
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, s, ws.ctl, (const int32_t *)g->row_ptr,
@@ -1568,7 +1628,8 @@ static sp_status batch_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *src
         if (l < levels - 1) maxh = std::max(maxh, hch[l]);
     }
     const int grid_d = pow2_at_least(grid_for(maxcnt, BS, maxb), maxb);
-    const int grid_h = pow2_at_least(grid_for((int64_t)std::max(maxh, 1) * kWave, BS, maxb), maxb);
+    const int grid_h =
+        xcd_grid(pow2_at_least(grid_for((int64_t)std::max(maxh, 1) * kWave, BS, maxb), maxb), maxb);
     const bool hubs = maxh > 0;
     hipLaunchKernelGGL(k_ms_bwd_init, dim3(1), dim3(1), 0, s, ws.ctl);
     const int32_t steps = levels - 1;  // levels L-1 .. 1

@@ -75,6 +75,7 @@ struct sp_graph_s {
     int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
     int32_t n_hubs_in = 0;       // the same for incoming rows (= n_hubs when undirected)
     int64_t hub_chunks_in = 0;
+    int64_t ms_hub_chunks = 0;   // sum over hubs of ms_hub_span(degree): batched path
     size_t bytes = 0;
     std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
     std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
@@ -91,6 +92,10 @@ struct sp_graph_s {
     // chunk; built on first use by the whole-graph kernels (ensure_static_hubs).
     sp::HubEntry *hub_static = nullptr;  // device, n_hubs (>= 1)
     int32_t *owner_static = nullptr;     // device, hub_chunks (>= 1)
+    // PageRank's hub chunks, cut by row eighths (ensure_pr_hubs).
+    sp::HubEntry *pr_hubs = nullptr;     // device, n_hubs (>= 1)
+    int32_t *pr_owner = nullptr;         // device, pr_chunks (>= 1)
+    int64_t pr_chunks = 0;
     // Triangle counting: rows oriented toward higher (degree, id) rank, built
     // on first use (ensure_oriented): offsets, entries, and each entry's row.
     int32_t *tc_orp = nullptr;       // device, n + 1
@@ -124,6 +129,26 @@ enum : int32_t { MODE_TOPDOWN = 0, MODE_BOTTOMUP = 1 };
 // chunks 256-1024.
 constexpr int32_t kHubDeg = 256;
 constexpr int32_t kHubChunk = 512;
+
+// Batched path: a hub of more than kHubSplitDeg neighbours is cut into 8*m
+// chunks of near-equal length (at most kHubChunk), m = ceil(deg/(8*kHubChunk)),
+// numbered so that chunk id mod 8 names the eighth of the row the chunk lies
+// in, with the hub's first id a multiple of 8.  Workgroups are dispatched to
+// the device's 8 XCDs round-robin, so when the chunk kernels give the waves of
+// block b the chunk ids congruent to b mod 8, each XCD (with its own L2)
+// gathers from one eighth of every such hub row: one eighth of the vertex ids
+// when they are randomly numbered.  A registration reserves 7 ids more than it
+// uses, to align its first id.  Smaller hubs keep kHubChunk-entry chunks (at
+// most 4), so a hub is split exactly when it has 8 or more chunks.
+constexpr int32_t kXcds = 8;
+constexpr int32_t kHubSplitDeg = 4 * kHubChunk;
+__host__ __device__ constexpr int32_t ms_hub_nchunks(int32_t deg) {
+    return deg > kHubSplitDeg ? kXcds * ((deg + kXcds * kHubChunk - 1) / (kXcds * kHubChunk))
+                              : (deg + kHubChunk - 1) / kHubChunk;
+}
+__host__ __device__ constexpr int32_t ms_hub_span(int32_t deg) {
+    return deg > kHubSplitDeg ? ms_hub_nchunks(deg) + kXcds - 1 : ms_hub_nchunks(deg);
+}
 
 // One hub occurrence on a level: vertex, its queue entry, and the range of
 // level-local chunk ids [chunk_base, chunk_base + nchunks).
@@ -478,6 +503,8 @@ sp_status undirected_only(const char *what);
 
 // Builds g->hub_static / g->owner_static once (thread-safe).
 sp_status ensure_static_hubs(sp_graph g, hipStream_t s);
+// Builds g->pr_hubs / g->pr_owner once (thread-safe).
+sp_status ensure_pr_hubs(sp_graph g, hipStream_t s);
 
 // Workspace pools and configuration shared by the entry points and the server.
 int64_t initial_qcap(int32_t n, int32_t width);

@@ -302,6 +302,58 @@ __device__ __forceinline__ void hub_chunk(int32_t k, int32_t beg, int32_t end, d
     if (lane == 0) partial[k] = x;
 }
 
+// Rows cut by row eighths (kXcds): a row of deg entries in nchunks = 8m
+// near-equal pieces; chunk id offset t = 8g + x is piece x*m + g, in the x-th
+// eighth of the row.  Workgroups are dispatched to the device's XCDs
+// round-robin and each XCD has its own L2, so when the waves of block b take
+// the ids congruent to b mod 8 (for_xcd_chunks) and every split row starts at
+// an id that is a multiple of 8, each XCD gathers from one eighth of every
+// such row: one eighth of the vertex ids when they are randomly numbered.
+__device__ __forceinline__ void split_piece(int32_t rb, int32_t deg, int32_t nchunks, int32_t t,
+                                            int32_t &beg, int32_t &end) {
+    const int32_t m = nchunks / kXcds;
+    const int64_t r = (int64_t)(t % kXcds) * m + t / kXcds;
+    beg = rb + (int32_t)((int64_t)deg * r / nchunks);
+    end = rb + (int32_t)((int64_t)deg * (r + 1) / nchunks);
+}
+
+// Chunk id offset of the piece at row position r (inverse of split_piece).
+__device__ __forceinline__ int32_t split_id(int32_t nchunks, int32_t r) {
+    const int32_t m = nchunks / kXcds;
+    return (r % m) * kXcds + r / m;
+}
+
+// Wave loop over chunk ids [0, nch): the waves of block b take the ids
+// congruent to b mod kXcds.  A grid that is not a multiple of kXcds walks the
+// ids in plain wave order.  Either way every id is visited exactly once.
+template <int BS, class F>
+__device__ __forceinline__ void for_xcd_chunks(int64_t nch, F f) {
+    constexpr int64_t wpb = BS / kWave;
+    const int64_t w = threadIdx.x / kWave;
+    if ((gridDim.x % kXcds) == 0) {
+        const int64_t x = blockIdx.x % kXcds;
+        const int64_t j = (int64_t)(blockIdx.x / kXcds) * wpb + w;
+        for (int64_t k = x + kXcds * j; k < nch; k += (int64_t)gridDim.x * wpb) f(k);
+    } else {
+        for (int64_t k = (int64_t)blockIdx.x * wpb + w; k < nch; k += (int64_t)gridDim.x * wpb)
+            f(k);
+    }
+}
+
+// Sum of a split row's chunk sums in row order, eight loads in flight.
+__device__ __forceinline__ double sum_split_chunks(const double *__restrict__ partial,
+                                                   int32_t base, int32_t n) {
+    double s = 0.0;
+    for (int32_t r = 0; r < n; r += 8) {  // n is a multiple of 8
+        double x[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) x[t] = partial[base + split_id(n, r + t)];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += x[t];
+    }
+    return s;
+}
+
 // Sum of partial[base .. base+n) in index order, eight loads in flight.
 __device__ __forceinline__ double sum_chunks(const double *__restrict__ partial, int32_t base,
                                              int32_t n) {

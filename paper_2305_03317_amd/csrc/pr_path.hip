@@ -12,9 +12,9 @@
 // 8 entries are summed in row order by their own lane, longer ones by the
 // wave in chunks of 8 aligned at the row start (wave_chunk_sum); either way a
 // vertex's sum depends only on its row, so results are reproducible.  Rows
-// longer than kHubDeg are cut
-// into chunks of kHubChunk that waves reduce into partials, added in chunk
-// order by a finishing kernel.  The stopping test sums |val - pr| per block in
+// longer than kHubDeg are cut by row eighths into 8m pieces of at most
+// kHubChunk entries (split_piece), which waves reduce into partials, one XCD
+// per eighth; a finishing kernel adds a row's partials in row order.  The stopping test sums |val - pr| per block in
 // a fixed order and adds the block sums as fixed-point integers, so the total
 // and the decision do not depend on scheduling.  The last working block of an
 // iteration's last kernel closes it; chunks of iterations are captured as HIP
@@ -148,21 +148,21 @@ __global__ __launch_bounds__(BS) void k_pr_pull(PrCtl *c, const int32_t *__restr
         }
         add_block_diff<BS>(c, my_diff, s_w);
     } else {
-        const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
-        const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
-        for (int64_t k = wave0; k < nch; k += nwaves) {
+        // with a grid that is a multiple of 8, block (x, 1) runs on XCD x mod 8
+        for_xcd_chunks<BS>(nch, [&](int64_t k) {
             const HubEntry h = hs[os[k]];
-            const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
-            const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+            const int32_t rb = rp[h.v];
+            int32_t beg, end;
+            split_piece(rb, rp[h.v + 1] - rb, h.nchunks, (int32_t)k - h.chunk_base, beg, end);
             hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) { return sh[ci[e]]; });
             my_edges += lane == 0 ? (unsigned long long)(end - beg) : 0ull;
-        }
+        });
     }
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
     if (closes && last_block(c, working_blocks((int64_t)n, BS)) && threadIdx.x == 0) close_iteration(c);
 }
 
-// Hubs of one iteration from their chunk sums, in chunk order (a thread per
+// Hubs of one iteration from their chunk sums, in row order (a thread per
 // hub); closes the iteration.
 __global__ void k_pr_hub_fin(PrCtl *c, const int32_t *__restrict__ rp, double *pr0, double *pr1,
                              double *sh0, double *sh1, const double *__restrict__ partial,
@@ -178,7 +178,7 @@ __global__ void k_pr_hub_fin(PrCtl *c, const int32_t *__restrict__ rp, double *p
     const int32_t stride = gridDim.x * blockDim.x;
     for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nh; j += stride) {
         const HubEntry h = hs[j];
-        const double val = teleport + delta * sum_chunks(partial, h.chunk_base, h.nchunks);
+        const double val = teleport + delta * sum_split_chunks(partial, h.chunk_base, h.nchunks);
         my_diff += fabs(val - pr[h.v]);
         pr_n[h.v] = val;
         sh_n[h.v] = val / (double)(rp[h.v + 1] - rp[h.v]);
@@ -198,7 +198,7 @@ sp_status pr_ws_create(sp_graph g, PrWorkspace &ws) {
         st = dev_alloc((void **)&ws.pr[p], sizeof(double) * n);
         if (st == SP_OK) st = dev_alloc((void **)&ws.share[p], sizeof(double) * n);
     }
-    if (st == SP_OK) st = dev_alloc((void **)&ws.partial, sizeof(double) * ((size_t)g->hub_chunks + 1));
+    if (st == SP_OK) st = dev_alloc((void **)&ws.partial, sizeof(double) * ((size_t)g->pr_chunks + 1));
     if (st == SP_OK) st = dev_alloc((void **)&ws.ctl, sizeof(PrCtl));
     if (st != SP_OK) {
         pr_ws_destroy(ws);
@@ -245,15 +245,15 @@ static void enqueue_iterations(sp_graph g, PrWorkspace &ws, int count, int grid,
             hipLaunchKernelGGL(k_pr_pull<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
                                (const int32_t *)g->row_ptr, (const int32_t *)g->col_idx, ws.pr[0],
                                ws.pr[1], ws.share[0], ws.share[1], ws.partial,
-                               (const HubEntry *)g->hub_static, (const int32_t *)g->owner_static, g->n,
-                               (int32_t)g->hub_chunks, teleport, delta, (int32_t)!hubs, parity,
+                               (const HubEntry *)g->pr_hubs, (const int32_t *)g->pr_owner, g->n,
+                               (int32_t)g->pr_chunks, teleport, delta, (int32_t)!hubs, parity,
                                prof_counters(P_PR_PULL));
         }
         if (hubs) {
             ProfScope ps(P_PR_HUB, s);
             hipLaunchKernelGGL(k_pr_hub_fin, dim3(fin_grid), dim3(256), 0, s, ws.ctl,
                                (const int32_t *)g->row_ptr, ws.pr[0], ws.pr[1], ws.share[0], ws.share[1],
-                               (const double *)ws.partial, (const HubEntry *)g->hub_static, g->n_hubs,
+                               (const double *)ws.partial, (const HubEntry *)g->pr_hubs, g->n_hubs,
                                teleport, delta, parity);
         }
     }
@@ -284,7 +284,7 @@ static sp_status pr_run_bs(sp_graph g, PrWorkspace &ws, double beta, double delt
         if (capture) {
             const std::array<long long, 12> key = {
                 BS, grid, fin_grid, chunk, (long long)(intptr_t)ws.pr[0], (long long)(intptr_t)ws.ctl,
-                (long long)(intptr_t)g->hub_static, bits_of(teleport),
+                (long long)(intptr_t)g->pr_hubs, bits_of(teleport),
                 bits_of(delta), g->n_hubs, 0, 0};
             SP_TRY(replay_captured(&ws.cap_stream, ws.iters, key,
                                    [&](hipStream_t cs) {

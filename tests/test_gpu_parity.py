@@ -164,6 +164,53 @@ def test_rmat_14_both_paths(sp):
     g.release()
 
 
+HUB_DEGREES = (2048, 2049, 3000, 4096, 4097, 8193, 40000)
+
+
+def split_hub_graph(seed=31):
+    """Sparse random graph on 60000 vertices plus hubs (vertices 60000 on)
+    of exactly the degrees in HUB_DEGREES: either side of the batched path's
+    split threshold (2048) and of its piece-count steps (every 4096)."""
+    n0 = 60000
+    n = n0 + len(HUB_DEGREES)
+    rng = np.random.default_rng(seed)
+    base = graphs.uniform(n0, 120000, seed)
+    src = [np.repeat(np.arange(n0, dtype=np.int64), np.diff(base[0]))]
+    dst = [base[1].astype(np.int64)]
+    for i, d in enumerate(HUB_DEGREES):
+        src.append(np.full(d, n0 + i, np.int64))
+        dst.append(rng.choice(n0, size=d, replace=False).astype(np.int64))
+    rp, ci = graphs.from_edges(n, np.concatenate(src), np.concatenate(dst))
+    assert list(np.diff(rp)[n0:]) == list(HUB_DEGREES)
+    return rp, ci
+
+
+@pytest.mark.parametrize("case", ["rmat-16", "synthetic"])
+def test_split_hubs(sp, case):
+    # hubs above 2048 neighbours are cut into 8m pieces numbered by row eighth
+    # in the batched path; sources include the hubs themselves (level-0 hubs)
+    if case == "rmat-16":
+        rp, ci = graphs.rmat(16, 16, graphs.RMAT_ABC, 8)
+        deg = np.diff(rp)
+        assert (deg > 2048).sum() >= 10
+        top = np.argsort(-deg, kind="stable")[:6].astype(np.int32)
+    else:
+        rp, ci = split_hub_graph()
+        top = np.arange(60000, 60000 + len(HUB_DEGREES), dtype=np.int32)[::-1].copy()
+    rest = [s for s in graphs.sources(rp, 80, 32, min_degree=1) if s not in set(top.tolist())]
+    srcs = np.concatenate([top, np.array(rest[:64 - len(top)], np.int32)])
+    print(case, "vertices", len(rp) - 1, "max degree", int(np.diff(rp).max()), flush=True)
+    g = sp.sp_graph_upload(rp, ci)
+    ref = oracle.bc(rp, ci, srcs)
+    b, sb = sp.sp_bc_batch(g, srcs)
+    assert sb == sp.SP_OK
+    assert_bc(b.cpu().numpy(), ref, "sp_bc_batch " + case)
+    b2, _ = sp.sp_bc_batch(g, srcs[::-1].copy())
+    assert_bc(b2.cpu().numpy(), ref, "sp_bc_batch reversed " + case)
+    check_sources_detail(sp, g, rp, ci, srcs[:12])
+    g.release()
+
+
 def test_road_grid_128(sp):
     """High diameter (hundreds of levels) and path counts beyond 2^53."""
     rp, ci = graphs.road(128, 0.02, 9)
