@@ -618,6 +618,7 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     g->ci_in = g->col_idx;
     g->n_hubs_in = g->n_hubs;
     g->hub_chunks_in = g->hub_chunks;
+    g->ms_hub_chunks_in = g->ms_hub_chunks;
     g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
     *out = g;
     return SP_OK;
@@ -685,13 +686,14 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
     }
     int32_t md = g->max_degree;
     int32_t nh_in = 0;
-    int64_t nch_in = 0;
+    int64_t nch_in = 0, ms_in = 0;
     for (int32_t v = 0; v < n_vertices; ++v) {
         const int32_t d = ir[v + 1] - ir[v];
         md = std::max(md, d);
         if (d > kHubDeg) {
             ++nh_in;
             nch_in += (d + kHubChunk - 1) / kHubChunk;
+            ms_in += ms_hub_span(d);
         }
     }
     g->rp_in = rp_in;
@@ -700,6 +702,7 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
     g->max_degree = md;
     g->n_hubs_in = nh_in;  // n_hubs / hub_chunks count the outgoing rows
     g->hub_chunks_in = nch_in;
+    g->ms_hub_chunks_in = ms_in;
     g->bytes += ir.size() * 4 + ic.size() * 4;
     *out = g;
     return SP_OK;

@@ -133,7 +133,7 @@ __device__ __forceinline__ uint4 no_front() { return make_uint4(0u, 0u, kNoTag, 
 // Hub registration for the batched path's chunking (ms_hub_nchunks): reserves
 // ms_hub_span(deg) chunk ids and aligns a split hub's first id to a multiple
 // of kXcds; every reserved id, the alignment slack included, records the hub
-// in `owner`, and ms_chunk_range turns the slack ids away.  Overflows of the
+// in `owner`, and hub_chunk_range turns the slack ids away.  Overflows of the
 // list or the owner map are reported by `advance`, as for the other paths.
 __device__ __forceinline__ void ms_hub_register(LevelCtl *c, HubEntry *list, long long cap,
                                                 int32_t v, int32_t entry, int32_t deg,
@@ -148,24 +148,6 @@ __device__ __forceinline__ void ms_hub_register(LevelCtl *c, HubEntry *list, lon
         const long long p = (long long)c->chunk_next + at + q;
         if (p < owner_cap) owner[p] = c->hub_next + idx;
     }
-}
-
-// Adjacency range [beg, end) of level-local chunk id k of hub h; false for an
-// alignment slack id.  Hubs of fewer than kXcds chunks: consecutive kHubChunk
-// pieces; split hubs: split_piece.
-__device__ __forceinline__ bool ms_chunk_range(const HubEntry &h, int64_t k,
-                                               const int32_t *__restrict__ rp, int32_t &beg,
-                                               int32_t &end) {
-    const int32_t t = (int32_t)k - h.chunk_base;
-    if (t < 0 || t >= h.nchunks) return false;
-    const int32_t rb = rp[h.v];
-    if (h.nchunks < kXcds) {
-        beg = rb + t * kHubChunk;
-        end = min(rp[h.v + 1], beg + kHubChunk);
-    } else {
-        split_piece(rb, rp[h.v + 1] - rb, h.nchunks, t, beg, end);
-    }
-    return true;
 }
 
 // dense_sum given the records `f` of the first window (entries [beg, beg+kWave)).
@@ -448,7 +430,7 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
         for (int32_t k = blockIdx.x; k < nch; k += gridDim.x) {
             const HubEntry h = hub_list[owner[obase + k]];
             int32_t beg, end;
-            if (!ms_chunk_range(h, k, rp, beg, end)) continue;
+            if (!hub_chunk_range(h, k, rp, beg, end)) continue;
             const unsigned long long fm = qmask[h.entry];
             my_edges += (threadIdx.x == 0) ? (unsigned long long)(end - beg) : 0ull;
             for (int32_t e0 = beg; e0 < end; e0 += BS) {
@@ -965,7 +947,7 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
     for_xcd_chunks<BS>(nch, [&](int64_t k) {
         const HubEntry h = hub_list[owner[obase + k]];
         int32_t beg, end;
-        if (!ms_chunk_range(h, k, rp, beg, end)) return;
+        if (!hub_chunk_range(h, k, rp, beg, end)) return;
         const unsigned long long m = qmask[h.entry];
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
@@ -1141,7 +1123,7 @@ __global__ __launch_bounds__(BS) void k_ms_delta_hub(
     for_xcd_chunks<BS>(nch, [&](int64_t k) {
         const HubEntry h = hub_list[owner[obase + k]];
         int32_t beg, end;
-        if (!ms_chunk_range(h, k, rp, beg, end)) return;
+        if (!hub_chunk_range(h, k, rp, beg, end)) return;
         const unsigned long long m = qmask[h.entry];
         if (lane == 0) my_edges += (unsigned long long)(end - beg);
         unsigned long long pr = 0;
@@ -1279,13 +1261,6 @@ __global__ void k_ms_extract(const int32_t *__restrict__ queue,
 static int64_t hub_capacity(sp_graph g) { return (int64_t)g->n_hubs * kSlots + kSlots; }
 // A hub has at most one entry per slot, so at most kSlots entries per pass.
 static int64_t owner_capacity(sp_graph g) { return g->ms_hub_chunks * kSlots + kSlots; }
-
-// Grids of the hub chunk kernels: a multiple of kXcds blocks (at least kXcds,
-// at most max_blocks when that is a multiple), so that every XCD holds blocks.
-static int xcd_grid(int grid, int max_blocks) {
-    const int g = (std::max(grid, kXcds) + kXcds - 1) / kXcds * kXcds;
-    return g <= max_blocks ? g : std::max(kXcds, max_blocks / kXcds * kXcds);
-}
 
 static int64_t value_capacity(sp_graph g, int32_t width) {
     return (int64_t)std::max(g->n, 1) * width + kSlots;

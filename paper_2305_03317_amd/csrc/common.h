@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <cstring>
@@ -75,7 +76,8 @@ struct sp_graph_s {
     int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
     int32_t n_hubs_in = 0;       // the same for incoming rows (= n_hubs when undirected)
     int64_t hub_chunks_in = 0;
-    int64_t ms_hub_chunks = 0;   // sum over hubs of ms_hub_span(degree): batched path
+    int64_t ms_hub_chunks = 0;   // sum over hubs of ms_hub_span(degree): split chunking
+    int64_t ms_hub_chunks_in = 0;  // the same for incoming rows (= ms_hub_chunks when undirected)
     size_t bytes = 0;
     std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
     std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
@@ -237,6 +239,13 @@ class ProfScope {
 // Launch shape helpers.
 int device_cu_count();
 int grid_for(int64_t items, int block, int max_blocks);
+
+// Grids of the hub chunk kernels: a multiple of kXcds blocks (at least kXcds,
+// at most max_blocks when that is a multiple), so that every XCD holds blocks.
+inline int xcd_grid(int grid, int max_blocks) {
+    const int g = (std::max(grid, kXcds) + kXcds - 1) / kXcds * kXcds;
+    return g <= max_blocks ? g : std::max(kXcds, max_blocks / kXcds * kXcds);
+}
 
 // ---------------------------------------------------------------------------
 // Per-source path (source_path.hip)

@@ -370,4 +370,10 @@ __device__ __forceinline__ double sum_chunks(const double *__restrict__ partial,
     return s;
 }
 
+// A hub's chunk sums in row order under the split chunking (hub_chunk_range).
+__device__ __forceinline__ double sum_hub_chunks(const double *__restrict__ partial, int32_t base,
+                                                 int32_t n) {
+    return n < kXcds ? sum_chunks(partial, base, n) : sum_split_chunks(partial, base, n);
+}
+
 }  // namespace sp

@@ -29,6 +29,39 @@ __device__ __forceinline__ void hub_register(LevelCtl *c, HubEntry *list, long l
         }
 }
 
+// Registration with the split chunking of ms_hub_nchunks (rows over
+// kHubSplitDeg cut by row eighths, first id aligned to kXcds): reserves
+// ms_hub_span(deg) ids through the packed counter `pack`, list index `at`.
+__device__ __forceinline__ void hub_register_split(unsigned long long *pack, HubEntry *list,
+                                                   long long cap, int32_t at, int32_t v,
+                                                   int32_t entry, int32_t deg) {
+    const int32_t nch = ms_hub_nchunks(deg);
+    const unsigned long long old =
+        atomicAdd(pack, (1ull << 40) | (unsigned long long)ms_hub_span(deg));
+    const int32_t idx = (int32_t)(old >> 40);
+    const int32_t base0 = (int32_t)(old & ((1ull << 40) - 1));
+    const int32_t base = nch >= kXcds ? (base0 + kXcds - 1) & ~(kXcds - 1) : base0;
+    if ((long long)at + idx < cap) list[at + idx] = HubEntry{v, entry, base, nch};
+}
+
+// Adjacency range [beg, end) of chunk id k of hub h under the split chunking;
+// false for an alignment slack id.  Hubs of fewer than kXcds chunks:
+// consecutive kHubChunk pieces; split hubs: split_piece.
+__device__ __forceinline__ bool hub_chunk_range(const HubEntry &h, int64_t k,
+                                                const int32_t *__restrict__ rp, int32_t &beg,
+                                                int32_t &end) {
+    const int32_t t = (int32_t)k - h.chunk_base;
+    if (t < 0 || t >= h.nchunks) return false;
+    const int32_t rb = rp[h.v];
+    if (h.nchunks < kXcds) {
+        beg = rb + t * kHubChunk;
+        end = min(rp[h.v + 1], beg + kHubChunk);
+    } else {
+        split_piece(rb, rp[h.v + 1] - rb, h.nchunks, t, beg, end);
+    }
+    return true;
+}
+
 // The hub whose chunk range holds chunk id k, in segment [lo, hi) sorted by
 // chunk_base (the packed atomic hands out indices and bases in one order).
 __device__ __forceinline__ int32_t hub_find(const HubEntry *list, int32_t lo, int32_t hi, int32_t k) {

@@ -67,10 +67,13 @@ sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
 // row is longer than the hub threshold (list rebuilt every level).
 __device__ __forceinline__ void in_hub_register(LevelCtl *c, HubEntry *list, long long cap, int32_t v,
                                                 int32_t entry, int32_t deg) {
-    const int32_t nch = (deg + kHubChunk - 1) / kHubChunk;
-    const unsigned long long old = atomicAdd(&c->in_hub_pack_.v, (1ull << 40) | (unsigned long long)nch);
-    const int32_t idx = (int32_t)(old >> 40);
-    if (idx < cap) list[idx] = HubEntry{v, entry, (int32_t)(old & ((1ull << 40) - 1)), nch};
+    hub_register_split(&c->in_hub_pack_.v, list, cap, 0, v, entry, deg);
+}
+
+// A hub of the level being built (split chunking, see ms_hub_nchunks).
+__device__ __forceinline__ void out_hub_register(LevelCtl *c, HubEntry *list, long long cap,
+                                                 int32_t v, int32_t entry, int32_t deg) {
+    hub_register_split(&c->hub_pack_.v, list, cap, c->hub_next, v, entry, deg);
 }
 
 __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *queue,
@@ -98,7 +101,7 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     c->topdown_levels = 0;
     c->bottomup_levels = 0;
     const bool hub = deg > hub_deg;
-    const int32_t nch = hub ? (deg + kHubChunk - 1) / kHubChunk : 0;
+    const int32_t nch = hub ? ms_hub_nchunks(deg) : 0;
     if (hub) hub_list[0] = HubEntry{src, 0, 0, nch};
     c->hub_pack_.v = 0;
     c->in_hub_n = 0;
@@ -174,8 +177,8 @@ __global__ __launch_bounds__(BS) void k_src_topdown(LevelCtl *c, const int32_t *
         const int32_t hlo = c->hub_lo, hhi = c->hub_hi, nch = c->hub_nchunks;
         for (int32_t k = blockIdx.x; k < nch; k += gridDim.x) {
             const HubEntry h = hub_list[hub_find(hub_list, hlo, hhi, k)];
-            const int32_t beg = rp[h.v] + (k - h.chunk_base) * kHubChunk;
-            const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+            int32_t beg, end;
+            if (!hub_chunk_range(h, k, rp, beg, end)) continue;
             my_edges += (threadIdx.x == 0) ? (unsigned long long)(end - beg) : 0ull;
             for (int32_t e0 = beg; e0 < end; e0 += BS) {
                 const int32_t e = e0 + threadIdx.x;
@@ -274,10 +277,10 @@ __global__ __launch_bounds__(BS) void k_src_sigma(LevelCtl *c, const int32_t *__
                 // directed: rows walked by discovery and delta are the
                 // outgoing ones; the chunked path counts use in_list
                 const int32_t dout = rp_out[w + 1] - rp_out[w];
-                if (dout > hub_deg) hub_register(c, hub_list, hub_cap, w, i, dout);
+                if (dout > hub_deg) out_hub_register(c, hub_list, hub_cap, w, i, dout);
                 if (hub) in_hub_register(c, in_list, in_cap, w, i, deg);
             } else if (hub) {
-                hub_register(c, hub_list, hub_cap, w, i, deg);
+                out_hub_register(c, hub_list, hub_cap, w, i, deg);
             }
             if (!hub) {
                 my_scan += (unsigned long long)deg;
@@ -343,18 +346,15 @@ __global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t
     // undirected: the level's hub segment; directed: the incoming-row list
     const int32_t hlo = use_in ? 0 : c->hub_lo, hhi = use_in ? c->in_hub_n : c->hub_hi;
     const int32_t nch = use_in ? c->in_hub_nchunks : c->hub_nchunks, pl = c->level - 1;
-    const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
-    for (int64_t k = wave0; k < nch; k += nwaves) {
-        const int32_t j = hub_find(hub_list, hlo, hhi, (int32_t)k);
-        const HubEntry h = hub_list[j];
-        const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
-        const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+    for_xcd_chunks<BS>(nch, [&](int64_t k) {
+        const HubEntry h = hub_list[hub_find(hub_list, hlo, hhi, (int32_t)k)];
+        int32_t beg, end;
+        if (!hub_chunk_range(h, k, rp, beg, end)) return;
         hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) {
             const int32_t u = ci[e];
             return dist[u] == pl ? sigma[u] : 0.0;
         });
-    }
+    });
     (void)hub_cnt;
     (void)prof;
 }
@@ -367,7 +367,7 @@ __global__ void k_src_sigma_hub_fin(LevelCtl *c, double *sigma, const HubEntry *
     for (int64_t j = hlo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hhi;
          j += (int64_t)gridDim.x * blockDim.x) {
         const HubEntry h = hub_list[j];
-        const double s = sum_chunks(partial, h.chunk_base, h.nchunks);
+        const double s = sum_hub_chunks(partial, h.chunk_base, h.nchunks);
         sigma[h.v] = s;
         atomic_max_nonneg_f64(&c->sigma_max_bits_.v, s);
         if (sigma_is_large(s)) atomicOr(&c->flagged_slots_.v, 1ull);
@@ -428,19 +428,16 @@ __global__ __launch_bounds__(BS) void k_src_delta_hub(
     unsigned int *hub_cnt, double *partial) {
     const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1], nch = hub_lvl_chunks[lvl];
     const int32_t nl = lvl + 1;
-    const int64_t wave0 = ((int64_t)blockIdx.x * BS + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * BS / kWave;
-    for (int64_t k = wave0; k < nch; k += nwaves) {
-        const int32_t j = hub_find(hub_list, hlo, hhi, (int32_t)k);
-        const HubEntry h = hub_list[j];
-        const int32_t beg = rp[h.v] + ((int32_t)k - h.chunk_base) * kHubChunk;
-        const int32_t end = min(rp[h.v + 1], beg + kHubChunk);
+    for_xcd_chunks<BS>(nch, [&](int64_t k) {
+        const HubEntry h = hub_list[hub_find(hub_list, hlo, hhi, (int32_t)k)];
+        int32_t beg, end;
+        if (!hub_chunk_range(h, k, rp, beg, end)) return;
         const double sv = sigma[h.v];
         hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) {
             const int32_t w = ci[e];
             return dist[w] == nl ? (sv / sigma[w]) * (1.0 + delta[w]) : 0.0;
         });
-    }
+    });
     (void)hub_cnt;
     (void)bc;
 }
@@ -453,7 +450,7 @@ __global__ void k_src_delta_hub_fin(const int32_t *__restrict__ hub_off, int32_t
     for (int64_t j = hlo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < hhi;
          j += (int64_t)gridDim.x * blockDim.x) {
         const HubEntry h = hub_list[j];
-        const double s = sum_chunks(partial, h.chunk_base, h.nchunks);
+        const double s = sum_hub_chunks(partial, h.chunk_base, h.nchunks);
         delta[h.v] = s;
         if (bc) bc[h.v] += s;
     }
@@ -478,7 +475,7 @@ sp_status source_ws_create(sp_graph g, SourceWorkspace &ws) {
     SP_TRY(dev_alloc((void **)&ws.in_hub_list, ((size_t)g->n_hubs_in + 1) * sizeof(HubEntry)));
     SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
     SP_TRY(dev_alloc((void **)&ws.partial,
-                     ((size_t)std::max(g->hub_chunks, g->hub_chunks_in) + 1) * sizeof(double)));
+                     ((size_t)std::max(g->ms_hub_chunks, g->ms_hub_chunks_in) + 1) * sizeof(double)));
     SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
     SP_HIP(hipHostMalloc((void **)&ws.ctl_host, sizeof(LevelCtl), hipHostMallocDefault));
@@ -557,7 +554,8 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                 ProfScope ps(P_SRC_SIGMA_HUB, s);
                 const HubEntry *plist = directed ? ws.in_hub_list : ws.hub_list;
                 hipLaunchKernelGGL(k_src_sigma_hub<BS>,
-                                   dim3(grid_for((int64_t)g->hub_chunks_in * kWave, BS, maxb)), dim3(BS), 0, s,
+                                   dim3(xcd_grid(grid_for((int64_t)g->ms_hub_chunks_in * kWave, BS, maxb), maxb)),
+                                   dim3(BS), 0, s,
                                    ws.ctl, g->rp_in, g->ci_in, ws.dist, ws.sigma, plist, ws.hub_cnt,
                                    ws.partial, prof_counters(P_SRC_SIGMA_HUB), (int32_t)directed);
                 hipLaunchKernelGGL(k_src_sigma_hub_fin, dim3(grid_for(g->n_hubs_in, 256, maxb)), dim3(256), 0,
@@ -593,7 +591,8 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
             }
             if (hubs && hchunks[l] > 0) {
                 ProfScope ps(P_SRC_DELTA_HUB, s);
-                hipLaunchKernelGGL(k_src_delta_hub<BS>, dim3(grid_for((int64_t)hchunks[l] * kWave, BS, maxb)),
+                hipLaunchKernelGGL(k_src_delta_hub<BS>,
+                                   dim3(xcd_grid(grid_for((int64_t)hchunks[l] * kWave, BS, maxb), maxb)),
                                    dim3(BS), 0, s, (const int32_t *)ws.hub_off,
                                    (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
                                    ws.dist, ws.sigma, ws.delta, bc, (const HubEntry *)ws.hub_list,

@@ -65,6 +65,37 @@ def test_bc_and_levels(sp, name):
         assert_bc(dl.cpu().numpy(), dl_ref, name + " delta")
 
 
+def test_split_hubs_directed(sp):
+    # the split-hub graph with every edge given a seeded direction: hubs keep
+    # about half their neighbours as out-arcs and half as in-arcs, so both
+    # hub lists of the per-source path meet rows either side of 2048
+    from tests.test_gpu_parity import HUB_DEGREES, split_hub_graph
+    rp, ci = split_hub_graph()
+    n = len(rp) - 1
+    u = np.repeat(np.arange(n), np.diff(rp))
+    keep = u < ci
+    a, b = u[keep], ci[keep]
+    flip = np.random.default_rng(41).random(len(a)) < 0.5
+    drp, dci = brute.directed_csr(n, np.where(flip, b, a), np.where(flip, a, b))
+    dout = np.diff(drp)
+    print("hub out-degrees", dout[60000:], flush=True)
+    g = sp.sp_graph_upload(drp, dci, validate=True, directed=True)
+    hubs = np.arange(60000, 60000 + len(HUB_DEGREES), dtype=np.int32)
+    srcs = np.concatenate([hubs, graphs.sources(drp, 17, 42, min_degree=1)]).astype(np.int32)
+    srcs = np.unique(srcs)
+    ref = oracle.bc(drp, dci, srcs)
+    got, st = sp.sp_bc(g, srcs)
+    assert st == sp.SP_OK
+    assert_bc(got.cpu().numpy(), ref, "directed split hubs")
+    for s in list(hubs[-2:]) + list(srcs[:2]):
+        d_ref, sig_ref, del_ref = oracle.source_detail(drp, dci, int(s))
+        d, sig, dl, _ = sp.sp_bfs_levels(g, int(s), with_sigma=True, with_delta=True)
+        assert np.array_equal(d.cpu().numpy(), d_ref)
+        assert_sigma(sig.cpu().numpy(), sig_ref, "sigma, source %d" % s)
+        assert_bc(dl.cpu().numpy(), np.where(d_ref > 0, del_ref, 0.0), "delta, source %d" % s)
+    g.release()
+
+
 def test_directed_differs_from_symmetrised(sp):
     # the same arcs read as undirected edges give another BC: direction is used
     rp, ci = brute.directed_csr(6, [0, 1, 2, 3, 4], [1, 2, 3, 4, 5])

@@ -188,7 +188,7 @@ def split_hub_graph(seed=31):
 @pytest.mark.parametrize("case", ["rmat-16", "synthetic"])
 def test_split_hubs(sp, case):
     # hubs above 2048 neighbours are cut into 8m pieces numbered by row eighth
-    # in the batched path; sources include the hubs themselves (level-0 hubs)
+    # (both paths); sources include the hubs themselves (level-0 hubs)
     if case == "rmat-16":
         rp, ci = graphs.rmat(16, 16, graphs.RMAT_ABC, 8)
         deg = np.diff(rp)
@@ -202,9 +202,10 @@ def test_split_hubs(sp, case):
     print(case, "vertices", len(rp) - 1, "max degree", int(np.diff(rp).max()), flush=True)
     g = sp.sp_graph_upload(rp, ci)
     ref = oracle.bc(rp, ci, srcs)
-    b, sb = sp.sp_bc_batch(g, srcs)
-    assert sb == sp.SP_OK
-    assert_bc(b.cpu().numpy(), ref, "sp_bc_batch " + case)
+    a, b, sa, sb = both_paths(sp, g, srcs)
+    assert sa == sp.SP_OK and sb == sp.SP_OK
+    assert_bc(a, ref, "sp_bc " + case)
+    assert_bc(b, ref, "sp_bc_batch " + case)
     b2, _ = sp.sp_bc_batch(g, srcs[::-1].copy())
     assert_bc(b2.cpu().numpy(), ref, "sp_bc_batch reversed " + case)
     check_sources_detail(sp, g, rp, ci, srcs[:12])
