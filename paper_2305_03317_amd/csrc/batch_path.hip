@@ -130,26 +130,6 @@ __device__ __forceinline__ void window_acc(uint4 fu, unsigned long long m, uint3
 
 __device__ __forceinline__ uint4 no_front() { return make_uint4(0u, 0u, kNoTag, 0u); }
 
-// Hub registration for the batched path's chunking (ms_hub_nchunks): reserves
-// ms_hub_span(deg) chunk ids and aligns a split hub's first id to a multiple
-// of kXcds; every reserved id, the alignment slack included, records the hub
-// in `owner`, and hub_chunk_range turns the slack ids away.  Overflows of the
-// list or the owner map are reported by `advance`, as for the other paths.
-__device__ __forceinline__ void ms_hub_register(LevelCtl *c, HubEntry *list, long long cap,
-                                                int32_t v, int32_t entry, int32_t deg,
-                                                int32_t *owner, long long owner_cap) {
-    const int32_t nch = ms_hub_nchunks(deg), span = ms_hub_span(deg);
-    const unsigned long long old = atomicAdd(&c->hub_pack_.v, (1ull << 40) | (unsigned long long)span);
-    const int32_t idx = (int32_t)(old >> 40);
-    const int32_t at = (int32_t)(old & ((1ull << 40) - 1));
-    const int32_t base = nch >= kXcds ? (at + kXcds - 1) & ~(kXcds - 1) : at;
-    if ((long long)c->hub_next + idx < cap) list[c->hub_next + idx] = HubEntry{v, entry, base, nch};
-    for (int32_t q = 0; q < span; ++q) {
-        const long long p = (long long)c->chunk_next + at + q;
-        if (p < owner_cap) owner[p] = c->hub_next + idx;
-    }
-}
-
 // dense_sum given the records `f` of the first window (entries [beg, beg+kWave)).
 __device__ __forceinline__ double dense_sum_from(uint4 f, int32_t beg, int32_t end,
                                                  unsigned long long m, uint32_t tag,
@@ -663,7 +643,9 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                        }
                        my_flag |= __ballot(mine && sigma_is_large(acc));
                    });
-        if (hub) ms_hub_register(c, hub_list, hub_cap, w, i, deg, owner, owner_cap);
+        if (hub)
+            hub_register(&c->hub_pack_.v, hub_list, hub_cap, c->hub_next, w, i, deg, owner,
+                         c->chunk_next, owner_cap);
         if (sparse || dense) my_scan += (unsigned long long)deg;  // hubs: k_ms_sigma_hub
         if (valid) {
             qmask[i] = m;

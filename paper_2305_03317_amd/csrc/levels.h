@@ -9,39 +9,31 @@
 
 namespace sp {
 
-// Register a hub of the level being built: reserve its chunk ids.
-// `cap` is the list's capacity; an index past it is dropped and reported by
-// `advance` as an overflow.  With an owner map (batched path), each of the
-// hub's chunks also records the hub's list index at owner[chunk_next + id],
-// so chunk kernels find their hub with one load; `advance` checks owner_cap.
-__device__ __forceinline__ void hub_register(LevelCtl *c, HubEntry *list, long long cap, int32_t v,
-                                             int32_t entry, int32_t deg, int32_t *owner = nullptr,
-                                             long long owner_cap = 0) {
-    const int32_t nch = (deg + kHubChunk - 1) / kHubChunk;
-    const unsigned long long old = atomicAdd(&c->hub_pack_.v, (1ull << 40) | (unsigned long long)nch);
-    const int32_t idx = (int32_t)(old >> 40);
-    const int32_t base = (int32_t)(old & ((1ull << 40) - 1));
-    if ((long long)c->hub_next + idx < cap) list[c->hub_next + idx] = HubEntry{v, entry, base, nch};
-    if (owner)
-        for (int32_t q = 0; q < nch; ++q) {
-            const long long p = (long long)c->chunk_next + base + q;
-            if (p < owner_cap) owner[p] = c->hub_next + idx;
-        }
-}
-
-// Registration with the split chunking of ms_hub_nchunks (rows over
-// kHubSplitDeg cut by row eighths, first id aligned to kXcds): reserves
-// ms_hub_span(deg) ids through the packed counter `pack`, list index `at`.
-__device__ __forceinline__ void hub_register_split(unsigned long long *pack, HubEntry *list,
-                                                   long long cap, int32_t at, int32_t v,
-                                                   int32_t entry, int32_t deg) {
-    const int32_t nch = ms_hub_nchunks(deg);
-    const unsigned long long old =
-        atomicAdd(pack, (1ull << 40) | (unsigned long long)ms_hub_span(deg));
+// Register a hub of the level being built under the split chunking of
+// ms_hub_nchunks (rows over kHubSplitDeg cut by row eighths, first id aligned
+// to kXcds): reserve ms_hub_span(deg) chunk ids through the packed counter
+// `pack` (list index in the high bits, chunk ids in the low 40) and store the
+// entry at list[at + index].  `cap` is the list's capacity; an index past it
+// is dropped and reported by `advance` as an overflow.  With an owner map
+// (batched path), every reserved id, the alignment slack included, records
+// the hub's list index at owner[owner_at + id], so chunk kernels find their
+// hub with one load (hub_chunk_range turns the slack ids away); `advance`
+// checks owner_cap.
+__device__ __forceinline__ void hub_register(unsigned long long *pack, HubEntry *list,
+                                             long long cap, int32_t at, int32_t v, int32_t entry,
+                                             int32_t deg, int32_t *owner = nullptr,
+                                             long long owner_at = 0, long long owner_cap = 0) {
+    const int32_t nch = ms_hub_nchunks(deg), span = ms_hub_span(deg);
+    const unsigned long long old = atomicAdd(pack, (1ull << 40) | (unsigned long long)span);
     const int32_t idx = (int32_t)(old >> 40);
     const int32_t base0 = (int32_t)(old & ((1ull << 40) - 1));
     const int32_t base = nch >= kXcds ? (base0 + kXcds - 1) & ~(kXcds - 1) : base0;
     if ((long long)at + idx < cap) list[at + idx] = HubEntry{v, entry, base, nch};
+    if (owner)
+        for (int32_t q = 0; q < span; ++q) {
+            const long long p = owner_at + base0 + q;
+            if (p < owner_cap) owner[p] = at + idx;
+        }
 }
 
 // Adjacency range [beg, end) of chunk id k of hub h under the split chunking;

@@ -67,13 +67,13 @@ sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
 // row is longer than the hub threshold (list rebuilt every level).
 __device__ __forceinline__ void in_hub_register(LevelCtl *c, HubEntry *list, long long cap, int32_t v,
                                                 int32_t entry, int32_t deg) {
-    hub_register_split(&c->in_hub_pack_.v, list, cap, 0, v, entry, deg);
+    hub_register(&c->in_hub_pack_.v, list, cap, 0, v, entry, deg);
 }
 
 // A hub of the level being built (split chunking, see ms_hub_nchunks).
 __device__ __forceinline__ void out_hub_register(LevelCtl *c, HubEntry *list, long long cap,
                                                  int32_t v, int32_t entry, int32_t deg) {
-    hub_register_split(&c->hub_pack_.v, list, cap, c->hub_next, v, entry, deg);
+    hub_register(&c->hub_pack_.v, list, cap, c->hub_next, v, entry, deg);
 }
 
 __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *queue,
