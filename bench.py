@@ -68,6 +68,7 @@ BYTE_MODEL = {
     "src_bottomup": dict(items=12, edges=8),
     "src_sigma": dict(items=20, edges=8, pairs=8),
     "src_sigma_hub": dict(edges=8, pairs=8),
+    "src_delta_hub": dict(edges=8, pairs=16),
     "src_delta": dict(items=44, edges=8, pairs=16),
     # SSSP rounds: items = frontier vertices (push: queue entry, row offsets,
     # own distance) or all vertices (pull: row offsets), edges = adjacency

@@ -346,17 +346,22 @@ __global__ __launch_bounds__(BS) void k_src_sigma_hub(LevelCtl *c, const int32_t
     // undirected: the level's hub segment; directed: the incoming-row list
     const int32_t hlo = use_in ? 0 : c->hub_lo, hhi = use_in ? c->in_hub_n : c->hub_hi;
     const int32_t nch = use_in ? c->in_hub_nchunks : c->hub_nchunks, pl = c->level - 1;
+    __shared__ unsigned long long s_red[1];
+    unsigned long long my_edges = 0, my_pairs = 0;
     for_xcd_chunks<BS>(nch, [&](int64_t k) {
         const HubEntry h = hub_list[hub_find(hub_list, hlo, hhi, (int32_t)k)];
         int32_t beg, end;
         if (!hub_chunk_range(h, k, rp, beg, end)) return;
+        if (lane_id() == 0) my_edges += (unsigned long long)(end - beg);
         hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) {
             const int32_t u = ci[e];
-            return dist[u] == pl ? sigma[u] : 0.0;
+            if (dist[u] != pl) return 0.0;
+            ++my_pairs;
+            return sigma[u];
         });
     });
+    flush_counters<BS>(prof, 0, my_edges, my_pairs, s_red);
     (void)hub_cnt;
-    (void)prof;
 }
 
 // Path counts of the current level's hubs from their chunk sums (a thread per hub).
@@ -425,7 +430,9 @@ __global__ __launch_bounds__(BS) void k_src_delta_hub(
     const int32_t *__restrict__ hub_off, const int32_t *__restrict__ hub_lvl_chunks, int32_t lvl,
     const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const int32_t *__restrict__ dist,
     const double *__restrict__ sigma, double *delta, double *bc, const HubEntry *hub_list,
-    unsigned int *hub_cnt, double *partial) {
+    unsigned int *hub_cnt, double *partial, unsigned long long *prof) {
+    __shared__ unsigned long long s_red[1];
+    unsigned long long my_edges = 0, my_pairs = 0;
     const int32_t hlo = hub_off[lvl], hhi = hub_off[lvl + 1], nch = hub_lvl_chunks[lvl];
     const int32_t nl = lvl + 1;
     for_xcd_chunks<BS>(nch, [&](int64_t k) {
@@ -433,11 +440,15 @@ __global__ __launch_bounds__(BS) void k_src_delta_hub(
         int32_t beg, end;
         if (!hub_chunk_range(h, k, rp, beg, end)) return;
         const double sv = sigma[h.v];
+        if (lane_id() == 0) my_edges += (unsigned long long)(end - beg);
         hub_chunk((int32_t)k, beg, end, partial, [&](int32_t e) {
             const int32_t w = ci[e];
-            return dist[w] == nl ? (sv / sigma[w]) * (1.0 + delta[w]) : 0.0;
+            if (dist[w] != nl) return 0.0;
+            ++my_pairs;
+            return (sv / sigma[w]) * (1.0 + delta[w]);
         });
     });
+    flush_counters<BS>(prof, 0, my_edges, my_pairs, s_red);
     (void)hub_cnt;
     (void)bc;
 }
@@ -596,7 +607,7 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
                                    dim3(BS), 0, s, (const int32_t *)ws.hub_off,
                                    (const int32_t *)ws.hub_lvl_chunks, l, g->row_ptr, g->col_idx,
                                    ws.dist, ws.sigma, ws.delta, bc, (const HubEntry *)ws.hub_list,
-                                   ws.hub_cnt, ws.partial);
+                                   ws.hub_cnt, ws.partial, prof_counters(P_SRC_DELTA_HUB));
                 hipLaunchKernelGGL(k_src_delta_hub_fin, dim3(grid_for(g->n_hubs, 256, maxb)), dim3(256), 0, s,
                                    (const int32_t *)ws.hub_off, l, ws.delta, bc,
                                    (const HubEntry *)ws.hub_list, (const double *)ws.partial);
