@@ -610,7 +610,7 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
         if (d > kHubDeg) {
             g->n_hubs++;
             g->hub_chunks += (d + kHubChunk - 1) / kHubChunk;
-            g->ms_hub_chunks += ms_hub_span(d);
+            g->split_hub_chunks += split_hub_span(d);
         }
     }
     g->max_degree = md;
@@ -618,7 +618,7 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     g->ci_in = g->col_idx;
     g->n_hubs_in = g->n_hubs;
     g->hub_chunks_in = g->hub_chunks;
-    g->ms_hub_chunks_in = g->ms_hub_chunks;
+    g->split_hub_chunks_in = g->split_hub_chunks;
     g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
     *out = g;
     return SP_OK;
@@ -686,14 +686,14 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
     }
     int32_t md = g->max_degree;
     int32_t nh_in = 0;
-    int64_t nch_in = 0, ms_in = 0;
+    int64_t nch_in = 0, split_in = 0;
     for (int32_t v = 0; v < n_vertices; ++v) {
         const int32_t d = ir[v + 1] - ir[v];
         md = std::max(md, d);
         if (d > kHubDeg) {
             ++nh_in;
             nch_in += (d + kHubChunk - 1) / kHubChunk;
-            ms_in += ms_hub_span(d);
+            split_in += split_hub_span(d);
         }
     }
     g->rp_in = rp_in;
@@ -702,7 +702,7 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
     g->max_degree = md;
     g->n_hubs_in = nh_in;  // n_hubs / hub_chunks count the outgoing rows
     g->hub_chunks_in = nch_in;
-    g->ms_hub_chunks_in = ms_in;
+    g->split_hub_chunks_in = split_in;
     g->bytes += ir.size() * 4 + ic.size() * 4;
     *out = g;
     return SP_OK;

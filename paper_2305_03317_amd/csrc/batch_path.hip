@@ -293,7 +293,7 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
             pairs += (unsigned long long)__popcll(qmask[i]);
             if (qmask[i] == active) settled += (unsigned long long)d;
             if (d > kHubDeg) {  // at most kSlots hubs; split hubs start at a multiple of kXcds
-                const int32_t k = ms_hub_nchunks(d);
+                const int32_t k = split_hub_nchunks(d);
                 const int32_t base = k >= kXcds ? (nch + kXcds - 1) & ~(kXcds - 1) : nch;
                 for (int32_t q = nch; q < base + k; ++q) owner[q] = nh;
                 hub_list[nh++] = HubEntry{v, i, base, k};
@@ -1242,7 +1242,7 @@ __global__ void k_ms_extract(const int32_t *__restrict__ queue,
 // ---------------------------------------------------------------------------
 static int64_t hub_capacity(sp_graph g) { return (int64_t)g->n_hubs * kSlots + kSlots; }
 // A hub has at most one entry per slot, so at most kSlots entries per pass.
-static int64_t owner_capacity(sp_graph g) { return g->ms_hub_chunks * kSlots + kSlots; }
+static int64_t owner_capacity(sp_graph g) { return g->split_hub_chunks * kSlots + kSlots; }
 
 static int64_t value_capacity(sp_graph g, int32_t width) {
     return (int64_t)std::max(g->n, 1) * width + kSlots;
@@ -1254,7 +1254,7 @@ size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
            (size_t)qcap * 16 + (V + 2) * 12 + kSlots * 4 +
            (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
            (size_t)owner_capacity(g) * 4 + (V + 2) * 4 +
-           ((size_t)g->ms_hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
+           ((size_t)g->split_hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
 }
 
 sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws) {
@@ -1287,7 +1287,7 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
     SP_TRY(dev_alloc((void **)&ws.hub_lvl_chunks, (size_t)ws.level_cap * 4));
     SP_TRY(dev_alloc((void **)&ws.hub_list, (size_t)ws.hub_cap * sizeof(HubEntry)));
     SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * 4));
-    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->ms_hub_chunks + 1) * kSlots * 8));
+    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->split_hub_chunks + 1) * kSlots * 8));
     SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * 4));
     SP_TRY(dev_alloc((void **)&ws.slot_src, kSlots * 4));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
@@ -1430,7 +1430,7 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
     const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
-    const int hub_grid = xcd_grid(grid_for((int64_t)g->ms_hub_chunks * kWave, BS, maxb), maxb);
+    const int hub_grid = xcd_grid(grid_for((int64_t)g->split_hub_chunks * kWave, BS, maxb), maxb);
     hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.seen, ws.nxt,
                        ws.front[0], ws.front[1], n);
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, s, ws.ctl, (const int32_t *)g->row_ptr,

@@ -76,8 +76,8 @@ struct sp_graph_s {
     int64_t hub_chunks = 0;      // sum over hubs of ceil(degree / kHubChunk)
     int32_t n_hubs_in = 0;       // the same for incoming rows (= n_hubs when undirected)
     int64_t hub_chunks_in = 0;
-    int64_t ms_hub_chunks = 0;   // sum over hubs of ms_hub_span(degree): split chunking
-    int64_t ms_hub_chunks_in = 0;  // the same for incoming rows (= ms_hub_chunks when undirected)
+    int64_t split_hub_chunks = 0;     // sum over hubs of split_hub_span(degree) (BC paths)
+    int64_t split_hub_chunks_in = 0;  // the same for incoming rows (= split_hub_chunks when undirected)
     size_t bytes = 0;
     std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
     std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
@@ -132,7 +132,7 @@ enum : int32_t { MODE_TOPDOWN = 0, MODE_BOTTOMUP = 1 };
 constexpr int32_t kHubDeg = 256;
 constexpr int32_t kHubChunk = 512;
 
-// Batched path: a hub of more than kHubSplitDeg neighbours is cut into 8*m
+// Both BC paths: a hub of more than kHubSplitDeg neighbours is cut into 8*m
 // chunks of near-equal length (at most kHubChunk), m = ceil(deg/(8*kHubChunk)),
 // numbered so that chunk id mod 8 names the eighth of the row the chunk lies
 // in, with the hub's first id a multiple of 8.  Workgroups are dispatched to
@@ -144,12 +144,12 @@ constexpr int32_t kHubChunk = 512;
 // most 4), so a hub is split exactly when it has 8 or more chunks.
 constexpr int32_t kXcds = 8;
 constexpr int32_t kHubSplitDeg = 4 * kHubChunk;
-__host__ __device__ constexpr int32_t ms_hub_nchunks(int32_t deg) {
+__host__ __device__ constexpr int32_t split_hub_nchunks(int32_t deg) {
     return deg > kHubSplitDeg ? kXcds * ((deg + kXcds * kHubChunk - 1) / (kXcds * kHubChunk))
                               : (deg + kHubChunk - 1) / kHubChunk;
 }
-__host__ __device__ constexpr int32_t ms_hub_span(int32_t deg) {
-    return deg > kHubSplitDeg ? ms_hub_nchunks(deg) + kXcds - 1 : ms_hub_nchunks(deg);
+__host__ __device__ constexpr int32_t split_hub_span(int32_t deg) {
+    return deg > kHubSplitDeg ? split_hub_nchunks(deg) + kXcds - 1 : split_hub_nchunks(deg);
 }
 
 // One hub occurrence on a level: vertex, its queue entry, and the range of

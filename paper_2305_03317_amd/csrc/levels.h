@@ -10,8 +10,8 @@
 namespace sp {
 
 // Register a hub of the level being built under the split chunking of
-// ms_hub_nchunks (rows over kHubSplitDeg cut by row eighths, first id aligned
-// to kXcds): reserve ms_hub_span(deg) chunk ids through the packed counter
+// split_hub_nchunks (rows over kHubSplitDeg cut by row eighths, first id aligned
+// to kXcds): reserve split_hub_span(deg) chunk ids through the packed counter
 // `pack` (list index in the high bits, chunk ids in the low 40) and store the
 // entry at list[at + index].  `cap` is the list's capacity; an index past it
 // is dropped and reported by `advance` as an overflow.  With an owner map
@@ -23,7 +23,7 @@ __device__ __forceinline__ void hub_register(unsigned long long *pack, HubEntry 
                                              long long cap, int32_t at, int32_t v, int32_t entry,
                                              int32_t deg, int32_t *owner = nullptr,
                                              long long owner_at = 0, long long owner_cap = 0) {
-    const int32_t nch = ms_hub_nchunks(deg), span = ms_hub_span(deg);
+    const int32_t nch = split_hub_nchunks(deg), span = split_hub_span(deg);
     const unsigned long long old = atomicAdd(pack, (1ull << 40) | (unsigned long long)span);
     const int32_t idx = (int32_t)(old >> 40);
     const int32_t base0 = (int32_t)(old & ((1ull << 40) - 1));

@@ -14,11 +14,12 @@
 // vertex's sum depends only on its row, so results are reproducible.  Rows
 // longer than kHubDeg are cut by row eighths into 8m pieces of at most
 // kHubChunk entries (split_piece), which waves reduce into partials, one XCD
-// per eighth; a finishing kernel adds a row's partials in row order.  The stopping test sums |val - pr| per block in
-// a fixed order and adds the block sums as fixed-point integers, so the total
-// and the decision do not depend on scheduling.  The last working block of an
-// iteration's last kernel closes it; chunks of iterations are captured as HIP
-// graphs and replayed until the device reports done.
+// per eighth; a finishing kernel adds a row's partials in row order.  The
+// stopping test sums |val - pr| per block in a fixed order and adds the block
+// sums as fixed-point integers, so the total and the decision do not depend on
+// scheduling.  The last working block of an iteration's last kernel closes it;
+// chunks of iterations are captured as HIP graphs and replayed until the
+// device reports done.
 #include "capture.h"
 #include "common.h"
 #include "devutil.h"

@@ -70,7 +70,7 @@ __device__ __forceinline__ void in_hub_register(LevelCtl *c, HubEntry *list, lon
     hub_register(&c->in_hub_pack_.v, list, cap, 0, v, entry, deg);
 }
 
-// A hub of the level being built (split chunking, see ms_hub_nchunks).
+// A hub of the level being built (split chunking, see split_hub_nchunks).
 __device__ __forceinline__ void out_hub_register(LevelCtl *c, HubEntry *list, long long cap,
                                                  int32_t v, int32_t entry, int32_t deg) {
     hub_register(&c->hub_pack_.v, list, cap, c->hub_next, v, entry, deg);
@@ -101,7 +101,7 @@ __global__ void k_src_init(LevelCtl *c, int32_t *dist, double *sigma, int32_t *q
     c->topdown_levels = 0;
     c->bottomup_levels = 0;
     const bool hub = deg > hub_deg;
-    const int32_t nch = hub ? ms_hub_nchunks(deg) : 0;
+    const int32_t nch = hub ? split_hub_nchunks(deg) : 0;
     if (hub) hub_list[0] = HubEntry{src, 0, 0, nch};
     c->hub_pack_.v = 0;
     c->in_hub_n = 0;
@@ -486,7 +486,7 @@ sp_status source_ws_create(sp_graph g, SourceWorkspace &ws) {
     SP_TRY(dev_alloc((void **)&ws.in_hub_list, ((size_t)g->n_hubs_in + 1) * sizeof(HubEntry)));
     SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
     SP_TRY(dev_alloc((void **)&ws.partial,
-                     ((size_t)std::max(g->ms_hub_chunks, g->ms_hub_chunks_in) + 1) * sizeof(double)));
+                     ((size_t)std::max(g->split_hub_chunks, g->split_hub_chunks_in) + 1) * sizeof(double)));
     SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * sizeof(unsigned int)));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
     SP_HIP(hipHostMalloc((void **)&ws.ctl_host, sizeof(LevelCtl), hipHostMallocDefault));
@@ -564,9 +564,8 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
             if (hubs_in) {
                 ProfScope ps(P_SRC_SIGMA_HUB, s);
                 const HubEntry *plist = directed ? ws.in_hub_list : ws.hub_list;
-                hipLaunchKernelGGL(k_src_sigma_hub<BS>,
-                                   dim3(xcd_grid(grid_for((int64_t)g->ms_hub_chunks_in * kWave, BS, maxb), maxb)),
-                                   dim3(BS), 0, s,
+                const int hub_grid = xcd_grid(grid_for(g->split_hub_chunks_in * kWave, BS, maxb), maxb);
+                hipLaunchKernelGGL(k_src_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s,
                                    ws.ctl, g->rp_in, g->ci_in, ws.dist, ws.sigma, plist, ws.hub_cnt,
                                    ws.partial, prof_counters(P_SRC_SIGMA_HUB), (int32_t)directed);
                 hipLaunchKernelGGL(k_src_sigma_hub_fin, dim3(grid_for(g->n_hubs_in, 256, maxb)), dim3(256), 0,
