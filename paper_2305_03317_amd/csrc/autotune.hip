@@ -86,24 +86,31 @@ extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_s
         };
         double best_ms = 0;
         SP_TRY(time_config(g, *ws, sources, n, best.batch_width, opts(best), st, &best_ms));
-        auto try_field = [&](auto setter, const std::vector<double> &values) -> sp_status {
+        // a candidate replaces the current best only when it is faster by the
+        // field's margin: block sizes 128-512 time within a few per cent of
+        // each other on the sample, so they need 5% to move off the default
+        // (a smaller margin let the choice flip from run to run)
+        auto try_field = [&](auto setter, const std::vector<double> &values,
+                             double margin) -> sp_status {
             for (double v : values) {
                 sp_batch_config c = best;
                 setter(c, v);
                 double ms = 0;
                 SP_TRY(time_config(g, *ws, sources, n, c.batch_width, opts(c), st, &ms));
-                if (ms < best_ms * 0.98) {
+                if (ms < best_ms * (1.0 - margin)) {
                     best_ms = ms;
                     best = c;
                 }
             }
             return SP_OK;
         };
-        SP_TRY(try_field([](sp_batch_config &c, double v) { c.block_size = (int32_t)v; }, {128, 512}));
-        SP_TRY(try_field([](sp_batch_config &c, double v) { c.batch_width = (int32_t)v; }, {32, 48}));
+        SP_TRY(try_field([](sp_batch_config &c, double v) { c.block_size = (int32_t)v; }, {128, 512},
+                         0.05));
+        SP_TRY(try_field([](sp_batch_config &c, double v) { c.batch_width = (int32_t)v; }, {32, 48},
+                         0.02));
         if (g->max_degree > 8) {
-            SP_TRY(try_field([](sp_batch_config &c, double v) { c.alpha = v; }, {4, 60}));
-            SP_TRY(try_field([](sp_batch_config &c, double v) { c.beta = v; }, {8, 96}));
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.alpha = v; }, {4, 60}, 0.02));
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.beta = v; }, {8, 96}, 0.02));
         }
         {
             std::lock_guard<std::mutex> lk(g->mu);
