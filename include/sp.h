@@ -173,6 +173,9 @@ typedef struct sp_stats {
     double alpha, beta;
     int32_t chunk_levels;
     int32_t graph_launches;  /* hipGraph launches used */
+    double group_ms;         /* sp_bc_batch: host time spent in this call computing the
+                                graph's source-grouping keys (0 once cached; not part
+                                of device_ms) */
 } sp_stats;
 
 /* Per-source path: one BFS pass per source, sources in list order.
@@ -219,12 +222,66 @@ sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources,
  * slots on this graph (bytes). */
 sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes);
 
-/* Autotuner: times candidate configurations of the batched path on a sample
- * of `sources` (at most n_sources) and writes the fastest to *out.  The
- * choice is cached on the graph and used whenever a later call passes a
- * zero field.  Output buffers are not touched.  Synchronises the stream. */
+/* Autotuner: times candidate configurations of the batched path and writes
+ * the fastest to *out.  The sample is up to 128 consecutive sources of
+ * `sources` in the order sp_bc_batch would batch them (grouped, see above),
+ * taken from the middle of that order, so candidates run the batches
+ * production runs.  Search: coordinate descent from the built-in defaults
+ * (width 64, block 512, alpha 15, beta 24, chunk_levels 8), one field at a
+ * time: block {256, 128}, width {32, 48}, alpha {4, 60} and beta {8, 96}
+ * (graphs with a vertex of degree > 8 only), chunk_levels {16, 32}.  Each
+ * candidate runs the sample once untimed, then twice timed (HIP events); its
+ * score is the faster of the two, per source, and it replaces the running
+ * best only when 2% faster.  The choice is kept on the graph (used whenever
+ * a later call passes a zero field, by sp_bc for the block size) and in a
+ * process-wide cache keyed by the graph's fingerprint (sp_graph_fingerprint):
+ * a graph whose fingerprint is cached is not timed again, and an upload of a
+ * graph with a cached fingerprint starts with that configuration.  When the
+ * environment variable SP_TUNE_CACHE names a file, the cache is read from it
+ * on first use and every new choice is appended to it (one line per graph:
+ * fingerprint in hex, width, block, alpha, beta, chunk_levels).  Output
+ * buffers are not touched.  Synchronises the stream. */
 sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_sources,
                       sp_batch_config *out, sp_stream s);
+
+/* One configuration timed by the last sp_autotune call on this thread. */
+typedef struct sp_tune_candidate {
+    sp_batch_config cfg;
+    double ms_per_source;   /* the faster of the two timed repetitions, per source */
+    int32_t accepted;       /* 1: became the running best when timed */
+    int32_t reserved;
+} sp_tune_candidate;
+
+#define SP_TUNE_MAX_CANDIDATES 16
+
+/* Report of the last sp_autotune call on this thread. */
+typedef struct sp_tune_report {
+    uint64_t fingerprint;
+    int32_t from_cache;      /* 1: the configuration came from the cache; nothing was timed */
+    int32_t sample_sources;  /* sources in the timed sample */
+    int32_t repetitions;     /* timed repetitions per candidate */
+    int32_t n_candidates;    /* entries of cand[] filled, in the order timed */
+    double tuning_ms;        /* host time of the whole call, grouping keys included */
+    double group_ms;         /* of which computing the source-grouping keys */
+    sp_batch_config chosen;
+    sp_tune_candidate cand[SP_TUNE_MAX_CANDIDATES];
+} sp_tune_report;
+sp_status sp_autotune_get_last_report(sp_tune_report *out);
+
+/* 64-bit fingerprint of an uploaded graph: a hash of V, nnz, whether it is
+ * directed, the maximum degree, the sum of squared degrees and the
+ * histogram of degrees by power of two (in-degrees too for a directed
+ * graph).  Graphs with equal fingerprints share a cached tuning. */
+sp_status sp_graph_fingerprint(sp_graph g, uint64_t *out);
+
+/* Set the graph's tuned configuration (as if sp_autotune had chosen it; for
+ * example one saved by an earlier process), or clear it with NULL.  Fields
+ * are checked as for sp_bc_batch; zero fields keep their built-in defaults.
+ * Does not touch the fingerprint cache. */
+sp_status sp_graph_set_tuned(sp_graph g, const sp_batch_config *cfg);
+
+/* Empty the process-wide tuning cache (the SP_TUNE_CACHE file is kept). */
+sp_status sp_tune_cache_clear(void);
 
 /* ------------------------------------------------------------------------
  * Single-source shortest paths on a weighted graph (paper Section 2.2,

@@ -3,6 +3,7 @@
 // C++ exceptions and returns a status; nothing here aborts the process.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,16 +107,6 @@ static sp_status check_device(int *dev_out) {
     return SP_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int d) {
-        if (hipGetDevice(&prev) == hipSuccess && prev != d) (void)hipSetDevice(d);
-        else prev = -1;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // CSR checks
@@ -175,6 +166,20 @@ static bool host_validate(int32_t n, int64_t nnz, const int32_t *rp, const int32
         }
     }
     return true;
+}
+
+// Fingerprint of a freshly uploaded graph, and the tuned configuration the
+// cache holds for it (if any) as its starting configuration.
+static void adopt_cached_tuning(sp_graph g, const int32_t *in_deg) {
+    g->fingerprint = graph_fingerprint(g, in_deg);
+    sp_batch_config c{};
+    const bool hit = tune_cache_lookup(g->fingerprint, &c);
+    std::lock_guard<std::mutex> lk(g->mu);
+    g->tuned = TuneEntry{};
+    if (hit) {
+        g->tuned.valid = true;
+        g->tuned.cfg = c;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -251,6 +256,15 @@ static sp_status check_sources(sp_graph g, const int32_t *sources, int32_t n_sou
     return SP_OK;
 }
 
+sp_status check_bc_args(sp_graph g, const int32_t *sources, int32_t n_sources, const double *out_bc,
+                        const char *what) {
+    if (!g || (g->n > 0 && !out_bc)) {
+        set_error("%s: null graph or output", what);
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    return check_sources(g, sources, n_sources);
+}
+
 // Effective batched configuration: explicit fields, else tuned, else defaults.
 BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *width) {
     sp_batch_config t{};
@@ -261,15 +275,15 @@ BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *widt
     auto pick_i = [](int32_t a, int32_t b, int32_t d) { return a ? a : (b ? b : d); };
     auto pick_d = [](double a, double b, double d) { return a > 0 ? a : (b > 0 ? b : d); };
     BatchRunOpts o;
-    *width = pick_i(cfg ? cfg->batch_width : 0, t.batch_width, 64);
-    o.block = pick_i(cfg ? cfg->block_size : 0, t.block_size, 256);
-    o.alpha = pick_d(cfg ? cfg->alpha : 0, t.alpha, 15.0);
-    o.beta = pick_d(cfg ? cfg->beta : 0, t.beta, 24.0);
-    o.chunk_levels = pick_i(cfg ? cfg->chunk_levels : 0, t.chunk_levels, 8);
+    *width = pick_i(cfg ? cfg->batch_width : 0, t.batch_width, kDefaultWidth);
+    o.block = pick_i(cfg ? cfg->block_size : 0, t.block_size, kDefaultBlock);
+    o.alpha = pick_d(cfg ? cfg->alpha : 0, t.alpha, kDefaultAlpha);
+    o.beta = pick_d(cfg ? cfg->beta : 0, t.beta, kDefaultBeta);
+    o.chunk_levels = pick_i(cfg ? cfg->chunk_levels : 0, t.chunk_levels, kDefaultChunkLevels);
     return o;
 }
 
-static sp_status check_batch_cfg(const sp_batch_config *cfg) {
+sp_status check_batch_cfg(const sp_batch_config *cfg) {
     if (!cfg) return SP_OK;
     if (cfg->batch_width < 0 || cfg->batch_width > kSlots) {
         set_error("batch_width %d outside 0..64", cfg->batch_width);
@@ -484,6 +498,54 @@ sp_status ensure_pr_hubs(sp_graph g, hipStream_t st) {
     return SP_OK;
 }
 
+// The per-source loop shared by sp_bc and sp_bc_noalloc: out_bc zeroed,
+// then one pass per source in list order (block size from the graph's tuned
+// configuration).  Times the call with ws's events when it has them.
+sp_status bc_per_source(sp_graph g, SourceWorkspace &ws, const int32_t *sources, int32_t n_sources,
+                        double *out_bc, hipStream_t st, sp_stats *stats) {
+    sp_batch_config tcfg{};
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->tuned.valid) tcfg = g->tuned.cfg;
+    }
+    SourceRunOpts o;
+    if (tcfg.block_size) o.block = tcfg.block_size;
+    const bool timed = ws.ev0 && ws.ev1;
+    if (timed) SP_HIP(hipEventRecord(ws.ev0, st));
+    SP_TRY(launch_fill_f64(out_bc, g->n, 0.0, st));
+    bool flagged = false;
+    for (int32_t i = 0; i < n_sources; ++i) {
+        SourceResult r;
+        SP_TRY(source_run(g, ws, sources[i], out_bc, true, o, st, &r));
+        stats->n_passes++;
+        stats->max_levels = std::max(stats->max_levels, r.levels);
+        stats->levels_total += r.levels;
+        stats->topdown_levels += r.td;
+        stats->bottomup_levels += r.bu;
+        stats->reached_total += r.reached;
+        stats->sigma_max = std::max(stats->sigma_max, r.sigma_max);
+        if (r.flagged) {
+            stats->sigma_flagged++;
+            flagged = true;
+        }
+    }
+    if (timed) {
+        SP_HIP(hipEventRecord(ws.ev1, st));
+        SP_HIP(hipEventSynchronize(ws.ev1));
+        float ms = 0;
+        SP_HIP(hipEventElapsedTime(&ms, ws.ev0, ws.ev1));
+        stats->device_ms = ms;
+    } else {
+        SP_HIP(hipStreamSynchronize(st));
+    }
+    stats->batch_width = 1;
+    stats->block_size = o.block;
+    stats->alpha = o.alpha;
+    stats->beta = o.beta;
+    stats->chunk_levels = o.chunk_levels;
+    return flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
+}
+
 }  // namespace sp
 
 using namespace sp;
@@ -620,6 +682,7 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
     g->hub_chunks_in = g->hub_chunks;
     g->split_hub_chunks_in = g->split_hub_chunks;
     g->bytes = ((size_t)n_vertices + 1) * 4 + (size_t)std::max<int64_t>(nnz, 1) * 4;
+    adopt_cached_tuning(g, nullptr);
     *out = g;
     return SP_OK;
     SP_GUARD_END
@@ -704,6 +767,11 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
     g->hub_chunks_in = nch_in;
     g->split_hub_chunks_in = split_in;
     g->bytes += ir.size() * 4 + ic.size() * 4;
+    {
+        std::vector<int32_t> in_deg(n_vertices);
+        for (int32_t v = 0; v < n_vertices; ++v) in_deg[v] = ir[v + 1] - ir[v];
+        adopt_cached_tuning(g, in_deg.data());
+    }
     *out = g;
     return SP_OK;
     SP_GUARD_END
@@ -769,11 +837,7 @@ sp_status sp_get_last_stats(sp_stats *out) {
 sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc, sp_stream s) {
     SP_GUARD_BEGIN
     clear_error();
-    if (!g || (g->n > 0 && !out_bc)) {
-        set_error("sp_bc: null graph or output");
-        return SP_ERR_INVALID_ARGUMENT;
-    }
-    SP_TRY(check_sources(g, sources, n_sources));
+    SP_TRY(check_bc_args(g, sources, n_sources, out_bc, "sp_bc"));
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;
     sp_stats stats{};
@@ -789,45 +853,15 @@ sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *o
         SourceWorkspace *ws;
         ~Rel() { release_source_ws(g, ws); }
     } rel{g, ws};
-    sp_batch_config tcfg{};
-    {
-        std::lock_guard<std::mutex> lk(g->mu);
-        if (g->tuned.valid) tcfg = g->tuned.cfg;
-    }
-    SourceRunOpts o;
-    if (tcfg.block_size) o.block = tcfg.block_size;
-    SP_HIP(hipEventRecord(ws->ev0, st));
-    SP_TRY(launch_fill_f64(out_bc, g->n, 0.0, st));
-    bool flagged = false;
-    for (int32_t i = 0; i < n_sources; ++i) {
-        SourceResult r;
-        SP_TRY(source_run(g, *ws, sources[i], out_bc, true, o, st, &r));
-        stats.n_passes++;
-        stats.max_levels = std::max(stats.max_levels, r.levels);
-        stats.levels_total += r.levels;
-        stats.topdown_levels += r.td;
-        stats.bottomup_levels += r.bu;
-        stats.reached_total += r.reached;
-        stats.sigma_max = std::max(stats.sigma_max, r.sigma_max);
-        if (r.flagged) {
-            stats.sigma_flagged++;
-            flagged = true;
-        }
-    }
-    SP_HIP(hipEventRecord(ws->ev1, st));
-    SP_HIP(hipEventSynchronize(ws->ev1));
-    float ms = 0;
-    SP_HIP(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
-    stats.device_ms = ms;
-    stats.batch_width = 1;
-    stats.block_size = o.block;
-    stats.alpha = o.alpha;
-    stats.beta = o.beta;
-    stats.chunk_levels = o.chunk_levels;
-    g_stats = stats;
-    return flagged ? SP_WARN_SIGMA_LARGE : SP_OK;
+    const sp_status rc = bc_per_source(g, *ws, sources, n_sources, out_bc, st, &stats);
+    if (rc >= 0) g_stats = stats;
+    return rc;
     SP_GUARD_END
 }
+
+}  // extern "C"
+
+namespace sp {
 
 // Order in which sp_bc_batch cuts `sources` into batches: ascending summed
 // BFS distance to the kGroupHubs highest-degree vertices, then descending
@@ -836,10 +870,11 @@ sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *o
 // distances are computed once per graph with the per-source path.
 constexpr int kGroupHubs = 4;
 
-static sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sources, int32_t width,
-                               hipStream_t st, std::vector<int32_t> &order) {
+sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sources, int32_t width,
+                        hipStream_t st, std::vector<int32_t> &order, double *key_ms) {
     order.resize(n_sources);
     for (int32_t i = 0; i < n_sources; ++i) order[i] = i;
+    if (key_ms) *key_ms = 0.0;
     if (n_sources <= width) return SP_OK;
     bool ready;
     {
@@ -847,6 +882,7 @@ static sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sou
         ready = !g->group_key.empty();
     }
     if (!ready) {
+        const auto t0 = std::chrono::steady_clock::now();
         const int32_t n = g->n;
         std::vector<int32_t> hubs(n);
         for (int32_t v = 0; v < n; ++v) hubs[v] = v;
@@ -870,6 +906,8 @@ static sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sou
             SP_HIP(hipStreamSynchronize(st));
             for (int32_t v = 0; v < n; ++v) key[v] += dist[v] >= 0 ? dist[v] : n;
         }
+        if (key_ms)
+            *key_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         std::lock_guard<std::mutex> lk(g->mu);
         if (g->group_key.empty()) g->group_key = std::move(key);
     }
@@ -881,6 +919,10 @@ static sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sou
     });
     return SP_OK;
 }
+
+}  // namespace sp
+
+extern "C" {
 
 sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
                       const sp_batch_config *cfg, sp_stream s) {
@@ -927,7 +969,9 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
         }
     } evrel{e0, e1};
     std::vector<int32_t> order;
-    SP_TRY(source_groups(g, sources, n_sources, width, st, order));
+    double key_ms = 0.0;
+    SP_TRY(source_groups(g, sources, n_sources, width, st, order, &key_ms));
+    stats.group_ms = key_ms;
     std::vector<int32_t> grouped(n_sources);
     for (int32_t i = 0; i < n_sources; ++i) grouped[i] = sources[order[i]];
     SP_HIP(hipEventRecord(e0, st));

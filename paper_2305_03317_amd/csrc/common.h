@@ -79,6 +79,7 @@ struct sp_graph_s {
     int64_t split_hub_chunks = 0;     // sum over hubs of split_hub_span(degree) (BC paths)
     int64_t split_hub_chunks_in = 0;  // the same for incoming rows (= split_hub_chunks when undirected)
     size_t bytes = 0;
+    uint64_t fingerprint = 0;    // graph_fingerprint(): keys the tuning cache
     std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
     std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
                                      // (unreached: n each); empty until first needed
@@ -112,8 +113,20 @@ struct sp_graph_s {
 
 namespace sp {
 
-// Per-thread stats of the last BC call.
+// Per-thread stats of the last BC call (what sp_get_last_stats returns).
 sp_stats &tls_stats();
+
+// Makes device d current for the guard's scope.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int d) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != d) (void)hipSetDevice(d);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Level-loop control block shared by the kernels of one BFS pass.  It lives in
@@ -272,10 +285,18 @@ struct SourceWorkspace {
 sp_status source_ws_create(sp_graph g, SourceWorkspace &ws);
 void source_ws_destroy(SourceWorkspace &ws);
 
+// Built-in configuration of both BC paths (used where neither the caller nor
+// the autotuner set a field); the autotuner starts its search here.
+constexpr int32_t kDefaultWidth = 64;
+constexpr int kDefaultBlock = 512;
+constexpr double kDefaultAlpha = 15.0;
+constexpr double kDefaultBeta = 24.0;
+constexpr int kDefaultChunkLevels = 8;
+
 struct SourceRunOpts {
-    double alpha = 15.0, beta = 24.0;
-    int block = 256;
-    int chunk_levels = 8;
+    double alpha = kDefaultAlpha, beta = kDefaultBeta;
+    int block = kDefaultBlock;
+    int chunk_levels = kDefaultChunkLevels;
 };
 struct SourceResult {
     int32_t levels = 0;   // levels including level 0
@@ -287,6 +308,13 @@ struct SourceResult {
 // One source: forward (+ backward when with_backward); bc may be null.
 sp_status source_run(sp_graph g, SourceWorkspace &ws, int32_t src, double *bc, bool with_backward,
                      const SourceRunOpts &o, hipStream_t s, SourceResult *res);
+// sp_bc's work on a given workspace (api.hip): BC zeroed, then every source
+// in list order; counters added to *stats.  Synchronises the stream.
+sp_status bc_per_source(sp_graph g, SourceWorkspace &ws, const int32_t *sources, int32_t n_sources,
+                        double *out_bc, hipStream_t st, sp_stats *stats);
+// sp_bc's argument checks (null graph or output, sources in range).
+sp_status check_bc_args(sp_graph g, const int32_t *sources, int32_t n_sources, const double *out_bc,
+                        const char *what);
 
 // ---------------------------------------------------------------------------
 // Batched path (batch_path.hip)
@@ -344,9 +372,9 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
 void batch_ws_destroy(BatchWorkspace &ws);
 
 struct BatchRunOpts {
-    double alpha = 15.0, beta = 24.0;
-    int block = 256;
-    int chunk_levels = 8;
+    double alpha = kDefaultAlpha, beta = kDefaultBeta;
+    int block = kDefaultBlock;
+    int chunk_levels = kDefaultChunkLevels;
 };
 
 // Per-slot results of a pass, source-major ([slot * V + v]); any may be null.
@@ -510,6 +538,10 @@ sp_status tc_run(sp_graph g, unsigned long long *d_total, unsigned long long *pe
 // undirected graph.
 sp_status undirected_only(const char *what);
 
+// SP_ERR_INVALID_ARGUMENT with a message unless every field of cfg (nullable)
+// is within its documented range.
+sp_status check_batch_cfg(const sp_batch_config *cfg);
+
 // Builds g->hub_static / g->owner_static once (thread-safe).
 sp_status ensure_static_hubs(sp_graph g, hipStream_t s);
 // Builds g->pr_hubs / g->pr_owner once (thread-safe).
@@ -520,6 +552,20 @@ int64_t initial_qcap(int32_t n, int32_t width);
 sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out);
 void release_batch_ws(sp_graph g, BatchWorkspace *ws);
 BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *width);
+
+// Order in which sp_bc_batch cuts `sources` into batches of `width` (see
+// sp_bc_batch); *key_ms receives the time spent computing the per-graph
+// grouping keys in this call (0 when they were already cached).
+sp_status source_groups(sp_graph g, const int32_t *sources, int32_t n_sources, int32_t width,
+                        hipStream_t st, std::vector<int32_t> &order, double *key_ms);
+
+// Tuning cache keyed by graph fingerprint (autotune.hip): a hash of the
+// vertex and entry counts, direction and degree statistics, computed at
+// upload.  Process-wide; also kept in the file named by the environment
+// variable SP_TUNE_CACHE when it is set.
+uint64_t graph_fingerprint(const sp_graph_s *g, const int32_t *in_deg);
+bool tune_cache_lookup(uint64_t fp, sp_batch_config *out);
+void tune_cache_store(uint64_t fp, const sp_batch_config &cfg);
 
 // Kernels used by several files.
 sp_status launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);

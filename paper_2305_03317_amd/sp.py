@@ -46,7 +46,24 @@ class sp_stats(ctypes.Structure):
                 ("sigma_max", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("batch_width", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("chunk_levels", ctypes.c_int32), ("graph_launches", ctypes.c_int32)]
+                ("chunk_levels", ctypes.c_int32), ("graph_launches", ctypes.c_int32),
+                ("group_ms", ctypes.c_double)]
+
+
+SP_TUNE_MAX_CANDIDATES = 16
+
+
+class sp_tune_candidate(ctypes.Structure):
+    _fields_ = [("cfg", sp_batch_config), ("ms_per_source", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class sp_tune_report(ctypes.Structure):
+    _fields_ = [("fingerprint", ctypes.c_uint64), ("from_cache", ctypes.c_int32),
+                ("sample_sources", ctypes.c_int32), ("repetitions", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32), ("tuning_ms", ctypes.c_double),
+                ("group_ms", ctypes.c_double), ("chosen", sp_batch_config),
+                ("cand", sp_tune_candidate * SP_TUNE_MAX_CANDIDATES)]
 
 
 class sp_sssp_config(ctypes.Structure):
@@ -130,6 +147,10 @@ SIGNATURES = [
                               ctypes.POINTER(sp_batch_config), _VP]),
     ("sp_bc_workspace_bytes", _ST, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
     ("sp_autotune", _ST, [_VP, _I32P, ctypes.c_int32, ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_autotune_get_last_report", _ST, [ctypes.POINTER(sp_tune_report)]),
+    ("sp_graph_fingerprint", _ST, [_VP, ctypes.POINTER(ctypes.c_uint64)]),
+    ("sp_graph_set_tuned", _ST, [_VP, ctypes.POINTER(sp_batch_config)]),
+    ("sp_tune_cache_clear", _ST, []),
     ("sp_graph_set_weights", _ST, [_VP, _VP, ctypes.c_uint32, _VP]),
     ("sp_sssp", _ST, [_VP, ctypes.c_int32, _VP, ctypes.POINTER(sp_sssp_config), _VP]),
     ("sp_sssp_get_last_stats", _ST, [ctypes.POINTER(sp_sssp_stats)]),
@@ -471,6 +492,31 @@ def sp_autotune(g: Graph, sources, stream=None) -> dict:
     c = sp_batch_config()
     _check(lib().sp_autotune(g.handle, p, len(src), ctypes.byref(c), _stream(stream)), "sp_autotune")
     return _struct_dict(c)
+
+
+def sp_autotune_get_last_report() -> dict:
+    r = sp_tune_report()
+    _check(lib().sp_autotune_get_last_report(ctypes.byref(r)), "sp_autotune_get_last_report")
+    out = {k: getattr(r, k) for k, _ in r._fields_ if k not in ("chosen", "cand")}
+    out["chosen"] = _struct_dict(r.chosen)
+    out["candidates"] = [dict(cfg=_struct_dict(r.cand[i].cfg), ms_per_source=r.cand[i].ms_per_source,
+                              accepted=bool(r.cand[i].accepted)) for i in range(r.n_candidates)]
+    return out
+
+
+def sp_graph_fingerprint(g: Graph) -> int:
+    v = ctypes.c_uint64()
+    _check(lib().sp_graph_fingerprint(g.handle, ctypes.byref(v)), "sp_graph_fingerprint")
+    return v.value
+
+
+def sp_graph_set_tuned(g: Graph, config) -> None:
+    """Make `config` (dict or sp_batch_config) the graph's tuned configuration; None clears it."""
+    _check(lib().sp_graph_set_tuned(g.handle, _config(config)), "sp_graph_set_tuned")
+
+
+def sp_tune_cache_clear() -> None:
+    _check(lib().sp_tune_cache_clear(), "sp_tune_cache_clear")
 
 
 # ---------------------------------------------------------------------------

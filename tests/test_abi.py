@@ -59,7 +59,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
                "sp_server_config": sp.sp_server_config, "sp_server_stats": sp.sp_server_stats,
                "sp_kernel_profile": sp.sp_kernel_profile, "sp_sssp_config": sp.sp_sssp_config,
                "sp_sssp_stats": sp.sp_sssp_stats, "sp_pagerank_config": sp.sp_pagerank_config,
-               "sp_pagerank_stats": sp.sp_pagerank_stats, "sp_tc_stats": sp.sp_tc_stats}
+               "sp_pagerank_stats": sp.sp_pagerank_stats, "sp_tc_stats": sp.sp_tc_stats,
+               "sp_tune_candidate": sp.sp_tune_candidate, "sp_tune_report": sp.sp_tune_report}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sp.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
@@ -126,6 +127,12 @@ def test_server_calls_reject_bad_arguments_on_the_host():
     assert L.sp_request_release(None) == sp.SP_OK
     assert L.sp_server_destroy(None) == sp.SP_OK
     assert L.sp_autotune(None, None, 0, None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_autotune_get_last_report(None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_graph_fingerprint(None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_graph_set_tuned(None, None) == sp.SP_ERR_INVALID_ARGUMENT
+    assert L.sp_tune_cache_clear() == sp.SP_OK
+    rep = sp.sp_autotune_get_last_report()   # nothing tuned on this thread yet
+    assert rep["n_candidates"] == 0 and rep["candidates"] == []
     n = ctypes.c_int32()
     assert L.sp_profile_read(None, 4, ctypes.byref(n)) == sp.SP_ERR_INVALID_ARGUMENT
     assert L.sp_profile_enable(0) == sp.SP_OK

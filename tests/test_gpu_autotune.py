@@ -1,0 +1,129 @@
+"""The autotuner's choice is run and checked against the oracle, and its
+fingerprint cache behaves as documented (in-process and through the
+SP_TUNE_CACHE file).
+
+Bar as in the parity tests (Appendix Fig. "BC computation in StarPlat"):
+distances bit-exact, BC within 1e-9 relative and exactly zero where the
+oracle is zero.
+"""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_03317_amd import graphs
+from tests.test_gpu_parity import assert_bc, assert_sigma
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_03317_amd import sp as spmod
+    spmod.lib()
+    return spmod
+
+
+def tuned_graph():
+    rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 41)
+    srcs = graphs.sources(rp, 200, 42, min_degree=1)
+    return rp, ci, srcs
+
+
+def test_tuned_configuration_matches_oracle(sp):
+    rp, ci, srcs = tuned_graph()
+    sp.sp_tune_cache_clear()
+    g = sp.sp_graph_upload(rp, ci)
+    cfg = sp.sp_autotune(g, srcs)
+    rep = sp.sp_autotune_get_last_report()
+    print("tuned", json.dumps(cfg), "report", json.dumps(rep), flush=True)
+    assert not rep["from_cache"]
+    assert rep["sample_sources"] == 128 and rep["repetitions"] == 2
+    # block 2 + width 2 + alpha 2 + beta 2 + chunk 2, after the starting point
+    assert rep["n_candidates"] == 11
+    assert rep["candidates"][0]["cfg"]["block_size"] == 512
+    assert rep["candidates"][0]["cfg"]["batch_width"] == 64
+    assert all(c["ms_per_source"] > 0 for c in rep["candidates"])
+    assert rep["chosen"] == cfg and rep["fingerprint"] == sp.sp_graph_fingerprint(g)
+    assert cfg["block_size"] in (128, 256, 512) and 1 <= cfg["batch_width"] <= 64
+    ref = oracle.bc(rp, ci, srcs)
+    b, st = sp.sp_bc_batch(g, srcs)
+    stats = sp.sp_get_last_stats()
+    assert st == sp.SP_OK
+    for k in ("batch_width", "block_size", "alpha", "beta", "chunk_levels"):
+        assert stats[k] == cfg[k], k
+    assert_bc(b.cpu().numpy(), ref, "sp_bc_batch, tuned %s" % cfg)
+    a, st = sp.sp_bc(g, srcs)
+    assert st == sp.SP_OK and sp.sp_get_last_stats()["block_size"] == cfg["block_size"]
+    assert_bc(a.cpu().numpy(), ref, "sp_bc, tuned block %d" % cfg["block_size"])
+    # one tuned pass slot by slot
+    few = srcs[:cfg["batch_width"]]
+    bd, bs, bdl, st = sp.sp_batch_levels(g, few)
+    for i in (0, len(few) - 1):
+        d_ref, sig_ref, del_ref = oracle.source_detail(rp, ci, int(few[i]))
+        assert np.array_equal(bd[i].cpu().numpy(), d_ref), "dist, slot %d" % i
+        assert_sigma(bs[i].cpu().numpy(), sig_ref, "sigma, slot %d" % i)
+        assert_bc(bdl[i].cpu().numpy(), np.where(d_ref > 0, del_ref, 0.0), "delta, slot %d" % i)
+    # cached: not timed again; a re-upload of the same graph starts tuned
+    again = sp.sp_autotune(g, srcs)
+    assert again == cfg and sp.sp_autotune_get_last_report()["from_cache"]
+    g2 = sp.sp_graph_upload(rp, ci)
+    assert sp.sp_graph_fingerprint(g2) == sp.sp_graph_fingerprint(g)
+    b2, _ = sp.sp_bc_batch(g2, srcs)
+    assert sp.sp_get_last_stats()["block_size"] == cfg["block_size"]
+    assert np.array_equal(b2.cpu().numpy(), b.cpu().numpy())
+    # clearing the graph's tuning returns it to the built-in defaults
+    sp.sp_graph_set_tuned(g2, None)
+    sp.sp_bc_batch(g2, srcs)
+    s2 = sp.sp_get_last_stats()
+    assert (s2["batch_width"], s2["block_size"], s2["alpha"], s2["beta"], s2["chunk_levels"]) == \
+        (64, 512, 15.0, 24.0, 8)
+    g.release()
+    g2.release()
+    sp.sp_tune_cache_clear()
+
+
+CHILD = r"""
+import json, sys
+sys.path.insert(0, %(root)r)
+from paper_2305_03317_amd import graphs, sp
+rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 41)
+srcs = graphs.sources(rp, 200, 42, min_degree=1)
+g = sp.sp_graph_upload(rp, ci)
+sp.sp_bc_batch(g, srcs)
+st = sp.sp_get_last_stats()
+cfg = sp.sp_autotune(g, srcs)
+rep = sp.sp_autotune_get_last_report()
+print(json.dumps(dict(stats=st, cfg=cfg, from_cache=rep["from_cache"])))
+"""
+
+
+def test_tuning_cache_file(sp, tmp_path):
+    """A configuration stored under the graph's fingerprint in the SP_TUNE_CACHE
+    file is adopted at upload by a new process and returned by sp_autotune
+    without timing."""
+    rp, ci, _ = tuned_graph()
+    g = sp.sp_graph_upload(rp, ci)
+    fp = sp.sp_graph_fingerprint(g)
+    g.release()
+    path = tmp_path / "tune.txt"
+    path.write_text("%016x 17 128 7 9 6\n" % fp)
+    env = dict(os.environ, SP_TUNE_CACHE=str(path))
+    out = subprocess.run([sys.executable, "-c", CHILD % dict(root=ROOT)], env=env, cwd=ROOT,
+                         stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    st = res["stats"]
+    assert (st["batch_width"], st["block_size"], st["alpha"], st["beta"], st["chunk_levels"]) == \
+        (17, 128, 7.0, 9.0, 6)
+    assert res["from_cache"] == 1 and res["cfg"]["batch_width"] == 17

@@ -27,13 +27,15 @@ def sp():
     return spmod
 
 
-@pytest.mark.parametrize("k,slots", [(2, (0, 37)), (3, (0, 63)), (4, (5, 50))])
-def test_full_size_batch_slots(sp, k, slots):
+@pytest.mark.parametrize("k,slots,alpha", [(2, (0, 37), 15.0), (3, (0, 63), 4.0), (4, (5, 50), 15.0)])
+def test_full_size_batch_slots(sp, k, slots, alpha):
+    """Block 512 (the built-in default); on RMAT-22 with the threshold the
+    autotuner picks there (alpha 4)."""
     rp, ci, src, spec = graphs.workload(k)
     print("workload", spec["name"], "vertices", len(rp) - 1, flush=True)
     g = sp.sp_graph_upload(rp, ci)
     batch = src[:64]
-    bd, bs, bdl, st = sp.sp_batch_levels(g, batch)
+    bd, bs, bdl, st = sp.sp_batch_levels(g, batch, config={"block_size": 512, "alpha": alpha})
     assert st == sp.SP_OK
     for i in slots:
         s = int(batch[i])

@@ -78,6 +78,29 @@ def both_paths(sp, g, srcs, config=None):
     return a.cpu().numpy(), b.cpu().numpy(), sa, sb
 
 
+# Launch configurations the parity tests run: every block size both paths
+# are instantiated for, with the top-down -> bottom-up threshold at the
+# built-in value (15) and at the one the autotuner picks on RMAT graphs (4).
+# Set as the graph's tuned configuration, so sp_bc (block size) and
+# sp_bc_batch (block size, alpha) both run it.
+LAUNCH_CONFIGS = [(b, a) for b in (128, 256, 512) for a in (4.0, 15.0)]
+LAUNCH_IDS = ["block%d-alpha%g" % c for c in LAUNCH_CONFIGS]
+
+
+def use_launch_config(sp, g, block, alpha):
+    sp.sp_graph_set_tuned(g, {"block_size": block, "alpha": alpha})
+
+
+_REF = {}
+
+
+def cached(key, make):
+    """Oracle results shared by the parametrized cases of one input."""
+    if key not in _REF:
+        _REF[key] = make()
+    return _REF[key]
+
+
 # --------------------------------------------------------------------------
 
 def test_workload_uniform_4096_full(sp):
@@ -152,12 +175,18 @@ def test_batch_widths_and_partial_batches(sp, width):
     g.release()
 
 
-def test_rmat_14_both_paths(sp):
-    rp, ci = graphs.rmat(14, 16, graphs.RMAT_ABC, 5)
-    srcs = graphs.sources(rp, 130, 6, min_degree=1)
+@pytest.mark.parametrize("block,alpha", LAUNCH_CONFIGS, ids=LAUNCH_IDS)
+def test_rmat_14_both_paths(sp, block, alpha):
+    def make():
+        rp, ci = graphs.rmat(14, 16, graphs.RMAT_ABC, 5)
+        srcs = graphs.sources(rp, 130, 6, min_degree=1)
+        return rp, ci, srcs, oracle.bc(rp, ci, srcs)
+    rp, ci, srcs, ref = cached("rmat14", make)
     g = sp.sp_graph_upload(rp, ci)
-    ref = oracle.bc(rp, ci, srcs)
+    use_launch_config(sp, g, block, alpha)
     a, b, _, _ = both_paths(sp, g, srcs)
+    st = sp.sp_get_last_stats()
+    assert st["block_size"] == block and st["alpha"] == alpha
     assert_bc(a, ref, "sp_bc rmat14")
     assert_bc(b, ref, "sp_bc_batch rmat14")
     check_sources_detail(sp, g, rp, ci, srcs[:64])
@@ -185,23 +214,27 @@ def split_hub_graph(seed=31):
     return rp, ci
 
 
+@pytest.mark.parametrize("block,alpha", LAUNCH_CONFIGS, ids=LAUNCH_IDS)
 @pytest.mark.parametrize("case", ["rmat-16", "synthetic"])
-def test_split_hubs(sp, case):
+def test_split_hubs(sp, case, block, alpha):
     # hubs above 2048 neighbours are cut into 8m pieces numbered by row eighth
     # (both paths); sources include the hubs themselves (level-0 hubs)
-    if case == "rmat-16":
-        rp, ci = graphs.rmat(16, 16, graphs.RMAT_ABC, 8)
-        deg = np.diff(rp)
-        assert (deg > 2048).sum() >= 10
-        top = np.argsort(-deg, kind="stable")[:6].astype(np.int32)
-    else:
-        rp, ci = split_hub_graph()
-        top = np.arange(60000, 60000 + len(HUB_DEGREES), dtype=np.int32)[::-1].copy()
-    rest = [s for s in graphs.sources(rp, 80, 32, min_degree=1) if s not in set(top.tolist())]
-    srcs = np.concatenate([top, np.array(rest[:64 - len(top)], np.int32)])
+    def make():
+        if case == "rmat-16":
+            rp, ci = graphs.rmat(16, 16, graphs.RMAT_ABC, 8)
+            deg = np.diff(rp)
+            assert (deg > 2048).sum() >= 10
+            top = np.argsort(-deg, kind="stable")[:6].astype(np.int32)
+        else:
+            rp, ci = split_hub_graph()
+            top = np.arange(60000, 60000 + len(HUB_DEGREES), dtype=np.int32)[::-1].copy()
+        rest = [s for s in graphs.sources(rp, 80, 32, min_degree=1) if s not in set(top.tolist())]
+        srcs = np.concatenate([top, np.array(rest[:64 - len(top)], np.int32)])
+        return rp, ci, srcs, oracle.bc(rp, ci, srcs)
+    rp, ci, srcs, ref = cached("split-" + case, make)
     print(case, "vertices", len(rp) - 1, "max degree", int(np.diff(rp).max()), flush=True)
     g = sp.sp_graph_upload(rp, ci)
-    ref = oracle.bc(rp, ci, srcs)
+    use_launch_config(sp, g, block, alpha)
     a, b, sa, sb = both_paths(sp, g, srcs)
     assert sa == sp.SP_OK and sb == sp.SP_OK
     assert_bc(a, ref, "sp_bc " + case)
@@ -212,12 +245,17 @@ def test_split_hubs(sp, case):
     g.release()
 
 
-def test_road_grid_128(sp):
-    """High diameter (hundreds of levels) and path counts beyond 2^53."""
-    rp, ci = graphs.road(128, 0.02, 9)
-    srcs = graphs.sources(rp, 20, 10)
+@pytest.mark.parametrize("block", [128, 256, 512])
+def test_road_grid_128(sp, block):
+    """High diameter (hundreds of levels) and path counts beyond 2^53.  (Road
+    graphs never switch to bottom-up levels, so alpha plays no part.)"""
+    def make():
+        rp, ci = graphs.road(128, 0.02, 9)
+        srcs = graphs.sources(rp, 20, 10)
+        return rp, ci, srcs, oracle.bc(rp, ci, srcs)
+    rp, ci, srcs, ref = cached("road128", make)
     g = sp.sp_graph_upload(rp, ci)
-    ref = oracle.bc(rp, ci, srcs)
+    use_launch_config(sp, g, block, 15.0)
     a, b, _, _ = both_paths(sp, g, srcs)
     assert_bc(a, ref, "sp_bc road")
     assert_bc(b, ref, "sp_bc_batch road")
@@ -268,6 +306,22 @@ def test_runs_are_bit_identical(sp):
     a1, b1, _, _ = both_paths(sp, g, srcs)
     a2, b2, _, _ = both_paths(sp, g, srcs)
     assert np.array_equal(a1, a2) and np.array_equal(b1, b2)
+    g.release()
+
+
+def test_results_do_not_depend_on_block_size(sp):
+    """Sums run in CSR order and hub chunks are fixed by the degree, so each
+    path gives the same bits at every block size."""
+    rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 12)
+    srcs = graphs.sources(rp, 70, 13, min_degree=1)
+    g = sp.sp_graph_upload(rp, ci)
+    got = {}
+    for block in (128, 256, 512):
+        use_launch_config(sp, g, block, 4.0)
+        got[block] = both_paths(sp, g, srcs)[:2]
+    for block in (128, 256):
+        assert np.array_equal(got[block][0], got[512][0]), "sp_bc, block %d" % block
+        assert np.array_equal(got[block][1], got[512][1]), "sp_bc_batch, block %d" % block
     g.release()
 
 
@@ -330,20 +384,24 @@ def test_star_and_meshes_never_switch_direction(sp):
         g.release()
 
 
+@pytest.mark.parametrize("block", [128, 256, 512])
 @pytest.mark.parametrize("case", ["rmat", "road"])
-def test_hipgraph_capture_matches_direct_launches(sp, case):
+def test_hipgraph_capture_matches_direct_launches(sp, case, block):
     """The forward level chunk replayed from a captured hipGraph gives the same
     bits as direct launches, on every replay, with other device work between
     calls; an odd chunk length and a narrower batch (new slot set, so a new
     capture) still match the oracle."""
-    if case == "rmat":
-        rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 21)
-        srcs = graphs.sources(rp, 100, 22, min_degree=1)
-    else:
-        rp, ci = graphs.road(96, 0.02, 23)  # hundreds of levels: many replays per pass
-        srcs = graphs.sources(rp, 70, 24)
+    def make():
+        if case == "rmat":
+            rp, ci = graphs.rmat(13, 16, graphs.RMAT_ABC, 21)
+            srcs = graphs.sources(rp, 100, 22, min_degree=1)
+        else:
+            rp, ci = graphs.road(96, 0.02, 23)  # hundreds of levels: many replays per pass
+            srcs = graphs.sources(rp, 70, 24)
+        return rp, ci, srcs, oracle.bc(rp, ci, srcs)
+    rp, ci, srcs, ref = cached("capture-" + case, make)
     g = sp.sp_graph_upload(rp, ci)
-    ref = oracle.bc(rp, ci, srcs)
+    use_launch_config(sp, g, block, 4.0)
     direct, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": -8})
     assert st == sp.SP_OK and sp.sp_get_last_stats()["graph_launches"] == 0
     direct = direct.cpu().numpy()
