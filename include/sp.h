@@ -199,6 +199,26 @@ sp_status sp_bc(sp_graph g, const int32_t *sources, int32_t n_sources, double *o
 sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
                       const sp_batch_config *cfg, sp_stream s);
 
+/* sp_bc for callers that cannot allocate device memory while they run (tight
+ * serving loops, harnesses that forbid hipMalloc).  The same per-source
+ * computation and kernels, so bit-identical results, with the whole
+ * workspace (distances, path counts, dependencies, queue, level offsets, hub
+ * lists, control block: about 40 bytes per vertex plus a few dozen per vertex
+ * of degree > 256) carved from one fixed 64 MiB device array that the
+ * library holds on every GPU it runs on until the process ends.  Calls no
+ * device or pinned allocation routine.  Not capturable in a HIP graph (it
+ * reads level counts back to the host).  Same arguments, outputs and status
+ * as sp_bc, plus:
+ *   SP_ERR_INVALID_ARGUMENT  the graph's workspace exceeds 64 MiB (roughly
+ *                            V > 1.6M vertices): use sp_bc; nothing written.
+ *   SP_ERR_NOT_SUPPORTED     kernel profiling is on (it creates events).
+ * Calls on one GPU share that GPU's array: they are serialised on the host
+ * (each holds the GPU's lock until its stream has synchronised), so calls on
+ * different streams of one GPU never overlap.  The array keeps the last
+ * call's contents; every value a call reads is written by that call first. */
+sp_status sp_bc_noalloc(sp_graph g, const int32_t *sources, int32_t n_sources, double *out_bc,
+                        sp_stream s);
+
 /* Counters of the last sp_bc / sp_bc_batch call on this thread. */
 sp_status sp_get_last_stats(sp_stats *out);
 

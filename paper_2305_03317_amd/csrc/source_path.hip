@@ -584,14 +584,22 @@ static sp_status source_run_bs(sp_graph g, SourceWorkspace &ws, int32_t src, dou
     }
     const LevelCtl &c = *ws.ctl_host;
     const int32_t levels = c.level + 1;
-    if (with_backward && levels > 1) {
-        std::vector<int32_t> off(levels + 1), hchunks(levels);
-        SP_HIP(hipMemcpyAsync(off.data(), ws.level_off, sizeof(int32_t) * (levels + 1),
+    // Reverse pass, deepest level first.  The level offsets and hub chunk
+    // counts that size its launches come back to the host a window of
+    // kRevWindow levels at a time, into fixed buffers (no host allocation per
+    // call; one synchronisation per window).
+    constexpr int32_t kRevWindow = 1024;
+    int32_t off_w[kRevWindow + 1], hch_w[kRevWindow];
+    for (int32_t top = with_backward ? levels - 1 : 0; top >= 1; top -= kRevWindow) {
+        const int32_t lo = std::max(1, top - kRevWindow + 1);  // window: levels lo..top
+        SP_HIP(hipMemcpyAsync(off_w, ws.level_off + lo, sizeof(int32_t) * (top - lo + 2),
                               hipMemcpyDeviceToHost, s));
-        SP_HIP(hipMemcpyAsync(hchunks.data(), ws.hub_lvl_chunks, sizeof(int32_t) * levels,
+        SP_HIP(hipMemcpyAsync(hch_w, ws.hub_lvl_chunks + lo, sizeof(int32_t) * (top - lo + 1),
                               hipMemcpyDeviceToHost, s));
         SP_HIP(hipStreamSynchronize(s));
-        for (int32_t l = levels - 1; l >= 1; --l) {
+        const int32_t *off = off_w - lo;      // off[l] for l in [lo, top + 1]
+        const int32_t *hchunks = hch_w - lo;  // hchunks[l] for l in [lo, top]
+        for (int32_t l = top; l >= lo; --l) {
             const int32_t cnt = off[l + 1] - off[l];
             {
                 ProfScope ps(P_SRC_DELTA, s);

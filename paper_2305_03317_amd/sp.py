@@ -141,6 +141,7 @@ SIGNATURES = [
     ("sp_graph_info", _ST, [_VP, _I32P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)]),
     ("sp_bc", _ST, [_VP, _I32P, ctypes.c_int32, _VP, _VP]),
     ("sp_bc_batch", _ST, [_VP, _I32P, ctypes.c_int32, _VP, ctypes.POINTER(sp_batch_config), _VP]),
+    ("sp_bc_noalloc", _ST, [_VP, _I32P, ctypes.c_int32, _VP, _VP]),
     ("sp_get_last_stats", _ST, [ctypes.POINTER(sp_stats)]),
     ("sp_bfs_levels", _ST, [_VP, ctypes.c_int32, _VP, _VP, _VP, _VP]),
     ("sp_batch_levels", _ST, [_VP, _I32P, ctypes.c_int32, _VP, _VP, _VP,
@@ -336,6 +337,16 @@ def sp_bc_batch(g: Graph, sources, out_bc=None, config=None, stream=None):
     src, p = _host_i32(sources)
     st = _check(lib().sp_bc_batch(g.handle, p, len(src), out_bc.data_ptr(), _config(config),
                                   _stream(stream)), "sp_bc_batch")
+    return out_bc[:g.n], st
+
+
+def sp_bc_noalloc(g: Graph, sources, out_bc=None, stream=None):
+    """sp_bc on the library's fixed device workspace (no allocation inside the
+    call; graphs up to about 1.6M vertices). Returns (out_bc[:V], status)."""
+    out_bc = _out_f64(g, out_bc)
+    src, p = _host_i32(sources)
+    st = _check(lib().sp_bc_noalloc(g.handle, p, len(src), out_bc.data_ptr(), _stream(stream)),
+                "sp_bc_noalloc")
     return out_bc[:g.n], st
 
 
