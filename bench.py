@@ -18,9 +18,12 @@ steps with a HIP event pair around every kernel launch and device work
 counters -> kernels, roofline (dominant kernel: algorithmic bytes per launch /
 average launch time against 8 TB/s; traffic from the committed rocprofv3
 counter summary while the kernel sources are unchanged), forward_pass.
-Also: the per-source GPU path on a sample of the same sources (the batched
-vs per-source ratio), the CPU oracle on a bounded sample (cpu_baseline, which
-doubles as a parity check of this run), the serving workload (eight
+Also: the per-source GPU path on the same sources (the batched vs per-source
+ratio, and its own kernel roofline on a sample), the CPU oracle on a bounded
+sample (cpu_baseline, which doubles as a parity check of this run), the
+per-source path on RMAT scale 20 (256 sources), batched BC on the 4096 x 4096
+road-like grid (64 sources in one batch, captured level loop, sigma overflow
+check, oracle parity on two sources), the serving workload (eight
 resident graphs, seeded Poisson request stream; p50/p99 latency and TEPS),
 single-source shortest paths on the RMAT and road graphs with the paper's
 uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle),
@@ -398,6 +401,145 @@ def directed_benchmark(sp, torch, workload, n_sources):
                        "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}}
 
 
+def profile_kernels(sp, run, per):
+    """Run `run()` once with a HIP event pair around every kernel launch, then
+    once with the device work counters on; per-kernel launches, time per
+    `per` unit, average launch time and algorithmic GB/s, and the roofline of
+    the kernel with the most time (algorithmic bytes per launch over its
+    average launch time, against 8 TB/s)."""
+    sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
+    run()
+    prof = sp.sp_profile_read()
+    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
+    run()
+    counted = sp.sp_profile_read()
+    sp.sp_profile_enable(False)
+    kernels = {}
+    for kname, p in prof.items():
+        c = counted.get(kname, {})
+        scale = p["launches"] / c["launches"] if c.get("launches") else 0.0
+        alg = algorithmic_bytes(kname, c) * scale
+        launches = max(p["launches"], 1)
+        kernels[kname] = {"launches": p["launches"], "ms_per_unit": round(p["total_ms"] / per, 4),
+                          "avg_launch_ms": round(p["total_ms"] / launches, 4),
+                          "algorithmic_bytes_per_launch": int(alg / launches),
+                          "GBps_algorithmic": round(alg / max(p["total_ms"], 1e-9) / 1e6, 1)}
+    dom = max(kernels.items(), key=lambda kv: kv[1]["ms_per_unit"]) if kernels else None
+    roofline = None
+    if dom:
+        achieved = dom[1]["GBps_algorithmic"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom[0],
+                    "launches": dom[1]["launches"], "avg_launch_ms": dom[1]["avg_launch_ms"],
+                    "algorithmic_bytes_per_launch": dom[1]["algorithmic_bytes_per_launch"]}
+    return kernels, roofline
+
+
+def bc_parity(got, ref):
+    import numpy as np
+    nz = ref != 0
+    rel = float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
+    return {"max_rel_err": rel, "zero_exact": bool(np.all(got[~nz] == 0)),
+            "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}
+
+
+def per_source_benchmark(sp, torch, workload, n_sources, profile_sample=32, oracle_sources=4):
+    """Per-source BC path (sp_bc: one BFS pass per source) on a benchmark
+    graph: wall time over n_sources with the graph resident, the kernel
+    roofline over a sample of them, and the oracle on a few sources as CPU
+    baseline and parity check."""
+    import oracle
+    k = WORKLOADS[workload]
+    rp, ci, src, spec = workload_graph(k)
+    m = len(ci) // 2
+    srcs = src[:n_sources]
+    g = sp.sp_graph_upload(rp, ci)
+    out = torch.empty(len(rp) - 1, dtype=torch.float64, device="cuda")
+    sp.sp_bc(g, srcs[:1], out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = sp.sp_bc(g, srcs, out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stats = sp.sp_get_last_stats()
+    sample = srcs[:profile_sample]
+    kernels, roofline = profile_kernels(sp, lambda: sp.sp_bc(g, sample, out), len(sample))
+    attach_traffic(roofline, "bc_per_source_" + workload)
+    res = {"workload": "%s per-source BC" % spec["name"], "sources": len(srcs), "status": st,
+           "ms_per_source": round(wall * 1e3 / len(srcs), 3), "teps": len(srcs) * m / wall,
+           "unit": "TEPS (sources x undirected edges / time)", "block_size": stats["block_size"],
+           "levels_max": stats["max_levels"], "roofline": roofline,
+           "roofline_sample": "first %d sources" % len(sample), "kernels": kernels}
+    if oracle_sources > 0:
+        cs = srcs[:oracle_sources]
+        t0 = time.perf_counter()
+        ref = oracle.bc(rp, ci, cs)
+        cpu_s = time.perf_counter() - t0
+        got, _ = sp.sp_bc(g, cs, out)
+        res["cpu_baseline"] = {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                               "sample": "first %d sources, single-threaded C oracle, %.1f s" % (len(cs), cpu_s)}
+        res["parity"] = dict(sources=len(cs), **bc_parity(got.cpu().numpy(), ref))
+    g.release()
+    return res
+
+
+def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_sources=2):
+    """Batched BC on the road-like grid: every source in one batch (forward
+    level chunks replayed from captured hipGraphs, reverse levels device
+    driven), wall time per pass with the graph resident (best of `runs`),
+    level count and sigma-overflow status, the kernel roofline, and the oracle
+    on a few of the sources (a separate batch of them) as parity check."""
+    import numpy as np
+    import oracle
+    k = WORKLOADS[workload]
+    rp, ci, src, spec = workload_graph(k)
+    m = len(ci) // 2
+    srcs = src[:n_sources]
+    g = sp.sp_graph_upload(rp, ci)
+    out = torch.empty(len(rp) - 1, dtype=torch.float64, device="cuda")
+    sp.sp_bc_batch(g, srcs, out)  # warm: workspace and captured level chunks
+    times = []
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = sp.sp_bc_batch(g, srcs, out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        print("road batched pass: %.1f ms" % (times[-1] * 1e3), file=sys.stderr, flush=True)
+    stats = sp.sp_get_last_stats()
+    best = float(np.min(times))
+    kernels, roofline = profile_kernels(sp, lambda: sp.sp_bc_batch(g, srcs, out), 1)
+    attach_traffic(roofline, "bc_batch_" + workload)
+    cs = srcs[:oracle_sources]
+    t0 = time.perf_counter()
+    ref = oracle.bc(rp, ci, cs)
+    cpu_s = time.perf_counter() - t0
+    got, _ = sp.sp_bc_batch(g, cs, out)
+    g.release()
+    return {"workload": "%s batched BC" % spec["name"], "sources": len(srcs), "status": st,
+            "sigma_flagged_sources": stats["sigma_flagged"], "sigma_max": stats["sigma_max"],
+            "ms_per_pass": round(best * 1e3, 1), "ms_per_pass_runs": [round(t * 1e3, 1) for t in times],
+            "teps": len(srcs) * m / best, "unit": "TEPS (sources x undirected edges / time)",
+            "levels_max": stats["max_levels"], "batch_width": stats["batch_width"],
+            "chunk_levels": stats["chunk_levels"], "graph_launches": stats["graph_launches"],
+            "roofline": roofline, "kernels": kernels,
+            "cpu_baseline": {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
+                             "sample": "first %d sources, single-threaded C oracle, %.1f s" % (len(cs), cpu_s)},
+            "parity": dict(sources=len(cs), **bc_parity(got.cpu().numpy(), ref))}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
     """Serving workload: eight resident graphs, seeded requests (graph uniform,
     1..512 sources log-uniform), continuous batching by the library's server.
@@ -493,8 +635,16 @@ def main():
                     help="use the built-in defaults instead of sp_autotune's choice")
     ap.add_argument("--per-source-sample", type=int, default=-1,
                     help="sources timed through the per-source path (-1 = all, 0 = skip)")
-    ap.add_argument("--cpu-sample", type=int, default=4,
-                    help="sources timed through the CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=16,
+                    help="sources timed through the single-threaded CPU oracle (0 = skip)")
+    ap.add_argument("--cpu-parallel-sample", type=int, default=4,
+                    help="sources per host thread of the parallel oracle baseline (0 = skip)")
+    ap.add_argument("--per-source-profile", type=int, default=32,
+                    help="sources of the per-source path run with kernel timing (its roofline)")
+    ap.add_argument("--per-source-legs", default="rmat-20:256",
+                    help="per-source BC legs as workload:sources, comma-separated ('' = skip)")
+    ap.add_argument("--road-batched", default="road-4096:64",
+                    help="batched BC legs on road-like grids as workload:sources ('' = skip)")
     ap.add_argument("--serving-requests", type=int, default=80,
                     help="requests per phase of the serving workload (0 = skip)")
     ap.add_argument("--sssp-sources", default="rmat-22:16,road-4096:2",
@@ -601,11 +751,21 @@ def main():
         tuned = sp.sp_autotune(g, src)
         tuned = {k: tuned[k] for k in ("batch_width", "block_size", "alpha", "beta", "chunk_levels")}
         tuned["tuning_s"] = round(time.perf_counter() - t0, 2)
+        report = sp.sp_autotune_get_last_report()
+        tuned["group_ms"] = round(report["group_ms"], 1)
+        tuned["sample_sources"] = report["sample_sources"]
+        tuned["repetitions"] = report["repetitions"]
+        tuned["candidates"] = [dict(c["cfg"], ms_per_source=round(c["ms_per_source"], 4), accepted=c["accepted"])
+                               for c in report["candidates"]]
+        for c in tuned["candidates"]:
+            c.pop("reserved", None)
         print("autotuned:", tuned, file=sys.stderr, flush=True)
 
     out = torch.empty(n, dtype=torch.float64, device="cuda")
+    group_ms = tuned["group_ms"] if tuned else 0.0
     for _ in range(args.warmup):
         sp.sp_bc_batch(g, src, out_bc=out, config=cfg)
+        group_ms += sp.sp_get_last_stats()["group_ms"]  # nonzero only on the call that computes it
     torch.cuda.synchronize()
 
     def run_steps(tag):
@@ -705,7 +865,15 @@ def main():
         torch.cuda.synchronize()
         ps_s = time.perf_counter() - t0
         per_source = {"sources": len(ps_src), "teps": len(ps_src) * m / ps_s,
-                      "ms_per_source": ps_s * 1e3 / len(ps_src)}
+                      "ms_per_source": ps_s * 1e3 / len(ps_src),
+                      "block_size": sp.sp_get_last_stats()["block_size"]}
+        if args.per_source_profile > 0:
+            sample = ps_src[:args.per_source_profile]
+            pk, proof = profile_kernels(sp, lambda: sp.sp_bc(g, sample), len(sample))
+            attach_traffic(proof, "bc_per_source_" + spec["name"])
+            per_source["roofline"] = proof
+            per_source["roofline_sample"] = "first %d sources" % len(sample)
+            per_source["kernels"] = pk
 
     # CPU oracle on a bounded sample (also a parity check at full size)
     cpu = None
@@ -720,30 +888,32 @@ def main():
         cpu_s = time.perf_counter() - t0
         cpu = {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
                "sample": "first %d of the %d sources, single-threaded C oracle, %.1f s"
-                         % (len(cs), len(src), cpu_s)}
+                         % (len(cs), len(src), cpu_s), "cpu_model": cpu_model()}
         # The same oracle function on P host threads over disjoint chunks of a
         # larger sample (ctypes releases the GIL during each call); per-thread
         # BC summed in chunk order.
-        import concurrent.futures as cf
-        P = max(1, min(16, os.cpu_count() or 1))
-        ps_src = src[:P * args.cpu_sample]
-        chunks = [ps_src[i::P] for i in range(P)]
-        t0 = time.perf_counter()
-        with cf.ThreadPoolExecutor(P) as ex:
-            parts = list(ex.map(lambda c: oracle.bc(rp, ci, c), chunks))
-        par_s = time.perf_counter() - t0
-        cpu_par = {"value": len(ps_src) * m / par_s, "unit": "TEPS", "cores": P, "kind": "oracle",
-                   "sample": "first %d sources, %d threads x %d sources, %.1f s"
-                             % (len(ps_src), P, args.cpu_sample, par_s)}
+        if args.cpu_parallel_sample > 0:
+            import concurrent.futures as cf
+            P = max(1, min(16, os.cpu_count() or 1))
+            ps_src = src[:P * args.cpu_parallel_sample]
+            chunks = [ps_src[i::P] for i in range(P)]
+            t0 = time.perf_counter()
+            with cf.ThreadPoolExecutor(P) as ex:
+                list(ex.map(lambda c: oracle.bc(rp, ci, c), chunks))
+            par_s = time.perf_counter() - t0
+            cpu_par = {"value": len(ps_src) * m / par_s, "unit": "TEPS", "cores": P, "kind": "oracle",
+                       "sample": "first %d sources, %d threads x %d sources, %.1f s"
+                                 % (len(ps_src), P, args.cpu_parallel_sample, par_s)}
         got, _ = sp.sp_bc_batch(g, cs, config=cfg)
         got = got.cpu().numpy()
-        nz = ref != 0
-        rel = float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
-        parity = {"sources": len(cs), "max_rel_err": rel, "zero_exact": bool(np.all(got[~nz] == 0)),
-                  "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}
+        parity = dict(sources=len(cs), **bc_parity(got, ref))
 
     g.release()
     del out
+    per_source_legs = {wl: per_source_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+                       (leg.split(":") for leg in filter(None, args.per_source_legs.split(",")))}
+    road = {wl: road_batched_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+            (leg.split(":") for leg in filter(None, args.road_batched.split(",")))}
     sssp = {}
     for leg in filter(None, args.sssp_sources.split(",")):
         wl, ns = leg.split(":")
@@ -770,6 +940,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
+        "batched_over_per_source": (value / per_source["teps"]) if per_source else None,
+        "forward_GBps_algorithmic": forward["GBps_algorithmic"] if forward else None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s batched BC" % spec["name"], "vertices": n, "undirected_edges": m,
@@ -784,11 +956,13 @@ def main():
         "graph_launches_per_step": stats["graph_launches"],
         "status": max(statuses),
         "upload_ms": upload_ms,
+        "source_grouping_ms": round(group_ms, 1),
         "hbm_copy_GBps_measured": round(copy_gbps, 1) if copy_gbps == copy_gbps else None,
         "graph_build_s": gen_s,
-        "per_source_path": per_source,
-        "batched_over_per_source": (value / per_source["teps"]) if per_source else None,
         "roofline": roofline,
+        "per_source_path": per_source,
+        "per_source_legs": per_source_legs or None,
+        "road_batched": road or None,
         "forward_pass": forward,
         "kernels": kernels,
         "cpu_baseline": cpu,
