@@ -29,7 +29,7 @@ single-source shortest paths on the RMAT and road graphs with the paper's
 uniform [1, 100] weights (per-source time, kernel roofline, Dijkstra oracle),
 PageRank on the same graphs (time per iteration, kernel roofline, numpy
 oracle), the triangle count of the RMAT graph, and BC on a directed version
-of it (per-source path).
+of it (both paths).
 
 Prints one JSON line.
 """
@@ -342,10 +342,12 @@ def attach_traffic(roofline, profile_name):
 
 def directed_benchmark(sp, torch, workload, n_sources):
     """Betweenness centrality on a directed graph: the workload graph with
-    each undirected edge kept as one arc in a seeded direction, the first
-    n_sources of its sources, through the per-source path (the batched path
-    needs undirected graphs).  Kernel roofline as for the main line; the
-    oracle on two sources is the CPU baseline and a parity check."""
+    each undirected edge kept as one arc in a seeded direction.  Both paths
+    on the first n_sources of its sources (per-source: one BFS pass per
+    source; batched: one multi-source pass, parents from the reversed rows),
+    the batched path also on the workload's whole source list; kernel
+    roofline of the batched pass; the oracle on two sources is the CPU
+    baseline and a parity check of both paths."""
     import numpy as np
     import oracle
     from paper_2305_03317_amd import graphs
@@ -356,49 +358,55 @@ def directed_benchmark(sp, torch, workload, n_sources):
     g = sp.sp_graph_upload(rp, ci, directed=True)
     srcs = src[:n_sources]
     out = torch.empty(len(rp) - 1, dtype=torch.float64, device="cuda")
+
+    def timed(fn, s, reps=1):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = fn(g, s, out)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        return best, st, sp.sp_get_last_stats()
+
     sp.sp_bc(g, srcs[:1], out)
-    torch.cuda.synchronize()
+    ps_wall, st, ps_stats = timed(sp.sp_bc, srcs)
     t0 = time.perf_counter()
-    _, st = sp.sp_bc(g, srcs, out)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stats = sp.sp_get_last_stats()
-    sp.sp_profile_read()
-    sp.sp_profile_enable(sp.SP_PROFILE_TIMES)
-    sp.sp_bc(g, srcs, out)
-    prof = sp.sp_profile_read()
-    sp.sp_profile_enable(sp.SP_PROFILE_COUNTS)
-    sp.sp_bc(g, srcs, out)
-    counted = sp.sp_profile_read()
-    sp.sp_profile_enable(False)
-    kernels = {}
-    for kname, p in prof.items():
-        c = counted.get(kname, {})
-        kernels[kname] = {"launches": p["launches"], "ms": round(p["total_ms"], 3),
-                          "GBps_algorithmic": round(algorithmic_bytes(kname, c) / max(p["total_ms"], 1e-9) / 1e6, 1)}
-    dom = max(kernels.items(), key=lambda kv: kv[1]["ms"]) if kernels else None
-    roofline = None
-    if dom:
-        roofline = {"bound": "hbm", "achieved": dom[1]["GBps_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(dom[1]["GBps_algorithmic"] / HBM_PEAK_GBS, 4), "traffic": None,
-                    "kernel": dom[0], "avg_launch_ms": round(dom[1]["ms"] / max(dom[1]["launches"], 1), 4)}
-        attach_traffic(roofline, "directed_" + workload)
+    tuned = sp.sp_autotune(g, src)
+    tuning_s = time.perf_counter() - t0
+    sp.sp_bc_batch(g, srcs, out)  # warm: workspace, captured chunks
+    b_wall, bst, b_stats = timed(sp.sp_bc_batch, srcs, reps=3)
+    sp.sp_bc_batch(g, src, out)
+    ball_wall, ballst, ball_stats = timed(sp.sp_bc_batch, src, reps=2)
+    kernels, roofline = profile_kernels(sp, lambda: sp.sp_bc_batch(g, srcs, out), 1)
+    attach_traffic(roofline, "directed_" + workload)
     t0 = time.perf_counter()
     ref = oracle.bc(rp, ci, srcs[:2])
     cpu_s = time.perf_counter() - t0
-    got, _ = sp.sp_bc(g, srcs[:2], out)
-    got = got.cpu().numpy()
+    par = {}
+    for name, fn in (("per_source", sp.sp_bc), ("batched", sp.sp_bc_batch)):
+        got, _ = fn(g, srcs[:2], out)
+        par[name] = bc_parity(got.cpu().numpy(), ref)
     g.release()
-    nz = ref != 0
-    rel = float(np.max(np.abs(got[nz] - ref[nz]) / np.abs(ref[nz]))) if nz.any() else 0.0
+    per_source = {"sources": len(srcs), "ms_per_source": round(ps_wall * 1e3 / len(srcs), 3),
+                  "teps": len(srcs) * arcs / ps_wall, "status": st, "levels_max": ps_stats["max_levels"]}
+    batched = {"sources": len(srcs), "ms": round(b_wall * 1e3, 2), "teps": len(srcs) * arcs / b_wall,
+               "status": bst, "levels_max": b_stats["max_levels"],
+               "topdown_levels": b_stats["topdown_levels"], "bottomup_levels": b_stats["bottomup_levels"],
+               "config": {k2: tuned[k2] for k2 in ("batch_width", "block_size", "alpha", "beta", "chunk_levels")},
+               "tuning_s": round(tuning_s, 2)}
+    batched_all = {"sources": len(src), "ms": round(ball_wall * 1e3, 1), "teps": len(src) * arcs / ball_wall,
+                   "status": ballst, "passes": ball_stats["n_passes"]}
     return {"workload": "%s, each edge one arc (seed %d)" % (spec["name"], 4000 + k), "arcs": arcs,
-            "sources": len(srcs), "ms_per_source": round(wall * 1e3 / len(srcs), 3),
-            "teps": len(srcs) * arcs / wall, "unit": "TEPS (sources x arcs / time)", "status": st,
-            "levels_max": stats["max_levels"], "kernels": kernels, "roofline": roofline,
+            "unit": "TEPS (sources x arcs / time)",
+            "batched_over_per_source": batched["teps"] / per_source["teps"],
+            "per_source": per_source, "batched": batched, "batched_all_sources": batched_all,
+            "roofline": roofline, "kernels": kernels,
             "cpu_baseline": {"value": 2 * arcs / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
                              "sample": "first 2 sources, single-threaded C oracle, %.2f s" % cpu_s},
-            "parity": {"sources": 2, "max_rel_err": rel, "zero_exact": bool(np.all(got[~nz] == 0)),
-                       "pass": bool(rel <= 1e-9 and np.all(got[~nz] == 0))}}
+            "parity": dict(sources=2, **{k2: v for k2, v in par.items()},
+                           all_pass=all(v["pass"] for v in par.values()))}
 
 
 def profile_kernels(sp, run, per):
@@ -836,7 +844,8 @@ def main():
         launches = max(p["launches"], 1)
         e = {"launches": p["launches"], "ms_per_step": round(p["total_ms"] / args.steps, 3),
              "avg_launch_ms": round(p["total_ms"] / launches, 4),
-             "GBps_algorithmic": round(algorithmic_bytes(kname, p) / max(p["total_ms"], 1e-9) / 1e6, 1)}
+             "GBps_algorithmic": round(algorithmic_bytes(kname, p) / max(p["total_ms"], 1e-9) / 1e6, 1),
+             "per_launch": {u: int(p[u] / launches) for u in ("items", "edges", "pairs", "item_slots") if p[u]}}
         tr = traffic_doc["families"].get(kname) if traffic_doc else None
         if tr:
             e["GBps_hbm_counters"] = round(tr["traffic_bytes_per_launch"] * p["launches"] / max(p["total_ms"], 1e-9) / 1e6, 1)

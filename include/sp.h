@@ -121,12 +121,14 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
  * uploaded too), SP_VALIDATE adds sorted, duplicate-free rows without
  * self-loops.  Betweenness centrality then follows edge directions (paper
  * Section 2.3.1: the graph type offers neighbors and nodes_to; Brandes on a
- * directed graph counts shortest directed paths): sp_bc and sp_bfs_levels
- * run the per-source path, reading parents from the incoming rows and
- * children from the outgoing ones; sp_bc_batch runs that same path.  The
- * batched multi-source calls (sp_batch_levels, sp_autotune), the server,
- * edge weights / SSSP, PageRank and triangle counting need an undirected
- * graph and return SP_ERR_NOT_SUPPORTED. */
+ * directed graph counts shortest directed paths).  Both BC paths read
+ * parents from the incoming rows and children from the outgoing ones:
+ * discovery walks outgoing rows top-down and incoming rows bottom-up, path
+ * counts pull over incoming rows (long ones chunked, listed per level),
+ * dependencies over outgoing rows.  sp_bc, sp_bc_batch, sp_bfs_levels,
+ * sp_batch_levels, sp_autotune and the server accept directed graphs; edge
+ * weights / SSSP, PageRank and triangle counting need an undirected graph
+ * and return SP_ERR_NOT_SUPPORTED. */
 sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
                                    const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out);
 

@@ -934,8 +934,6 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
     }
     SP_TRY(check_sources(g, sources, n_sources));
     SP_TRY(check_batch_cfg(cfg));
-    // Directed graphs run the per-source path (one BFS pass per source).
-    if (g->directed) return sp_bc(g, sources, n_sources, out_bc, s);
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)s;
     int32_t width = 64;
@@ -1044,7 +1042,6 @@ sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources,
         set_error("sp_batch_levels: null graph/output or n_sources outside 1..64");
         return SP_ERR_INVALID_ARGUMENT;
     }
-    if (g->directed) return undirected_only("sp_batch_levels");
     SP_TRY(check_sources(g, sources, n_sources));
     SP_TRY(check_batch_cfg(cfg));
     DeviceGuard dg(g->device);

@@ -171,7 +171,6 @@ extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_s
             set_error("sp_autotune: need a graph, an output and at least one source");
             return SP_ERR_INVALID_ARGUMENT;
         }
-        if (g->directed) return undirected_only("sp_autotune");
         for (int32_t i = 0; i < n_sources; ++i)
             if (sources[i] < 0 || sources[i] >= g->n) {
                 set_error("sources[%d] out of range", i);

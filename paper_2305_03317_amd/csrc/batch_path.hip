@@ -325,6 +325,9 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->topdown_levels = 0;
         c->bottomup_levels = 0;
         c->hub_pack_.v = 0;
+        c->in_hub_pack_.v = 0;
+        c->in_hub_n = 0;
+        c->in_hub_nchunks = 0;
         c->hub_lo = 0;
         c->hub_hi = nh;
         c->hub_nchunks = nch;
@@ -546,6 +549,10 @@ __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
     hub_lvl_chunks[nl] = c->hub_nchunks;
     chunk_off[nl] = c->chunk_next;  // where this level's registrations put their chunk owners
     c->chunk_next += c->hub_nchunks;
+    const unsigned long long ip = ld_agent(&c->in_hub_pack_.v);  // directed: incoming-row hubs
+    c->in_hub_n = (int32_t)(ip >> 40);
+    c->in_hub_nchunks = (int32_t)(ip & ((1ull << 40) - 1));
+    c->in_hub_pack_.v = 0;
     c->front_deg = ld_agent(&c->next_deg_.v);
     c->unset_deg -= ld_agent(&c->settled_deg_.v);
     c->next_deg_.v = 0;
@@ -570,7 +577,9 @@ __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
 // seen, front of the new level) is done here.
 template <int BS>
 __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
-                                                 const int32_t *__restrict__ ci,
+                                                 const int32_t *__restrict__ rpi,
+                                                 const int32_t *__restrict__ cii,
+                                                 HubEntry *in_hub_list, long long in_hub_cap,
                                                  const int32_t *__restrict__ queue,
                                                  unsigned long long *qmask, uint32_t *qvb,
                                                  unsigned long long *seen, unsigned long long *nxt,
@@ -597,13 +606,14 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
     for (int32_t b = hi + (int32_t)(blockIdx.x * BS); b < tail; b += gridDim.x * BS) {
         const int32_t i = b + (int32_t)threadIdx.x;
         const bool valid = i < tail;
-        int32_t w = 0, beg = 0, end = 0;
+        int32_t w = 0, beg = 0, end = 0, dout = 0;
         unsigned long long m = 0;
         if (valid) {
             w = queue[i];
             m = nxt[w];
-            beg = rp[w];
-            end = rp[w + 1];
+            beg = rpi[w];  // parents: incoming row
+            end = rpi[w + 1];
+            dout = in_hub_list ? rp[w + 1] - rp[w] : end - beg;
         }
         const int32_t deg = end - beg;
         const int pc = __popcll(m);
@@ -625,13 +635,13 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
             while (bits) {
                 const int s = __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                const double acc = sparse_sum(beg, end, s, lvl, ci, front_cur, val, my_dag);
+                const double acc = sparse_sum(beg, end, s, lvl, cii, front_cur, val, my_dag);
                 val[vb + rank_in(m, s)] = acc;
                 my_max = fmax(my_max, acc);
                 if (sigma_is_large(acc)) my_flag |= 1ull << s;
             }
         }
-        dense_each(__ballot(dense), beg, end, m, lvl, ci, front_cur, val,
+        dense_each(__ballot(dense), beg, end, m, lvl, cii, front_cur, val,
                    [&](int jl, double acc, unsigned long long pr) {
                        const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
                        const unsigned long long mj = rl_u64(m, jl);
@@ -643,9 +653,18 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                        }
                        my_flag |= __ballot(mine && sigma_is_large(acc));
                    });
-        if (hub)
+        // Hub chunks of the level's outgoing rows (discovery, reverse pass)
+        // are kept for the whole pass; on a directed graph the path counts
+        // chunk the incoming rows, listed afresh for this level only.
+        if (in_hub_list) {
+            if (hub) hub_register(&c->in_hub_pack_.v, in_hub_list, in_hub_cap, 0, w, i, deg);
+            if (valid && fits && dout > kHubDeg)
+                hub_register(&c->hub_pack_.v, hub_list, hub_cap, c->hub_next, w, i, dout, owner,
+                             c->chunk_next, owner_cap);
+        } else if (hub) {
             hub_register(&c->hub_pack_.v, hub_list, hub_cap, c->hub_next, w, i, deg, owner,
                          c->chunk_next, owner_cap);
+        }
         if (sparse || dense) my_scan += (unsigned long long)deg;  // hubs: k_ms_sigma_hub
         if (valid) {
             qmask[i] = m;
@@ -654,11 +673,11 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
             const unsigned long long now = seen[w] | m;
             seen[w] = now;
             front_nxt[w] = make_front(m, lvl + 1, vb);
-            my_deg += (unsigned long long)deg;
+            my_deg += (unsigned long long)dout;  // the next frontier's outgoing entries
             my_pairs += (unsigned long long)pc;
             my_or |= m;
             ++my_items;
-            if (now == active) my_settled += (unsigned long long)deg;
+            if (now == active) my_settled += (unsigned long long)deg;  // incoming: bottom-up's scan
         }
     }
     my_max = wave_max_f64(my_max);
@@ -910,6 +929,9 @@ __device__ __forceinline__ double sum_hub_rows(const double *__restrict__ partia
 }
 
 // Path counts of the current level's hubs (after advance), chunk by chunk.
+// Undirected: the level's segment of the pass's hub list, through the owner
+// map; directed (in_hub_list set): the level's incoming-row hubs, found by
+// binary search over their chunk bases.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci,
@@ -919,15 +941,19 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
                                                      double *val, const HubEntry *hub_list,
                                                      const int32_t *__restrict__ owner,
                                                      const int32_t *__restrict__ chunk_off,
+                                                     const HubEntry *in_hub_list,
                                                      double *partial, unsigned long long *prof) {
     if (c->done) return;
     __shared__ unsigned long long s_red[1];
-    const int32_t nch = c->hub_nchunks, obase = chunk_off[c->level];
+    const bool in = in_hub_list != nullptr;
+    const int32_t nch = in ? c->in_hub_nchunks : c->hub_nchunks;
+    const int32_t obase = in ? 0 : chunk_off[c->level], in_n = in ? c->in_hub_n : 0;
     const uint32_t pl = (uint32_t)c->level - 1;
     const int lane = lane_id();
     unsigned long long my_dag = 0, my_edges = 0;
     for_xcd_chunks<BS>(nch, [&](int64_t k) {
-        const HubEntry h = hub_list[owner[obase + k]];
+        const HubEntry h = in ? in_hub_list[hub_find(in_hub_list, 0, in_n, (int32_t)k)]
+                              : hub_list[owner[obase + k]];
         int32_t beg, end;
         if (!hub_chunk_range(h, k, rp, beg, end)) return;
         const unsigned long long m = qmask[h.entry];
@@ -948,9 +974,11 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
 __global__ void k_ms_sigma_hub_fin(LevelCtl *c, const unsigned long long *__restrict__ qmask,
                                    const uint32_t *__restrict__ qvb, double *val,
                                    const HubEntry *__restrict__ hub_list,
-                                   const double *__restrict__ partial) {
+                                   const double *__restrict__ partial,
+                                   const HubEntry *__restrict__ in_hub_list) {
     if (c->done) return;
-    const int32_t hlo = c->hub_lo, hhi = c->hub_hi;
+    if (in_hub_list) hub_list = in_hub_list;  // directed: the level's incoming-row hubs
+    const int32_t hlo = in_hub_list ? 0 : c->hub_lo, hhi = in_hub_list ? c->in_hub_n : c->hub_hi;
     const int lane = lane_id();
     const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -1248,13 +1276,23 @@ static int64_t value_capacity(sp_graph g, int32_t width) {
     return (int64_t)std::max(g->n, 1) * width + kSlots;
 }
 
+// Hub chunk partial rows: the outgoing rows' chunks (reverse pass) or, on a
+// directed graph, one level's incoming-row chunks (path counts), whichever
+// needs more.
+static int64_t partial_rows(sp_graph g) {
+    return std::max(g->split_hub_chunks, g->directed ? g->split_hub_chunks_in : 0) + 1;
+}
+
+static int64_t in_hub_capacity(sp_graph g) { return g->directed ? (int64_t)g->n_hubs_in + 1 : 0; }
+
 size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
     const size_t V = (size_t)std::max(g->n, 1);
     return V * (8 + 8 + 16 + 16) + V * kSlots * 8 + (size_t)value_capacity(g, width) * 8 +
            (size_t)qcap * 16 + (V + 2) * 12 + kSlots * 4 +
            (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
+           (size_t)in_hub_capacity(g) * sizeof(HubEntry) +
            (size_t)owner_capacity(g) * 4 + (V + 2) * 4 +
-           ((size_t)g->split_hub_chunks + 1) * kSlots * 8 + sizeof(LevelCtl);
+           (size_t)partial_rows(g) * kSlots * 8 + sizeof(LevelCtl);
 }
 
 sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws) {
@@ -1287,7 +1325,9 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
     SP_TRY(dev_alloc((void **)&ws.hub_lvl_chunks, (size_t)ws.level_cap * 4));
     SP_TRY(dev_alloc((void **)&ws.hub_list, (size_t)ws.hub_cap * sizeof(HubEntry)));
     SP_TRY(dev_alloc((void **)&ws.hub_cnt, ((size_t)g->n_hubs + 1) * 4));
-    SP_TRY(dev_alloc((void **)&ws.partial, ((size_t)g->split_hub_chunks + 1) * kSlots * 8));
+    SP_TRY(dev_alloc((void **)&ws.partial, (size_t)partial_rows(g) * kSlots * 8));
+    ws.in_hub_cap = in_hub_capacity(g);
+    if (ws.in_hub_cap) SP_TRY(dev_alloc((void **)&ws.in_hub_list, (size_t)ws.in_hub_cap * sizeof(HubEntry)));
     SP_HIP(hipMemset(ws.hub_cnt, 0, ((size_t)g->n_hubs + 1) * 4));
     SP_TRY(dev_alloc((void **)&ws.slot_src, kSlots * 4));
     SP_TRY(dev_alloc((void **)&ws.ctl, sizeof(LevelCtl)));
@@ -1323,6 +1363,7 @@ void batch_ws_destroy(BatchWorkspace &ws) {
     dev_free(ws.chunk_off);
     dev_free(ws.hub_cnt);
     dev_free(ws.partial);
+    dev_free(ws.in_hub_list);
     dev_free(ws.slot_src);
     dev_free(ws.ctl);
     if (ws.ctl_host) (void)hipHostFree(ws.ctl_host);
@@ -1353,12 +1394,17 @@ static sp_status grow_queue(sp_graph g, BatchWorkspace &ws, int64_t qcap) {
 template <int BS>
 static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int count, int grid,
                            int hub_grid, bool may_pull, hipStream_t s) {
+    // Outgoing-row hubs (discovery, reverse pass); path-count hubs: the same
+    // rows when undirected, the incoming rows' own list when directed.
     const bool hubs = g->n_hubs > 0;
-    const int hub_fin_grid = grid_for((int64_t)g->n_hubs * kWave, 256, device_cu_count() * 8);
+    const bool sigma_hubs = g->directed ? g->n_hubs_in > 0 : hubs;
+    const HubEntry *in_list = g->directed ? (const HubEntry *)ws.in_hub_list : nullptr;
+    const int hub_fin_grid = grid_for((int64_t)std::max(g->n_hubs, g->n_hubs_in) * kWave, 256,
+                                      device_cu_count() * 8);
     for (int k = 0; k < count; ++k) {
         const int64_t l = first + k;  // level this group expands
         uint4 *fcur = ws.front[l & 1], *fnxt = ws.front[(l + 1) & 1];
-        if (!hubs && !may_pull && g->max_degree <= kExpandDeg) {  // road-like: one kernel per level
+        if (!hubs && !may_pull && g->max_degree <= kExpandDeg && !g->directed) {  // road-like: one kernel per level
             ProfScope ps(P_MS_EXPAND, s);
             hipLaunchKernelGGL(k_ms_expand<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, (int32_t *)ws.nxt,
@@ -1378,31 +1424,34 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
         }
         if (may_pull) {
             ProfScope ps(P_MS_BOTTOMUP, s);
-            hipLaunchKernelGGL(k_ms_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                               g->col_idx, ws.seen, ws.nxt, fcur, ws.queue, (long long)ws.qcap,
+            hipLaunchKernelGGL(k_ms_bottomup<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->rp_in,
+                               g->ci_in, ws.seen, ws.nxt, fcur, ws.queue, (long long)ws.qcap,
                                prof_counters(P_MS_BOTTOMUP));
         }
         {
             ProfScope ps(P_MS_SIGMA, s);
             hipLaunchKernelGGL(k_ms_sigma<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
-                               g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
+                               (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
+                               g->directed ? ws.in_hub_list : nullptr, (long long)ws.in_hub_cap,
+                               ws.queue, ws.qmask, ws.qvb, ws.seen, ws.nxt, fcur, fnxt,
                                ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
                                (long long)ws.qcap, (int32_t)may_pull, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks, ws.owner, (long long)ws.owner_cap,
                                ws.chunk_off, prof_counters(P_MS_SIGMA));
         }
-        if (hubs) {
+        if (sigma_hubs) {
             ProfScope ps(P_MS_SIGMA_HUB, s);
             hipLaunchKernelGGL(k_ms_sigma_hub<BS>, dim3(hub_grid), dim3(BS), 0, s, ws.ctl,
-                               g->row_ptr, g->col_idx, (const unsigned long long *)ws.qmask,
+                               g->rp_in, g->ci_in, (const unsigned long long *)ws.qmask,
                                (const uint32_t *)ws.qvb, (const uint4 *)fcur, ws.val,
                                (const HubEntry *)ws.hub_list, (const int32_t *)ws.owner,
-                               (const int32_t *)ws.chunk_off, ws.partial,
+                               (const int32_t *)ws.chunk_off, in_list, ws.partial,
                                prof_counters(P_MS_SIGMA_HUB));
             // (timed with the chunk kernel)
             hipLaunchKernelGGL(k_ms_sigma_hub_fin, dim3(hub_fin_grid), dim3(256), 0, s, ws.ctl,
                                (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
-                               ws.val, (const HubEntry *)ws.hub_list, (const double *)ws.partial);
+                               ws.val, (const HubEntry *)ws.hub_list, (const double *)ws.partial,
+                               in_list);
         }
     }
 }
@@ -1430,7 +1479,7 @@ static sp_status batch_forward(sp_graph g, BatchWorkspace &ws, int32_t n0, unsig
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
     const bool may_pull = o.alpha > 0 && g->max_degree > 8;  // sparse meshes never pull
-    const int hub_grid = xcd_grid(grid_for((int64_t)g->split_hub_chunks * kWave, BS, maxb), maxb);
+    const int hub_grid = xcd_grid(grid_for((partial_rows(g) - 1) * kWave, BS, maxb), maxb);
     hipLaunchKernelGGL(k_ms_clear, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.seen, ws.nxt,
                        ws.front[0], ws.front[1], n);
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, s, ws.ctl, (const int32_t *)g->row_ptr,

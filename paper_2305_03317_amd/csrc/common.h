@@ -354,7 +354,9 @@ struct BatchWorkspace {
     int32_t *hub_off = nullptr;          // device, level_cap: hub segment of each level
     int32_t *hub_lvl_chunks = nullptr;   // device, level_cap
     unsigned int *hub_cnt = nullptr;     // device, n_hubs + 1
-    double *partial = nullptr;           // device, (hub_chunks + 1) x 64
+    double *partial = nullptr;           // device, partial_rows x 64
+    HubEntry *in_hub_list = nullptr;     // device, directed graphs: one level's incoming-row hubs
+    int64_t in_hub_cap = 0;
     LevelCtl *ctl = nullptr;
     LevelCtl *ctl_host = nullptr;
     void *staging = nullptr;             // pinned: level-0 entries and slot sources

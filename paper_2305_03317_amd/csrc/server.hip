@@ -332,7 +332,6 @@ sp_status sp_server_create(const sp_server_config *cfg, sp_server *out) {
 
 sp_status sp_server_add_graph(sp_server srv, sp_graph g, int32_t *graph_id) {
     if (!srv || !g || !graph_id) return SP_ERR_INVALID_ARGUMENT;
-    if (g->directed) return undirected_only("sp_server_add_graph");
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stopping) return SP_ERR_REJECTED;
     GraphSlot gs;
