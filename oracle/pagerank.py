@@ -18,8 +18,9 @@ Reading: the paper accumulates the signed difference val - pr[v]; over a
 graph without dangling vertices that sum is zero after the first iteration
 (the iteration keeps total mass), so the loop would stop at once.  The
 convergence test here uses the absolute difference (the L1 norm of the
-change).  Vertices without out-edges keep their mass to themselves (it is
-not redistributed): the formula sums over in-neighbours only.
+change).  A vertex without out-edges passes nothing on: its term pr[u] /
+outdeg(u) appears in no sum, so its mass leaves the system each iteration
+(it is not redistributed; the formula sums over in-neighbours only).
 """
 from __future__ import annotations
 
