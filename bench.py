@@ -204,9 +204,12 @@ def pagerank_benchmark(sp, torch, workload, iterations):
     import numpy as np
     import oracle
     from paper_2305_03317_amd import graphs
-    k = WORKLOADS[workload]
+    directed = workload.endswith("-directed")
+    k = WORKLOADS[workload[:-len("-directed")] if directed else workload]
     rp, ci, _, spec = workload_graph(k)
-    g = sp.sp_graph_upload(rp, ci)
+    if directed:  # each undirected edge kept as one arc, seeded direction (as the directed BC leg)
+        rp, ci = graphs.directed_from(rp, ci, 4000 + k)
+    g = sp.sp_graph_upload(rp, ci, directed=directed)
     out = torch.empty(len(rp) - 1, dtype=torch.float64, device="cuda")
     sp.sp_pagerank(g, 0.0, 0.85, iterations, out)  # warm: workspace, hub list, captured chunk
     times = []
@@ -247,7 +250,9 @@ def pagerank_benchmark(sp, torch, workload, iterations):
     got = out.cpu().numpy()
     g.release()
     m = len(ci) // 2
-    return {"workload": "%s, damping 0.85, %d iterations" % (spec["name"], iterations),
+    return {"workload": "%s%s, damping 0.85, %d iterations"
+                        % (spec["name"], ", each edge one arc (seed %d)" % (4000 + k) if directed else "",
+                           iterations),
             "ms_per_iteration": round(per_iter * 1e3, 4), "teps": len(ci) / per_iter,
             "unit": "TEPS (adjacency entries gathered / time per iteration)", "undirected_edges": m,
             "kernels": kernels, "roofline": roofline,
@@ -657,7 +662,7 @@ def main():
                     help="requests per phase of the serving workload (0 = skip)")
     ap.add_argument("--sssp-sources", default="rmat-22:16,road-4096:2",
                     help="SSSP legs as workload:sources, comma-separated ('' = skip)")
-    ap.add_argument("--pagerank", default="rmat-22:20,road-4096:20",
+    ap.add_argument("--pagerank", default="rmat-22:20,road-4096:20,rmat-22-directed:20",
                     help="PageRank legs as workload:iterations, comma-separated ('' = skip)")
     ap.add_argument("--tc", default="rmat-22",
                     help="triangle-count workloads, comma-separated ('' = skip)")

@@ -126,9 +126,10 @@ sp_status sp_graph_upload(int32_t n_vertices, int64_t nnz, const int32_t *row_pt
  * discovery walks outgoing rows top-down and incoming rows bottom-up, path
  * counts pull over incoming rows (long ones chunked, listed per level),
  * dependencies over outgoing rows.  sp_bc, sp_bc_batch, sp_bfs_levels,
- * sp_batch_levels, sp_autotune and the server accept directed graphs; edge
- * weights / SSSP, PageRank and triangle counting need an undirected graph
- * and return SP_ERR_NOT_SUPPORTED. */
+ * sp_batch_levels, sp_autotune and the server accept directed graphs, and
+ * so does sp_pagerank (gathering over the reversed rows); edge weights /
+ * SSSP and triangle counting need an undirected graph and return
+ * SP_ERR_NOT_SUPPORTED. */
 sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_t *row_ptr,
                                    const int32_t *col_idx, uint32_t flags, sp_stream s, sp_graph *out);
 
@@ -395,16 +396,19 @@ sp_status sp_sssp_get_last_stats(sp_sssp_stats *out);
  *
  * Every vertex starts at 1/N.  Each iteration computes, from the previous
  * iteration's values,
- *     pr'[v] = (1 - delta) / N + delta * sum over neighbours u of pr[u] / deg(u)
+ *     pr'[v] = (1 - delta) / N + delta * sum over in-neighbours u of pr[u] / outdeg(u)
  * and the run stops after the first iteration whose sum over vertices of
  * |pr'[v] - pr[v]| is at most beta, or after max_iter iterations (at least
  * one runs).  The paper writes the signed difference; its sum is zero on a
  * graph without isolated vertices (the iteration keeps total mass), which
- * would stop the loop at once, so the absolute difference is used.  Mass of
- * vertices without neighbours is not redistributed.  The graph is undirected
- * (a vertex's in-neighbours are its row).  All arithmetic is binary64; each
- * vertex's sum is taken in an order fixed by its row, so results are
- * reproducible.
+ * would stop the loop at once, so the absolute difference is used.  On an
+ * undirected graph a vertex's in-neighbours are its row and outdeg its
+ * degree; on a directed one (sp_graph_upload_directed) the in-neighbours are
+ * its row of the reversed graph (the paper's nodes_to) and outdeg the length
+ * of its outgoing row.  A vertex without outgoing edges passes nothing on:
+ * its mass leaves the system (not redistributed).  All arithmetic is
+ * binary64; each vertex's sum is taken in an order fixed by its row, so
+ * results are reproducible.
  * ------------------------------------------------------------------------ */
 
 typedef struct sp_pagerank_config {

@@ -479,22 +479,26 @@ sp_status ensure_static_hubs(sp_graph g, hipStream_t st) {
     return upload_hub_layout(g, hubs, owners, st, &g->hub_static, &g->owner_static);
 }
 
-// PageRank's hub layout: every hub cut by row eighths into 8m near-equal
-// pieces of at most kHubChunk entries (split_piece), m = ceil(deg / (8 *
-// kHubChunk)); every hub's first chunk id is a multiple of 8.
+// PageRank's hub layout over the rows it gathers (a vertex's in-neighbours:
+// its own row when undirected, its reversed row when directed): every hub cut
+// by row eighths into 8m near-equal pieces of at most kHubChunk entries
+// (split_piece), m = ceil(deg / (8 * kHubChunk)); every hub's first chunk id
+// is a multiple of 8.
 sp_status ensure_pr_hubs(sp_graph g, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g->mu);
     if (g->pr_hubs) return SP_OK;
+    const std::vector<int32_t> &deg = g->directed ? g->host_deg_in : g->host_deg;
     std::vector<HubEntry> hubs;
     std::vector<int32_t> owners;
     for (int32_t v = 0; v < g->n; ++v)
-        if (g->host_deg[v] > kHubDeg) {
-            const int32_t nch = kXcds * ((g->host_deg[v] + kXcds * kHubChunk - 1) / (kXcds * kHubChunk));
+        if (deg[v] > kHubDeg) {
+            const int32_t nch = kXcds * ((deg[v] + kXcds * kHubChunk - 1) / (kXcds * kHubChunk));
             hubs.push_back(HubEntry{v, 0, (int32_t)owners.size(), nch});
             owners.insert(owners.end(), (size_t)nch, (int32_t)hubs.size() - 1);
         }
     SP_TRY(upload_hub_layout(g, hubs, owners, st, &g->pr_hubs, &g->pr_owner));
     g->pr_chunks = (int64_t)owners.size();
+    g->pr_n_hubs = (int32_t)hubs.size();
     return SP_OK;
 }
 
@@ -771,6 +775,7 @@ sp_status sp_graph_upload_directed(int32_t n_vertices, int64_t nnz, const int32_
         std::vector<int32_t> in_deg(n_vertices);
         for (int32_t v = 0; v < n_vertices; ++v) in_deg[v] = ir[v + 1] - ir[v];
         adopt_cached_tuning(g, in_deg.data());
+        g->host_deg_in = std::move(in_deg);
     }
     *out = g;
     return SP_OK;
@@ -1231,7 +1236,6 @@ sp_status sp_pagerank(sp_graph g, double beta, double delta, int32_t max_iter, d
         set_error("sp_pagerank: null graph/output, beta < 0, delta outside [0, 1] or max_iter < 1");
         return SP_ERR_INVALID_ARGUMENT;
     }
-    if (g->directed) return undirected_only("sp_pagerank");
     PrOpts o;
     if (cfg) {
         if ((cfg->block_size != 0 && cfg->block_size != 128 && cfg->block_size != 256 &&

@@ -81,6 +81,7 @@ struct sp_graph_s {
     size_t bytes = 0;
     uint64_t fingerprint = 0;    // graph_fingerprint(): keys the tuning cache
     std::vector<int32_t> host_deg;   // host, n: vertex degrees (from the upload)
+    std::vector<int32_t> host_deg_in;  // host, n: in-degrees (directed graphs only)
     std::vector<int32_t> group_key;  // host, n: summed distance to the highest-degree vertices
                                      // (unreached: n each); empty until first needed
     std::mutex mu;               // guards `tuned`, `group_key` and the workspace pools
@@ -99,6 +100,7 @@ struct sp_graph_s {
     sp::HubEntry *pr_hubs = nullptr;     // device, n_hubs (>= 1)
     int32_t *pr_owner = nullptr;         // device, pr_chunks (>= 1)
     int64_t pr_chunks = 0;
+    int32_t pr_n_hubs = 0;               // entries of pr_hubs
     // Triangle counting: rows oriented toward higher (degree, id) rank, built
     // on first use (ensure_oriented): offsets, entries, and each entry's row.
     int32_t *tc_orp = nullptr;       // device, n + 1

@@ -4,7 +4,9 @@
 // from the previous iteration's values, and the run stops once the sum over
 // vertices of |val - pr| is at most beta or max_iter iterations have run
 // (the absolute difference is this library's reading of the paper's `diff`).
-// The graph is undirected, so a vertex's in-neighbours are its row.
+// A vertex's in-neighbours are its row on an undirected graph and its row of
+// the reversed graph on a directed one; outdeg is always the outgoing row's
+// length, and a vertex without outgoing arcs passes nothing on.
 //
 // Design: each iteration is one streaming pass over the CSR.  The producer of
 // a value also stores share = val / outdeg, so the gather reads one double
@@ -91,7 +93,8 @@ __global__ void k_pr_init(PrCtl *c, const int32_t *__restrict__ rp, double *pr, 
 // Without hubs this kernel closes the iteration.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_pr_pull(PrCtl *c, const int32_t *__restrict__ rp,
-                                                const int32_t *__restrict__ ci, double *pr0,
+                                                const int32_t *__restrict__ ci,
+                                                const int32_t *__restrict__ rpo, double *pr0,
                                                 double *pr1, double *sh0, double *sh1,
                                                 double *partial, const HubEntry *__restrict__ hs,
                                                 const int32_t *__restrict__ os, int32_t n,
@@ -115,10 +118,11 @@ __global__ __launch_bounds__(BS) void k_pr_pull(PrCtl *c, const int32_t *__restr
         const WaveScratch ws{s_coff + wbase, s_beg + wbase, s_deg + wbase, s_acc + wbase, nullptr};
         for (int32_t b = blockIdx.x * BS + wbase; b < n; b += gridDim.x * BS) {
             const int32_t v = b + lane;
-            int32_t beg = 0, deg = 0;
+            int32_t beg = 0, deg = 0, dout = 0;
             if (v < n) {
                 beg = rp[v];
                 deg = rp[v + 1] - beg;
+                dout = rpo == rp ? deg : rpo[v + 1] - rpo[v];
             }
             const bool hub = deg > kHubDeg, shortrow = deg <= kPrShortRow;
             // short rows: the lane's own row, all loads issued before the
@@ -142,7 +146,7 @@ __global__ __launch_bounds__(BS) void k_pr_pull(PrCtl *c, const int32_t *__restr
                 const double val = teleport + delta * sum;
                 my_diff += fabs(val - pr[v]);
                 pr_n[v] = val;
-                sh_n[v] = deg > 0 ? val / (double)deg : 0.0;
+                sh_n[v] = dout > 0 ? val / (double)dout : 0.0;
                 ++my_items;
                 my_edges += (unsigned long long)deg;
             }
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(BS) void k_pr_pull(PrCtl *c, const int32_t *__restr
 
 // Hubs of one iteration from their chunk sums, in row order (a thread per
 // hub); closes the iteration.
-__global__ void k_pr_hub_fin(PrCtl *c, const int32_t *__restrict__ rp, double *pr0, double *pr1,
+__global__ void k_pr_hub_fin(PrCtl *c, const int32_t *__restrict__ rpo, double *pr0, double *pr1,
                              double *sh0, double *sh1, const double *__restrict__ partial,
                              const HubEntry *__restrict__ hs, int32_t nh, double teleport,
                              double delta, int32_t parity) {
@@ -182,7 +186,8 @@ __global__ void k_pr_hub_fin(PrCtl *c, const int32_t *__restrict__ rp, double *p
         const double val = teleport + delta * sum_split_chunks(partial, h.chunk_base, h.nchunks);
         my_diff += fabs(val - pr[h.v]);
         pr_n[h.v] = val;
-        sh_n[h.v] = val / (double)(rp[h.v + 1] - rp[h.v]);
+        const int32_t dout = rpo[h.v + 1] - rpo[h.v];  // outgoing row (may be empty when directed)
+        sh_n[h.v] = dout > 0 ? val / (double)dout : 0.0;
     }
     add_block_diff<256>(c, my_diff, s_w);
     if (last_block(c, working_blocks((int64_t)nh, 256)) && threadIdx.x == 0) close_iteration(c);
@@ -238,13 +243,14 @@ void pr_ws_destroy(PrWorkspace &ws) {
 template <int BS>
 static void enqueue_iterations(sp_graph g, PrWorkspace &ws, int count, int grid, int fin_grid,
                                double teleport, double delta, hipStream_t s) {
-    const bool hubs = g->n_hubs > 0;
+    const bool hubs = g->pr_n_hubs > 0;
     for (int k = 0; k < count; ++k) {
         const int32_t parity = k & 1;
         {
             ProfScope ps(P_PR_PULL, s);
             hipLaunchKernelGGL(k_pr_pull<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
-                               (const int32_t *)g->row_ptr, (const int32_t *)g->col_idx, ws.pr[0],
+                               (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
+                               (const int32_t *)g->row_ptr, ws.pr[0],
                                ws.pr[1], ws.share[0], ws.share[1], ws.partial,
                                (const HubEntry *)g->pr_hubs, (const int32_t *)g->pr_owner, g->n,
                                (int32_t)g->pr_chunks, teleport, delta, (int32_t)!hubs, parity,
@@ -254,7 +260,7 @@ static void enqueue_iterations(sp_graph g, PrWorkspace &ws, int count, int grid,
             ProfScope ps(P_PR_HUB, s);
             hipLaunchKernelGGL(k_pr_hub_fin, dim3(fin_grid), dim3(256), 0, s, ws.ctl,
                                (const int32_t *)g->row_ptr, ws.pr[0], ws.pr[1], ws.share[0], ws.share[1],
-                               (const double *)ws.partial, (const HubEntry *)g->pr_hubs, g->n_hubs,
+                               (const double *)ws.partial, (const HubEntry *)g->pr_hubs, g->pr_n_hubs,
                                teleport, delta, parity);
         }
     }
@@ -272,7 +278,7 @@ static sp_status pr_run_bs(sp_graph g, PrWorkspace &ws, double beta, double delt
     const int32_t n = g->n;
     const int maxb = device_cu_count() * 8;
     const int grid = grid_for((int64_t)n, BS, maxb);
-    const int fin_grid = grid_for((int64_t)g->n_hubs, 256, maxb);
+    const int fin_grid = grid_for((int64_t)g->pr_n_hubs, 256, maxb);
     const double teleport = (1.0 - delta) / (double)n;
     hipLaunchKernelGGL(k_pr_init, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, ws.ctl,
                        (const int32_t *)g->row_ptr, ws.pr[0], ws.share[0], n, beta, max_iter);
@@ -286,7 +292,7 @@ static sp_status pr_run_bs(sp_graph g, PrWorkspace &ws, double beta, double delt
             const std::array<long long, 12> key = {
                 BS, grid, fin_grid, chunk, (long long)(intptr_t)ws.pr[0], (long long)(intptr_t)ws.ctl,
                 (long long)(intptr_t)g->pr_hubs, bits_of(teleport),
-                bits_of(delta), g->n_hubs, 0, 0};
+                bits_of(delta), g->pr_n_hubs, 0, 0};
             SP_TRY(replay_captured(&ws.cap_stream, ws.iters, key,
                                    [&](hipStream_t cs) {
                                        enqueue_iterations<BS>(g, ws, chunk, grid, fin_grid, teleport, delta, cs);

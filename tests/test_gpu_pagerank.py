@@ -139,3 +139,47 @@ def test_full_size(sp, k):
     assert sp.sp_pagerank_get_last_stats()["iterations"] == 3
     ref, _, _ = oracle.pagerank(rp, ci, 0.0, D, 3, iterations=3)
     assert np.max(np.abs(got - ref) / ref) <= TOL
+
+
+def directed_cases():
+    """Directed graphs: RMAT arcs with seeded directions (hubs with long
+    incoming rows, vertices without outgoing arcs), an in-star whose centre
+    has 3000 incoming arcs and none outgoing, an out-star, and a directed
+    cycle."""
+    from tests import brute
+    rp, ci = graphs.rmat(13, 16, seed=15)
+    yield "rmat-13-directed", graphs.directed_from(rp, ci, 16)
+    n = 3001
+    yield "in-star", brute.directed_csr(n, np.arange(1, n), np.zeros(n - 1, np.int64))
+    yield "out-star", brute.directed_csr(n, np.zeros(n - 1, np.int64), np.arange(1, n))
+    yield "cycle", brute.directed_csr(500, np.arange(500), (np.arange(500) + 1) % 500)
+
+
+@pytest.mark.parametrize("name", ["rmat-13-directed", "in-star", "out-star", "cycle"])
+@pytest.mark.parametrize("cfg", [None, {"block_size": 128}, {"chunk_iters": -3}])
+def test_directed(sp, name, cfg):
+    """PageRank over incoming arcs (the paper's nodes_to), shares divided by
+    the outgoing row's length; a vertex with no outgoing arcs passes nothing
+    on."""
+    rp, ci = dict(directed_cases())[name]
+    g = sp.sp_graph_upload(rp, ci, validate=True, directed=True)
+    print(name, cfg, flush=True)
+    got, _ = check(sp, g, rp, ci, 1e-10, 200, cfg, what=name)
+    if name == "cycle":
+        assert np.allclose(got, 1 / 500, rtol=1e-14, atol=0)
+    if name == "in-star":  # leaves: teleport only; the centre gathers every leaf
+        n = len(rp) - 1
+        a = (1 - D) / n
+        assert np.allclose(got[1:], a, rtol=1e-14)
+        assert abs(got[0] - (a + D * (n - 1) * a)) <= 1e-13 * got[0]
+    g.release()
+
+
+def test_directed_full_size(sp):
+    rp, ci, _, spec = graphs.workload(3)
+    drp, dci = graphs.directed_from(rp, ci, 4003)
+    g = sp.sp_graph_upload(drp, dci, directed=True)
+    got = sp.sp_pagerank(g, 0.0, D, 3).cpu().numpy()
+    ref, _, _ = oracle.pagerank(drp, dci, 0.0, D, 3, iterations=3)
+    assert np.max(np.abs(got - ref) / ref) <= TOL
+    g.release()
