@@ -67,6 +67,12 @@ BYTE_MODEL = {
     "ms_expand": dict(items=40, edges=16, pairs=8, item_slots=20),
     "ms_bottomup": dict(items=16, edges=20),
     "ms_bc": dict(items=24, item_slots=8),
+    # blocks engine, one workgroup per source, forward and reverse levels in
+    # one kernel: items = vertices reached, edges = outgoing entries expanded,
+    # pairs = DAG edges summed (path counts and dependencies); per source the
+    # forward and reverse byte models added up (28 + 44 per vertex, 8 + 8 per
+    # adjacency entry, 16 per DAG edge and pass)
+    "wg_bc": dict(items=72, edges=16, pairs=16),
     "src_topdown": dict(items=12, edges=8),
     "src_bottomup": dict(items=12, edges=8),
     "src_sigma": dict(items=20, edges=8, pairs=8),
@@ -498,11 +504,13 @@ def per_source_benchmark(sp, torch, workload, n_sources, profile_sample=32, orac
 
 
 def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_sources=2):
-    """Batched BC on the road-like grid: every source in one batch (forward
-    level chunks replayed from captured hipGraphs, reverse levels device
-    driven), wall time per pass with the graph resident (best of `runs`),
-    level count and sigma-overflow status, the kernel roofline, and the oracle
-    on a few of the sources (a separate batch of them) as parity check."""
+    """Batched BC on the road-like grid: every source in one batch, in the
+    library's automatic engine for road-like graphs (one workgroup per source,
+    the whole pass in one launch); wall time per pass with the graph resident
+    (best of `runs`), level count and sigma-overflow status, the kernel
+    roofline, the other engine (one multi-source bitmap pass, levels replayed
+    from captured hipGraphs) timed for comparison, and the oracle on a few of
+    the sources (a separate batch of them) as parity check."""
     import numpy as np
     import oracle
     k = WORKLOADS[workload]
@@ -524,6 +532,14 @@ def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_source
     best = float(np.min(times))
     kernels, roofline = profile_kernels(sp, lambda: sp.sp_bc_batch(g, srcs, out), 1)
     attach_traffic(roofline, "bc_batch_" + workload)
+    bitmap = {"engine": sp.SP_ENGINE_BITMAP}
+    sp.sp_bc_batch(g, srcs, out, config=bitmap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sp.sp_bc_batch(g, srcs, out, config=bitmap)
+    torch.cuda.synchronize()
+    bitmap_ms = (time.perf_counter() - t0) * 1e3
+    bitmap_levels = sp.sp_get_last_stats()["graph_launches"]
     cs = srcs[:oracle_sources]
     t0 = time.perf_counter()
     ref = oracle.bc(rp, ci, cs)
@@ -535,8 +551,11 @@ def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_source
             "ms_per_pass": round(best * 1e3, 1), "ms_per_pass_runs": [round(t * 1e3, 1) for t in times],
             "teps": len(srcs) * m / best, "unit": "TEPS (sources x undirected edges / time)",
             "levels_max": stats["max_levels"], "batch_width": stats["batch_width"],
+            "engine": {1: "bitmap", 2: "blocks"}.get(stats["engine"], stats["engine"]),
+            "block_size": stats["block_size"],
             "chunk_levels": stats["chunk_levels"], "graph_launches": stats["graph_launches"],
             "roofline": roofline, "kernels": kernels,
+            "bitmap_engine": {"ms_per_pass": round(bitmap_ms, 1), "graph_launches": bitmap_levels},
             "cpu_baseline": {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
                              "sample": "first %d sources, single-threaded C oracle, %.1f s" % (len(cs), cpu_s)},
             "parity": dict(sources=len(cs), **bc_parity(got.cpu().numpy(), ref))}
@@ -678,6 +697,8 @@ def main():
                     help="run only the SSSP legs and print their JSON object")
     ap.add_argument("--only-pagerank", action="store_true",
                     help="run only the PageRank legs and print their JSON object")
+    ap.add_argument("--only-road", action="store_true",
+                    help="run only the road-like batched BC legs and print their JSON object")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one elementwise kernel that reads and writes this many GiB "
                          "(a known-size kernel that calibrates hardware byte counters in a "
@@ -726,8 +747,11 @@ def main():
         rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
-    if args.only_sssp or args.only_pagerank or args.only_tc or args.only_directed:
+    if args.only_sssp or args.only_pagerank or args.only_tc or args.only_directed or args.only_road:
         legs = {}
+        if args.only_road:
+            legs["road_batched"] = {wl: road_batched_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+                                    (leg.split(":") for leg in filter(None, args.road_batched.split(",")))}
         if args.only_directed:
             legs["directed_bc"] = {wl: directed_benchmark(sp, torch, wl, int(ns)) for wl, ns in
                                    (leg.split(":") for leg in filter(None, args.directed.split(",")))}

@@ -155,9 +155,28 @@ typedef struct sp_batch_config {
                              to even) in one hipGraph and replays it, checking the
                              device "done" flag on the host after each replay;
                              k < 0: |k| levels per check, launched directly (no
-                             capture).  |k| <= 65536. */
-    int32_t reserved[3];  /* must be zero */
+                             capture).  |k| <= 65536.  (Bitmap engine only.) */
+    int32_t engine;       /* SP_ENGINE_* below; 0 = SP_ENGINE_AUTO */
+    int32_t reserved[2];  /* must be zero */
 } sp_batch_config;
+
+/* How a batch runs:
+ *   SP_ENGINE_BITMAP  one multi-source pass: a 64-bit source bitmap per vertex,
+ *                     all slots advancing level by level together, each level
+ *                     a few grid-wide kernels (levels captured in hipGraphs).
+ *   SP_ENGINE_BLOCKS  one workgroup per source, the whole pass (forward and
+ *                     reverse levels) inside one launch with the workgroup
+ *                     barrier between levels; per-slot dist/sigma/delta
+ *                     source-major.  For graphs of many small levels.
+ *   SP_ENGINE_AUTO    SP_ENGINE_BLOCKS on road-like graphs (no vertex with
+ *                     more than 8 neighbours in or out), else SP_ENGINE_BITMAP.
+ * Both compute the same per-source quantities; the bitmap engine regroups the
+ * reverse sum (sigma(v) times the sum of (1 + delta(w)) / sigma(w)), the
+ * blocks engine sums (sigma(v) / sigma(w)) (1 + delta(w)) as written, so
+ * their BC differs by rounding only. */
+#define SP_ENGINE_AUTO 0
+#define SP_ENGINE_BITMAP 1
+#define SP_ENGINE_BLOCKS 2
 
 /* Counters of the last sp_bc / sp_bc_batch call on the calling thread. */
 typedef struct sp_stats {
@@ -179,6 +198,7 @@ typedef struct sp_stats {
     double group_ms;         /* sp_bc_batch: host time spent in this call computing the
                                 graph's source-grouping keys (0 once cached; not part
                                 of device_ms) */
+    int32_t engine;          /* sp_bc_batch: SP_ENGINE_BITMAP or SP_ENGINE_BLOCKS (0 for sp_bc) */
 } sp_stats;
 
 /* Per-source path: one BFS pass per source, sources in list order.
@@ -249,10 +269,12 @@ sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes);
  * the fastest to *out.  The sample is up to 128 consecutive sources of
  * `sources` in the order sp_bc_batch would batch them (grouped, see above),
  * taken from the middle of that order, so candidates run the batches
- * production runs.  Search: coordinate descent from the built-in defaults
- * (width 64, block 512, alpha 15, beta 24, chunk_levels 8), one field at a
- * time: block {256, 128}, width {32, 48}, alpha {4, 60} and beta {8, 96}
- * (graphs with a vertex of degree > 8 only), chunk_levels {16, 32}.  Each
+ * production runs.  The engine is the graph's SP_ENGINE_AUTO choice (not
+ * searched).  Search: coordinate descent from the built-in defaults (width
+ * 64, block 512, alpha 15, beta 24, chunk_levels 8), one field at a time:
+ * block {256, 128}, width {32, 48}, alpha {4, 60} and beta {8, 96} (graphs
+ * with a vertex of degree > 8 only), chunk_levels {16, 32}; for the blocks
+ * engine from block 1024, width 64: block {512, 256}, width {32, 48}.  Each
  * candidate runs the sample once untimed, then twice timed (HIP events); its
  * score is the faster of the two, per source, and it replaces the running
  * best only when 2% faster.  The choice is kept on the graph (used whenever

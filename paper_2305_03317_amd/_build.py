@@ -23,7 +23,7 @@ GRAPH_LIB = os.path.join(HERE, "libspgraph.so")
 
 HIP_SOURCES = ["api.hip", "source_path.hip", "batch_path.hip", "server.hip", "profile.hip", "autotune.hip",
                "sssp_path.hip", "pr_path.hip",
-               "tc_path.hip", "noalloc.hip"]
+               "tc_path.hip", "noalloc.hip", "wg_path.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

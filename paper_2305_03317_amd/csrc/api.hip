@@ -216,11 +216,11 @@ int64_t initial_qcap(int32_t n, int32_t width) {
     return V * std::min(width, 16) + kSlots;
 }
 
-sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out) {
+sp_status acquire_batch_ws(sp_graph g, int32_t width, int32_t engine, BatchWorkspace **out) {
     {
         std::lock_guard<std::mutex> lk(g->mu);
         for (size_t i = 0; i < g->batch_pool.size(); ++i)
-            if (g->batch_pool[i]->width >= width) {
+            if (g->batch_pool[i]->width >= width && g->batch_pool[i]->engine == engine) {
                 *out = g->batch_pool[i];
                 g->batch_pool.erase(g->batch_pool.begin() + i);
                 return SP_OK;
@@ -228,7 +228,7 @@ sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out) {
     }
     auto *ws = new (std::nothrow) BatchWorkspace;
     if (!ws) return SP_ERR_OUT_OF_MEMORY;
-    sp_status st = batch_ws_create(g, initial_qcap(g->n, width), width, *ws);
+    sp_status st = batch_ws_create(g, initial_qcap(g->n, width), width, engine, *ws);
     if (st < 0) {
         batch_ws_destroy(*ws);
         delete ws;
@@ -280,6 +280,10 @@ BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *widt
     o.alpha = pick_d(cfg ? cfg->alpha : 0, t.alpha, kDefaultAlpha);
     o.beta = pick_d(cfg ? cfg->beta : 0, t.beta, kDefaultBeta);
     o.chunk_levels = pick_i(cfg ? cfg->chunk_levels : 0, t.chunk_levels, kDefaultChunkLevels);
+    o.engine = pick_i(cfg ? cfg->engine : 0, t.engine, auto_engine(g));
+    if (o.engine == SP_ENGINE_BLOCKS)  // its own default workgroup size
+        o.block = pick_i(cfg ? cfg->block_size : 0, t.engine == SP_ENGINE_BLOCKS ? t.block_size : 0,
+                         kDefaultBlocksEngineBlock);
     return o;
 }
 
@@ -290,8 +294,8 @@ sp_status check_batch_cfg(const sp_batch_config *cfg) {
         return SP_ERR_INVALID_ARGUMENT;
     }
     const int b = cfg->block_size;
-    if (b != 0 && b != 128 && b != 256 && b != 512) {
-        set_error("block_size %d not one of 128, 256, 512", b);
+    if (b != 0 && b != 128 && b != 256 && b != 512 && !(b == 1024 && cfg->engine == SP_ENGINE_BLOCKS)) {
+        set_error("block_size %d not one of 128, 256, 512 (1024: with engine SP_ENGINE_BLOCKS only)", b);
         return SP_ERR_INVALID_ARGUMENT;
     }
     if (cfg->alpha < 0 || cfg->beta < 0 || !std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta)) {
@@ -300,6 +304,10 @@ sp_status check_batch_cfg(const sp_batch_config *cfg) {
     }
     if (cfg->chunk_levels < -65536 || cfg->chunk_levels > 65536) {
         set_error("chunk_levels %d outside -65536..65536", cfg->chunk_levels);
+        return SP_ERR_INVALID_ARGUMENT;
+    }
+    if (cfg->engine != SP_ENGINE_AUTO && cfg->engine != SP_ENGINE_BITMAP && cfg->engine != SP_ENGINE_BLOCKS) {
+        set_error("engine %d not one of SP_ENGINE_AUTO, _BITMAP, _BLOCKS", cfg->engine);
         return SP_ERR_INVALID_ARGUMENT;
     }
     for (int r : cfg->reserved)
@@ -513,7 +521,7 @@ sp_status bc_per_source(sp_graph g, SourceWorkspace &ws, const int32_t *sources,
         if (g->tuned.valid) tcfg = g->tuned.cfg;
     }
     SourceRunOpts o;
-    if (tcfg.block_size) o.block = tcfg.block_size;
+    if (tcfg.block_size && tcfg.block_size <= 512) o.block = tcfg.block_size;  // (1024: blocks engine only)
     const bool timed = ws.ev0 && ws.ev1;
     if (timed) SP_HIP(hipEventRecord(ws.ev0, st));
     SP_TRY(launch_fill_f64(out_bc, g->n, 0.0, st));
@@ -955,7 +963,8 @@ sp_status sp_bc_batch(sp_graph g, const int32_t *sources, int32_t n_sources, dou
         return SP_OK;
     }
     BatchWorkspace *ws = nullptr;
-    SP_TRY(acquire_batch_ws(g, width, &ws));
+    stats.engine = o.engine;
+    SP_TRY(acquire_batch_ws(g, width, o.engine, &ws));
     struct Rel {
         sp_graph g;
         BatchWorkspace *ws;
@@ -1054,7 +1063,7 @@ sp_status sp_batch_levels(sp_graph g, const int32_t *sources, int32_t n_sources,
     int32_t width = 64;
     const BatchRunOpts o = resolve_batch(g, cfg, &width);
     BatchWorkspace *ws = nullptr;
-    SP_TRY(acquire_batch_ws(g, n_sources, &ws));
+    SP_TRY(acquire_batch_ws(g, n_sources, o.engine, &ws));
     struct Rel {
         sp_graph g;
         BatchWorkspace *ws;
@@ -1076,7 +1085,9 @@ sp_status sp_bc_workspace_bytes(sp_graph g, int32_t batch_width, size_t *bytes) 
         set_error("sp_bc_workspace_bytes: bad arguments");
         return SP_ERR_INVALID_ARGUMENT;
     }
-    *bytes = batch_ws_bytes(g, initial_qcap(g->n, batch_width), batch_width);
+    int32_t width = 0;
+    const BatchRunOpts o = resolve_batch(g, nullptr, &width);
+    *bytes = batch_ws_bytes(g, initial_qcap(g->n, batch_width), batch_width, o.engine);
     return SP_OK;
 }
 

@@ -40,7 +40,8 @@ const char *cache_path() {
     return (p && *p) ? p : nullptr;
 }
 
-// Lines "fingerprint width block alpha beta chunk_levels"; later lines win.
+// Lines "fingerprint width block alpha beta chunk_levels [engine]"; later
+// lines win.
 void read_cache_file_locked() {
     if (g_cache_file_read) return;
     g_cache_file_read = true;
@@ -52,8 +53,8 @@ void read_cache_file_locked() {
     while (std::fgets(line, sizeof line, f)) {
         unsigned long long fp = 0;
         sp_batch_config c{};
-        if (std::sscanf(line, "%llx %d %d %lf %lf %d", &fp, &c.batch_width, &c.block_size, &c.alpha,
-                        &c.beta, &c.chunk_levels) == 6 &&
+        if (std::sscanf(line, "%llx %d %d %lf %lf %d %d", &fp, &c.batch_width, &c.block_size, &c.alpha,
+                        &c.beta, &c.chunk_levels, &c.engine) >= 6 &&
             check_batch_cfg(&c) == SP_OK)
             g_cache[(uint64_t)fp] = c;
     }
@@ -117,12 +118,13 @@ sp_status time_config(sp_graph g, BatchWorkspace &ws, const int32_t *src, int32_
     return SP_OK;
 }
 
-BatchRunOpts opts_of(const sp_batch_config &c) {
+BatchRunOpts opts_of(sp_graph g, const sp_batch_config &c) {
     BatchRunOpts o;
     o.block = c.block_size;
     o.alpha = c.alpha;
     o.beta = c.beta;
     o.chunk_levels = c.chunk_levels;
+    o.engine = c.engine ? c.engine : sp::auto_engine(g);
     return o;
 }
 
@@ -154,8 +156,8 @@ void tune_cache_store(uint64_t fp, const sp_batch_config &c) {
     g_cache[fp] = c;
     if (const char *path = cache_path()) {
         if (FILE *f = std::fopen(path, "a")) {
-            std::fprintf(f, "%016" PRIx64 " %d %d %.17g %.17g %d\n", fp, c.batch_width, c.block_size,
-                         c.alpha, c.beta, c.chunk_levels);
+            std::fprintf(f, "%016" PRIx64 " %d %d %.17g %.17g %d %d\n", fp, c.batch_width, c.block_size,
+                         c.alpha, c.beta, c.chunk_levels, c.engine);
             std::fclose(f);
         }
     }
@@ -209,7 +211,8 @@ extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_s
         rep.sample_sources = n;
 
         BatchWorkspace *ws = nullptr;
-        SP_TRY(acquire_batch_ws(g, kSlots, &ws));
+        const int32_t engine = auto_engine(g);  // the engine is not searched
+        SP_TRY(acquire_batch_ws(g, kSlots, engine, &ws));
         struct Rel {
             sp_graph g;
             BatchWorkspace *ws;
@@ -217,8 +220,9 @@ extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_s
         } rel{g, ws};
 
         sp_batch_config best{};
+        best.engine = engine;
         best.batch_width = kDefaultWidth;
-        best.block_size = kDefaultBlock;
+        best.block_size = engine == SP_ENGINE_BLOCKS ? kDefaultBlocksEngineBlock : kDefaultBlock;
         best.alpha = kDefaultAlpha;
         best.beta = kDefaultBeta;
         best.chunk_levels = kDefaultChunkLevels;
@@ -230,14 +234,14 @@ extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_s
             k.accepted = accepted ? 1 : 0;
         };
         double best_ms = 0;
-        SP_TRY(time_config(g, *ws, sample.data(), n, best.batch_width, opts_of(best), st, &best_ms));
+        SP_TRY(time_config(g, *ws, sample.data(), n, best.batch_width, opts_of(g, best), st, &best_ms));
         record(best, best_ms, true);
         auto try_field = [&](auto setter, const std::vector<double> &values) -> sp_status {
             for (double v : values) {
                 sp_batch_config c = best;
                 setter(c, v);
                 double ms = 0;
-                SP_TRY(time_config(g, *ws, sample.data(), n, c.batch_width, opts_of(c), st, &ms));
+                SP_TRY(time_config(g, *ws, sample.data(), n, c.batch_width, opts_of(g, c), st, &ms));
                 const bool win = ms < best_ms * kMargin;
                 record(c, ms, win);
                 if (win) {
@@ -247,13 +251,18 @@ extern "C" sp_status sp_autotune(sp_graph g, const int32_t *sources, int32_t n_s
             }
             return SP_OK;
         };
-        SP_TRY(try_field([](sp_batch_config &c, double v) { c.block_size = (int32_t)v; }, {256, 128}));
+        if (engine == SP_ENGINE_BLOCKS)
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.block_size = (int32_t)v; }, {512, 256}));
+        else
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.block_size = (int32_t)v; }, {256, 128}));
         SP_TRY(try_field([](sp_batch_config &c, double v) { c.batch_width = (int32_t)v; }, {32, 48}));
-        if (g->max_degree > 8) {  // bottom-up levels never run on sparser graphs
-            SP_TRY(try_field([](sp_batch_config &c, double v) { c.alpha = v; }, {4, 60}));
-            SP_TRY(try_field([](sp_batch_config &c, double v) { c.beta = v; }, {8, 96}));
+        if (engine == SP_ENGINE_BITMAP) {  // the other fields do not apply to the blocks engine
+            if (g->max_degree > 8) {  // bottom-up levels never run on sparser graphs
+                SP_TRY(try_field([](sp_batch_config &c, double v) { c.alpha = v; }, {4, 60}));
+                SP_TRY(try_field([](sp_batch_config &c, double v) { c.beta = v; }, {8, 96}));
+            }
+            SP_TRY(try_field([](sp_batch_config &c, double v) { c.chunk_levels = (int32_t)v; }, {16, 32}));
         }
-        SP_TRY(try_field([](sp_batch_config &c, double v) { c.chunk_levels = (int32_t)v; }, {16, 32}));
         {
             std::lock_guard<std::mutex> lk(g->mu);
             g->tuned.valid = true;

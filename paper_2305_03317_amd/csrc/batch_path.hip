@@ -45,10 +45,6 @@
 
 namespace sp {
 
-struct SlotTable {
-    double *out[kSlots];
-};
-
 constexpr int kSparseSlots = 2;
 constexpr int32_t kSparseDeg = 64;
 constexpr uint32_t kNoTag = 0xFFFFFFFFu;
@@ -1285,8 +1281,14 @@ static int64_t partial_rows(sp_graph g) {
 
 static int64_t in_hub_capacity(sp_graph g) { return g->directed ? (int64_t)g->n_hubs_in + 1 : 0; }
 
-size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
+int32_t auto_engine(sp_graph g) {
+    return g->n_hubs == 0 && g->n_hubs_in == 0 && g->max_degree <= kExpandDeg ? SP_ENGINE_BLOCKS
+                                                                                : SP_ENGINE_BITMAP;
+}
+
+size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width, int32_t engine) {
     const size_t V = (size_t)std::max(g->n, 1);
+    if (engine == SP_ENGINE_BLOCKS) return wg_ws_bytes(g, width) + kSlots * 4 + sizeof(LevelCtl);
     return V * (8 + 8 + 16 + 16) + V * kSlots * 8 + (size_t)value_capacity(g, width) * 8 +
            (size_t)qcap * 16 + (V + 2) * 12 + kSlots * 4 +
            (size_t)hub_capacity(g) * sizeof(HubEntry) + ((size_t)g->n_hubs + 1) * 4 +
@@ -1295,10 +1297,19 @@ size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width) {
            (size_t)partial_rows(g) * kSlots * 8 + sizeof(LevelCtl);
 }
 
-sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws) {
+sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, int32_t engine, BatchWorkspace &ws) {
     ws.device = g->device;
     ws.n = g->n;
     ws.width = width;
+    ws.engine = engine;
+    if (engine == SP_ENGINE_BLOCKS) {  // per-slot arrays only
+        ws.qcap = 0;
+        SP_TRY(wg_ws_alloc(g, width, ws));
+        SP_TRY(dev_alloc((void **)&ws.slot_src, kSlots * 4));
+        SP_HIP(hipHostMalloc((void **)&ws.staging, kSlots * (4 + 8 + 4), hipHostMallocDefault));
+        ws.bytes = batch_ws_bytes(g, 0, width, engine);
+        return SP_OK;
+    }
     const size_t V = (size_t)std::max(g->n, 1);
     ws.qcap = qcap;
     ws.vcap = value_capacity(g, width);
@@ -1335,7 +1346,7 @@ sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspac
     SP_HIP(hipHostMalloc((void **)&ws.staging, kSlots * (4 + 8 + 4), hipHostMallocDefault));
     SP_HIP(hipEventCreate(&ws.ev0));
     SP_HIP(hipEventCreate(&ws.ev1));
-    ws.bytes = batch_ws_bytes(g, qcap, width);
+    ws.bytes = batch_ws_bytes(g, qcap, width, engine);
     return SP_OK;
 }
 
@@ -1346,6 +1357,7 @@ void batch_ws_destroy(BatchWorkspace &ws) {
     }
     if (ws.cap_stream) (void)hipStreamDestroy(ws.cap_stream);
     ws.cap_stream = nullptr;
+    wg_ws_free(ws);
     dev_free(ws.seen);
     dev_free(ws.nxt);
     dev_free(ws.front[0]);
@@ -1384,7 +1396,7 @@ static sp_status grow_queue(sp_graph g, BatchWorkspace &ws, int64_t qcap) {
     SP_TRY(dev_alloc((void **)&ws.qmask, (size_t)qcap * 8));
     SP_TRY(dev_alloc((void **)&ws.qvb, (size_t)qcap * 4));
     ws.qcap = qcap;
-    ws.bytes = batch_ws_bytes(g, qcap, ws.width);
+    ws.bytes = batch_ws_bytes(g, qcap, ws.width, ws.engine);
     return SP_OK;
 }
 
@@ -1405,8 +1417,13 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
         const int64_t l = first + k;  // level this group expands
         uint4 *fcur = ws.front[l & 1], *fnxt = ws.front[(l + 1) & 1];
         if (!hubs && !may_pull && g->max_degree <= kExpandDeg && !g->directed) {  // road-like: one kernel per level
+            // A road-like level holds a few thousand entries, and the kernel
+            // walks them grid-stride: one block per CU covers any frontier
+            // without dispatching the thousands of idle blocks a grid sized
+            // for V would start (and retire) every level.
             ProfScope ps(P_MS_EXPAND, s);
-            hipLaunchKernelGGL(k_ms_expand<BS>, dim3(grid), dim3(BS), 0, s, ws.ctl, g->row_ptr,
+            hipLaunchKernelGGL(k_ms_expand<BS>, dim3(std::min(grid, device_cu_count())), dim3(BS), 0, s,
+                               ws.ctl, g->row_ptr,
                                g->col_idx, ws.queue, ws.qmask, ws.qvb, ws.seen, (int32_t *)ws.nxt,
                                (const uint4 *)fcur, fnxt, ws.val, (long long)ws.vcap,
                                (long long)ws.qcap, ws.level_off, ws.hub_off, ws.hub_lvl_chunks,
@@ -1694,6 +1711,11 @@ sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t
         set_error("batch of %d sources (1..%d allowed)", nslots, ws.width);
         return SP_ERR_INVALID_ARGUMENT;
     }
+    if (o.engine != ws.engine) {
+        set_error("internal: workspace built for engine %d, pass asks for %d", ws.engine, o.engine);
+        return SP_ERR_DEVICE;
+    }
+    if (ws.engine == SP_ENGINE_BLOCKS) return wg_run(g, ws, srcs, nslots, bc_of_slot, o, s, res, ex);
     if (ex) {
         const int64_t total = (int64_t)nslots * g->n;
         if (ex->dist) SP_TRY(launch_fill_i32(ex->dist, total, -1, s));

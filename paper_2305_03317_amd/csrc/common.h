@@ -234,7 +234,7 @@ struct LevelCtl {
 enum ProfKind : int {
     P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
     P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_EXPAND, P_MS_DELTA, P_MS_DELTA_HUB,
-    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL, P_PR_PULL, P_PR_HUB, P_TC_COUNT,
+    P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL, P_PR_PULL, P_PR_HUB, P_TC_COUNT, P_WG_BC,
     P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
@@ -294,6 +294,7 @@ constexpr int kDefaultBlock = 512;
 constexpr double kDefaultAlpha = 15.0;
 constexpr double kDefaultBeta = 24.0;
 constexpr int kDefaultChunkLevels = 8;
+constexpr int kDefaultBlocksEngineBlock = 1024;  // workgroup size of the blocks engine
 
 struct SourceRunOpts {
     double alpha = kDefaultAlpha, beta = kDefaultBeta;
@@ -323,6 +324,20 @@ sp_status check_bc_args(sp_graph g, const int32_t *sources, int32_t n_sources, c
 // ---------------------------------------------------------------------------
 constexpr int kSlots = 64;  // bits per source bitmap; also the slot stride of sigma/delta rows
 
+// Output BC array of each slot of a pass (null: the slot adds to no output).
+struct SlotTable {
+    double *out[kSlots];
+};
+
+// Per-slot summary written by the workgroup engine.
+struct WgSlotResult {
+    int32_t levels;   // levels including level 0
+    int32_t reached;  // vertices reached
+    double sigma_max;
+    int32_t flagged;  // some sigma > 1e300 or not finite
+    int32_t pad;
+};
+
 struct CapturedChunk {
     hipGraphExec_t exec = nullptr;
     std::array<long long, 12> key{};
@@ -330,6 +345,11 @@ struct CapturedChunk {
 
 struct BatchWorkspace {
     int device = -1;
+    int32_t engine = SP_ENGINE_BITMAP;   // SP_ENGINE_BITMAP or SP_ENGINE_BLOCKS
+    // Workgroup engine (wg_path.hip), source-major [slot][V] per slot:
+    int32_t *wg_dist = nullptr, *wg_queue = nullptr, *wg_loff = nullptr;  // loff: [slot][V + 2]
+    double *wg_sigma = nullptr, *wg_delta = nullptr;
+    WgSlotResult *wg_res = nullptr, *wg_res_host = nullptr;
     int32_t n = 0;
     unsigned long long *seen = nullptr;  // V: slots that reached v at any level so far
     unsigned long long *nxt = nullptr;   // V: slots discovering v at the level being built
@@ -371,14 +391,21 @@ struct BatchWorkspace {
     hipStream_t cap_stream = nullptr;
     CapturedChunk fwd_short, fwd_long, bwd;
 };
-size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width);
-sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, BatchWorkspace &ws);
+size_t batch_ws_bytes(sp_graph g, int64_t qcap, int32_t width, int32_t engine);
+sp_status batch_ws_create(sp_graph g, int64_t qcap, int32_t width, int32_t engine, BatchWorkspace &ws);
+// The engine SP_ENGINE_AUTO resolves to on this graph.
+int32_t auto_engine(sp_graph g);
+// Workgroup engine (wg_path.hip).
+size_t wg_ws_bytes(sp_graph g, int32_t width);
+sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws);
+void wg_ws_free(BatchWorkspace &ws);
 void batch_ws_destroy(BatchWorkspace &ws);
 
 struct BatchRunOpts {
     double alpha = kDefaultAlpha, beta = kDefaultBeta;
     int block = kDefaultBlock;
     int chunk_levels = kDefaultChunkLevels;
+    int32_t engine = SP_ENGINE_BITMAP;  // resolved: SP_ENGINE_BITMAP or SP_ENGINE_BLOCKS
 };
 
 // Per-slot results of a pass, source-major ([slot * V + v]); any may be null.
@@ -404,6 +431,9 @@ struct BatchResult {
 sp_status batch_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
                     double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s,
                     BatchResult *res, const BatchExtract *ex = nullptr);
+sp_status wg_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
+                 double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s, BatchResult *res,
+                 const BatchExtract *ex);
 
 
 // ---------------------------------------------------------------------------
@@ -553,7 +583,7 @@ sp_status ensure_pr_hubs(sp_graph g, hipStream_t s);
 
 // Workspace pools and configuration shared by the entry points and the server.
 int64_t initial_qcap(int32_t n, int32_t width);
-sp_status acquire_batch_ws(sp_graph g, int32_t width, BatchWorkspace **out);
+sp_status acquire_batch_ws(sp_graph g, int32_t width, int32_t engine, BatchWorkspace **out);
 void release_batch_ws(sp_graph g, BatchWorkspace *ws);
 BatchRunOpts resolve_batch(sp_graph g, const sp_batch_config *cfg, int32_t *width);
 

@@ -148,7 +148,7 @@ static void worker_main(sp_server_s *srv) {
             gs.idle.pop_back();
             srv->held++;
         } else {
-            const size_t need = batch_ws_bytes(g, initial_qcap(g->n, kSlots), kSlots);
+            const size_t need = batch_ws_bytes(g, initial_qcap(g->n, kSlots), kSlots, o.engine);
             if (!admit(srv, need, gi)) {
                 // Memory is held by other workers: wait for one to return it.
                 // With none held every workspace is idle and freeable, so
@@ -173,7 +173,7 @@ static void worker_main(sp_server_s *srv) {
             srv->stats.peak_admitted_bytes = std::max(srv->stats.peak_admitted_bytes, srv->admitted);
             lk.unlock();
             ws = new (std::nothrow) BatchWorkspace;
-            sp_status st = ws ? batch_ws_create(g, initial_qcap(g->n, kSlots), kSlots, *ws)
+            sp_status st = ws ? batch_ws_create(g, initial_qcap(g->n, kSlots), kSlots, o.engine, *ws)
                               : SP_ERR_OUT_OF_MEMORY;
             lk.lock();
             if (st < 0) {
@@ -249,8 +249,8 @@ static void worker_main(sp_server_s *srv) {
         lk.lock();
         srv->stats.in_flight--;
         srv->held--;
-        if (ws->bytes != batch_ws_bytes(g, ws->qcap, ws->width)) {  // the queue grew
-            const size_t now = batch_ws_bytes(g, ws->qcap, ws->width);
+        if (ws->bytes != batch_ws_bytes(g, ws->qcap, ws->width, ws->engine)) {  // the queue grew
+            const size_t now = batch_ws_bytes(g, ws->qcap, ws->width, ws->engine);
             srv->admitted = srv->admitted - ws->bytes + now;
             ws->bytes = now;
             srv->stats.peak_admitted_bytes = std::max(srv->stats.peak_admitted_bytes, srv->admitted);
@@ -370,7 +370,9 @@ sp_status sp_stream_submit(sp_server srv, int32_t graph_id, const int32_t *sourc
             set_error("server is shutting down");
             return SP_ERR_REJECTED;
         }
-        const size_t need = batch_ws_bytes(g, initial_qcap(g->n, kSlots), kSlots);
+        int32_t width = 0;
+        const BatchRunOpts o = resolve_batch(g, nullptr, &width);
+        const size_t need = batch_ws_bytes(g, initial_qcap(g->n, kSlots), kSlots, o.engine);
         if (need > srv->cfg.memory_budget) {
             srv->stats.rejected++;
             set_error("one pass on this graph needs %zu bytes, budget is %zu", need,

@@ -1,0 +1,412 @@
+// Batched BC with one workgroup per source ("workgroup engine"), for graphs
+// of many short levels (road-like: no vertex of degree above kExpandDeg).
+//
+// The arithmetic is Brandes' per source (paper Appendix, Fig. "BC computation
+// in StarPlat"; DAG semantics of Section 2.3.2), as on the per-source path:
+//   sigma(w) = sum over parents u (incoming row, CSR order) of sigma(u),
+//   delta(v) = sum over children w (outgoing row, CSR order) of
+//              (sigma(v) / sigma(w)) * (1 + delta(w)).
+// What differs is the schedule.  On a road-like graph a source's BFS has
+// thousands of levels of a few hundred vertices each; the bitmap engine runs
+// the batch's sources in lockstep, one kernel per level for the whole batch,
+// and each level pays the kernel's chain of dependent memory round trips and
+// its grid-wide close.  Here each source's whole pass (forward levels, then
+// reverse levels) runs inside one workgroup, the level barrier is the
+// workgroup barrier, and the new frontier is appended with an LDS counter:
+// the batch's sources advance independently, each on its own CU.
+// (One thread block per source is the coarse-grained schedule of McLaughlin
+// and Bader, "Scalable and high performance betweenness centrality on the
+// GPU", SC 2014.)
+//
+// Layout, per slot s (source-major): dist[s*V + v], sigma[s*V + v],
+// delta[s*V + v], the BFS-order queue queue[s*V + i], and the level offsets
+// loff[s*(V+2) + l].  dist is filled with -1 before each pass; every other
+// value is written before it is read.  BC: for each vertex, the slots'
+// delta in ascending slot order, skipping unreached vertices and the
+// vertex's own source (dist <= 0).
+//
+// Only the slot's own workgroup touches its arrays during the pass, so the
+// claim on dist is a workgroup-scope compare-and-swap and the reads of
+// levels another wave may have claimed are workgroup-scope atomic loads
+// (coherent within the CU, and served by the XCD's L2 rather than the
+// memory-side point device-scope atomics need).  Everything else is written
+// with plain stores by waves of the same workgroup and read after a barrier.
+//
+// Memory-level parallelism: a thread takes kEntries queue entries at once
+// and walks their rows kRowStep entries at a time; for all of them the
+// column ids, then the neighbours' levels, then their values (or claims) are
+// each issued together, so one step of a level costs a few dependent round
+// trips for kEntries x kRowStep adjacency entries.  Sums still run in CSR
+// order per vertex.
+#include "common.h"
+#include "devutil.h"
+
+namespace sp {
+
+constexpr int kRowStep = 4;   // row entries per step (road-like rows hold at most 4)
+constexpr int kEntries = 4;   // queue entries a thread works on at once
+
+// Rows of the (up to) kEntries queue entries i0, i0 + BS, ... below `end`:
+// [b[u], e[u]) in the rows `rows`; returns the longest row's length.
+template <int BS>
+__device__ __forceinline__ int32_t rows_of_bs(const int32_t *queue, int32_t i0, int32_t end,
+                                              const int32_t *__restrict__ rows, int32_t *b, int32_t *e) {
+    int32_t v[kEntries];
+#pragma unroll
+    for (int u = 0; u < kEntries; ++u) v[u] = i0 + u * BS < end ? queue[i0 + u * BS] : -1;
+    int32_t len = 0;
+#pragma unroll
+    for (int u = 0; u < kEntries; ++u) {
+        b[u] = v[u] >= 0 ? rows[v[u]] : 0;
+        e[u] = v[u] >= 0 ? rows[v[u] + 1] : 0;
+        len = max(len, e[u] - b[u]);
+    }
+    return len;
+}
+
+__device__ __forceinline__ int32_t ld_level(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// dist -1 -> lvl; returns the value found (-1 when this call claimed it).
+__device__ __forceinline__ int32_t claim_level(int32_t *p, int32_t lvl) {
+    int32_t expected = -1;
+    __hip_atomic_compare_exchange_strong(p, &expected, lvl, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expected;
+}
+
+__global__ void k_wg_fill(int32_t *dist, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dist[i] = -1;
+}
+
+// One source per workgroup: blockIdx.x = slot.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                              const int32_t *__restrict__ rpi,
+                                              const int32_t *__restrict__ cii,
+                                              const int32_t *__restrict__ slot_src, int32_t n,
+                                              int32_t *dist_all, double *sigma_all, double *delta_all,
+                                              int32_t *queue_all, int32_t *loff_all, WgSlotResult *res,
+                                              unsigned long long *prof) {
+    const int32_t slot = blockIdx.x;
+    const int64_t base = (int64_t)slot * n;
+    int32_t *dist = dist_all + base;
+    double *sigma = sigma_all + base;
+    double *delta = delta_all + base;
+    int32_t *queue = queue_all + base;
+    int32_t *loff = loff_all + (int64_t)slot * ((int64_t)n + 2);
+    const int32_t src = slot_src[slot];
+    __shared__ int32_t s_tail, s_flag;
+    __shared__ double s_max[BS / kWave];
+    __shared__ unsigned long long s_red[1];
+    if (threadIdx.x == 0) {
+        dist[src] = 0;
+        sigma[src] = 1.0;
+        queue[0] = src;
+        loff[0] = 0;
+        loff[1] = 1;
+        s_tail = 1;
+        s_flag = 0;
+    }
+    __syncthreads();
+    int32_t lo = 0, hi = 1, level = 0;
+    double my_max = 1.0;
+    unsigned long long my_edges = 0, my_pairs = 0;
+    for (;;) {
+        // Discovery of level + 1 from the frontier [lo, hi), outgoing rows;
+        // the claim (dist -1 -> level + 1) decides who appends the vertex.
+        for (int32_t i0 = lo + (int32_t)threadIdx.x; i0 < hi; i0 += BS * kEntries) {
+            int32_t b[kEntries], e[kEntries];
+            int32_t len = rows_of_bs<BS>(queue, i0, hi, rp, b, e);
+            for (int32_t k0 = 0; k0 < len; k0 += kRowStep) {
+                int32_t w[kEntries][kRowStep], d[kEntries][kRowStep], old[kEntries][kRowStep];
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) w[u][t] = b[u] + k0 + t < e[u] ? ci[b[u] + k0 + t] : -1;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) d[u][t] = w[u][t] >= 0 ? ld_level(&dist[w[u][t]]) : 0;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t)
+                        old[u][t] = d[u][t] < 0 ? claim_level(&dist[w[u][t]], level + 1) : 0;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t)
+                        if (d[u][t] < 0 && old[u][t] == -1) queue[atomicAdd(&s_tail, 1)] = w[u][t];  // LDS
+            }
+#pragma unroll
+            for (int u = 0; u < kEntries; ++u) my_edges += (unsigned long long)(e[u] - b[u]);
+        }
+        __syncthreads();
+        const int32_t tail = s_tail;
+        if (tail == hi) break;  // block-uniform: every thread read the same tail
+        // Path counts of the new vertices [hi, tail): parents over incoming
+        // rows, added in row order.
+        for (int32_t j0 = hi + (int32_t)threadIdx.x; j0 < tail; j0 += BS * kEntries) {
+            int32_t b[kEntries], e[kEntries];
+            const int32_t len = rows_of_bs<BS>(queue, j0, tail, rpi, b, e);
+            double acc[kEntries] = {};
+            for (int32_t k0 = 0; k0 < len; k0 += kRowStep) {
+                int32_t p[kEntries][kRowStep];
+                bool par[kEntries][kRowStep];
+                double x[kEntries][kRowStep];
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) p[u][t] = b[u] + k0 + t < e[u] ? cii[b[u] + k0 + t] : -1;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) par[u][t] = p[u][t] >= 0 && ld_level(&dist[p[u][t]]) == level;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) x[u][t] = par[u][t] ? sigma[p[u][t]] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t)
+                        if (par[u][t]) {
+                            acc[u] += x[u][t];
+                            ++my_pairs;
+                        }
+            }
+#pragma unroll
+            for (int u = 0; u < kEntries; ++u) {
+                const int32_t j = j0 + u * BS;
+                if (j < tail) {
+                    sigma[queue[j]] = acc[u];
+                    my_max = fmax(my_max, acc[u]);
+                    if (sigma_is_large(acc[u])) s_flag = 1;
+                }
+            }
+        }
+        if (threadIdx.x == 0) loff[level + 2] = tail;
+        __syncthreads();
+        lo = hi;
+        hi = tail;
+        ++level;
+    }
+    // `level` is the deepest level; reverse sweep from it up to level 1
+    // (the deepest has no children: its delta is 0).  Children over outgoing
+    // rows, added in row order.
+    for (int32_t l = level; l >= 1; --l) {
+        const int32_t a = loff[l], z = loff[l + 1];
+        for (int32_t j0 = a + (int32_t)threadIdx.x; j0 < z; j0 += BS * kEntries) {
+            int32_t b[kEntries], e[kEntries], v[kEntries];
+            double sv[kEntries], acc[kEntries] = {};
+#pragma unroll
+            for (int u = 0; u < kEntries; ++u) v[u] = j0 + u * BS < z ? queue[j0 + u * BS] : -1;
+            int32_t len = 0;
+#pragma unroll
+            for (int u = 0; u < kEntries; ++u) {
+                b[u] = v[u] >= 0 ? rp[v[u]] : 0;
+                e[u] = v[u] >= 0 ? rp[v[u] + 1] : 0;
+                sv[u] = v[u] >= 0 ? sigma[v[u]] : 0.0;
+                len = max(len, e[u] - b[u]);
+            }
+            for (int32_t k0 = 0; k0 < len; k0 += kRowStep) {
+                int32_t w[kEntries][kRowStep];
+                bool ch[kEntries][kRowStep];
+                double sw[kEntries][kRowStep], dw[kEntries][kRowStep];
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) w[u][t] = b[u] + k0 + t < e[u] ? ci[b[u] + k0 + t] : -1;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) ch[u][t] = w[u][t] >= 0 && ld_level(&dist[w[u][t]]) == l + 1;
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t) {
+                        sw[u][t] = ch[u][t] ? sigma[w[u][t]] : 1.0;
+                        dw[u][t] = ch[u][t] ? delta[w[u][t]] : 0.0;
+                    }
+#pragma unroll
+                for (int u = 0; u < kEntries; ++u)
+#pragma unroll
+                    for (int t = 0; t < kRowStep; ++t)
+                        if (ch[u][t]) {
+                            acc[u] += (sv[u] / sw[u][t]) * (1.0 + dw[u][t]);
+                            ++my_pairs;
+                        }
+            }
+#pragma unroll
+            for (int u = 0; u < kEntries; ++u)
+                if (v[u] >= 0) delta[v[u]] = acc[u];
+        }
+        __syncthreads();
+    }
+    my_max = wave_max_f64(my_max);
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = my_max;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < BS / kWave; ++w) m = fmax(m, s_max[w]);
+        res[slot] = WgSlotResult{level + 1, hi, m, s_flag};
+    }
+    if (prof) {
+        __syncthreads();
+        block_add_u64<BS>(threadIdx.x == 0 ? (unsigned long long)hi : 0ull, s_red, prof + 0);
+        __syncthreads();
+        block_add_u64<BS>(my_edges, s_red, prof + 1);
+        __syncthreads();
+        block_add_u64<BS>(my_pairs, s_red, prof + 2);
+    }
+}
+
+// BC[v] += delta of v for every slot that reached v from another vertex, in
+// ascending slot order; consecutive slots with the same output array are
+// summed in a register.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, const int32_t *__restrict__ dist,
+                                                  const double *__restrict__ delta, SlotTable tbl,
+                                                  unsigned long long *prof) {
+    __shared__ unsigned long long s_red[1];
+    unsigned long long my_items = 0;
+    for (int32_t v = blockIdx.x * BS + threadIdx.x; v < n; v += gridDim.x * BS) {
+        double *cur = nullptr;
+        double acc = 0.0;
+        for (int32_t s = 0; s < nslots; ++s) {
+            double *out = tbl.out[s];
+            if (!out) continue;
+            if (out != cur) {
+                if (cur) cur[v] = acc;
+                cur = out;
+                acc = out[v];
+            }
+            const int64_t o = (int64_t)s * n + v;
+            if (dist[o] > 0) {
+                acc += delta[o];
+                ++my_items;
+            }
+        }
+        if (cur) cur[v] = acc;
+    }
+    if (prof) block_add_u64<BS>(my_items, s_red, prof + 3);
+}
+
+// Per-slot results into the caller's source-major arrays (sp_batch_levels):
+// dist as is, sigma of reached vertices, delta of vertices below the source.
+__global__ void k_wg_extract(int64_t count, const int32_t *__restrict__ dist, const double *__restrict__ sigma,
+                             const double *__restrict__ delta, int32_t *out_dist, double *out_sigma,
+                             double *out_delta) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const int32_t d = dist[i];
+        if (out_dist) out_dist[i] = d;
+        if (out_sigma) out_sigma[i] = d >= 0 ? sigma[i] : 0.0;
+        if (out_delta) out_delta[i] = d > 0 ? delta[i] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+size_t wg_ws_bytes(sp_graph g, int32_t width) {
+    const size_t V = (size_t)std::max(g->n, 1);
+    return (size_t)width * (V * (4 + 8 + 8 + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult);
+}
+
+sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
+    const size_t V = (size_t)std::max(g->n, 1), W = (size_t)width;
+    SP_TRY(dev_alloc((void **)&ws.wg_dist, W * V * 4));
+    SP_TRY(dev_alloc((void **)&ws.wg_sigma, W * V * 8));
+    SP_TRY(dev_alloc((void **)&ws.wg_delta, W * V * 8));
+    SP_TRY(dev_alloc((void **)&ws.wg_queue, W * V * 4));
+    SP_TRY(dev_alloc((void **)&ws.wg_loff, W * (V + 2) * 4));
+    SP_TRY(dev_alloc((void **)&ws.wg_res, W * sizeof(WgSlotResult)));
+    SP_HIP(hipHostMalloc((void **)&ws.wg_res_host, W * sizeof(WgSlotResult), hipHostMallocDefault));
+    return SP_OK;
+}
+
+void wg_ws_free(BatchWorkspace &ws) {
+    dev_free(ws.wg_dist);
+    dev_free(ws.wg_sigma);
+    dev_free(ws.wg_delta);
+    dev_free(ws.wg_queue);
+    dev_free(ws.wg_loff);
+    dev_free(ws.wg_res);
+    if (ws.wg_res_host) (void)hipHostFree(ws.wg_res_host);
+    ws.wg_dist = ws.wg_queue = ws.wg_loff = nullptr;
+    ws.wg_sigma = ws.wg_delta = nullptr;
+    ws.wg_res = ws.wg_res_host = nullptr;
+}
+
+template <int BS>
+static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
+                           double *const *bc_of_slot, hipStream_t s, BatchResult *res,
+                           const BatchExtract *ex) {
+    const int32_t n = g->n;
+    const int64_t count = (int64_t)nslots * n;
+    int32_t *h_src = (int32_t *)ws.staging;
+    for (int32_t i = 0; i < kSlots; ++i) h_src[i] = i < nslots ? srcs[i] : -1;
+    SP_HIP(hipMemcpyAsync(ws.slot_src, h_src, kSlots * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_wg_fill, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, ws.wg_dist, count);
+    {
+        ProfScope ps(P_WG_BC, s);
+        hipLaunchKernelGGL(k_wg_bc<BS>, dim3(nslots), dim3(BS), 0, s, (const int32_t *)g->row_ptr,
+                           (const int32_t *)g->col_idx, (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
+                           (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta, ws.wg_queue,
+                           ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
+    }
+    SP_HIP(hipGetLastError());
+    if (ex)
+        hipLaunchKernelGGL(k_wg_extract, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, count,
+                           (const int32_t *)ws.wg_dist, (const double *)ws.wg_sigma,
+                           (const double *)ws.wg_delta, ex->dist, ex->sigma, ex->delta);
+    SlotTable tbl{};
+    bool any_out = false;
+    for (int32_t i = 0; i < kSlots; ++i) {
+        tbl.out[i] = (bc_of_slot && i < nslots) ? bc_of_slot[i] : nullptr;
+        any_out |= tbl.out[i] != nullptr;
+    }
+    if (any_out) {
+        ProfScope ps(P_MS_BC, s);
+        hipLaunchKernelGGL(k_wg_bc_sum<BS>, dim3(grid_for(n, BS, device_cu_count() * 8)), dim3(BS), 0, s, n,
+                           nslots, (const int32_t *)ws.wg_dist, (const double *)ws.wg_delta, tbl,
+                           prof_counters(P_MS_BC));
+    }
+    SP_HIP(hipGetLastError());
+    SP_HIP(hipMemcpyAsync(ws.wg_res_host, ws.wg_res, (size_t)nslots * sizeof(WgSlotResult),
+                          hipMemcpyDeviceToHost, s));
+    SP_HIP(hipStreamSynchronize(s));
+    if (res) {
+        *res = BatchResult{};
+        for (int32_t i = 0; i < nslots; ++i) {
+            const WgSlotResult &r = ws.wg_res_host[i];
+            res->levels = std::max(res->levels, r.levels);
+            res->reached += r.reached;
+            res->entries += r.reached;
+            res->sigma_max = std::max(res->sigma_max, r.sigma_max);
+            if (r.flagged) {
+                res->flagged++;
+                res->flagged_mask |= 1ull << i;
+            }
+            res->td += r.levels - 1;  // every level expanded top-down
+        }
+    }
+    return SP_OK;
+}
+
+sp_status wg_run(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, int32_t nslots,
+                 double *const *bc_of_slot, const BatchRunOpts &o, hipStream_t s, BatchResult *res,
+                 const BatchExtract *ex) {
+    switch (o.block) {
+        case 128: return wg_run_bs<128>(g, ws, srcs, nslots, bc_of_slot, s, res, ex);
+        case 256: return wg_run_bs<256>(g, ws, srcs, nslots, bc_of_slot, s, res, ex);
+        case 512: return wg_run_bs<512>(g, ws, srcs, nslots, bc_of_slot, s, res, ex);
+        default: return wg_run_bs<1024>(g, ws, srcs, nslots, bc_of_slot, s, res, ex);
+    }
+}
+
+}  // namespace sp

@@ -30,12 +30,16 @@ SP_VALIDATE = 2
 SP_SSSP_AUTO = 0
 SP_SSSP_PUSH = 1
 SP_SSSP_PULL = 2
+SP_ENGINE_AUTO = 0
+SP_ENGINE_BITMAP = 1
+SP_ENGINE_BLOCKS = 2
 
 
 class sp_batch_config(ctypes.Structure):
     _fields_ = [("batch_width", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("chunk_levels", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("chunk_levels", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class sp_stats(ctypes.Structure):
@@ -47,7 +51,7 @@ class sp_stats(ctypes.Structure):
                 ("batch_width", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("chunk_levels", ctypes.c_int32), ("graph_launches", ctypes.c_int32),
-                ("group_ms", ctypes.c_double)]
+                ("group_ms", ctypes.c_double), ("engine", ctypes.c_int32)]
 
 
 SP_TUNE_MAX_CANDIDATES = 16

@@ -127,3 +127,31 @@ def test_tuning_cache_file(sp, tmp_path):
     assert (st["batch_width"], st["block_size"], st["alpha"], st["beta"], st["chunk_levels"]) == \
         (17, 128, 7.0, 9.0, 6)
     assert res["from_cache"] == 1 and res["cfg"]["batch_width"] == 17
+
+
+def test_tuned_blocks_engine_on_a_road_graph(sp):
+    """On a road-like graph the automatic engine is one workgroup per source;
+    the tuner searches its workgroup size from 1024 and the width, and the
+    tuned configuration matches the oracle."""
+    rp, ci = graphs.road(64, 0.02, 43)
+    srcs = graphs.sources(rp, 150, 44)
+    sp.sp_tune_cache_clear()
+    g = sp.sp_graph_upload(rp, ci)
+    cfg = sp.sp_autotune(g, srcs)
+    rep = sp.sp_autotune_get_last_report()
+    print("tuned", json.dumps(cfg), flush=True)
+    assert cfg["engine"] == sp.SP_ENGINE_BLOCKS
+    assert rep["candidates"][0]["cfg"]["block_size"] == 1024
+    assert rep["n_candidates"] == 5  # start + block {512, 256} + width {32, 48}
+    assert cfg["block_size"] in (256, 512, 1024)
+    ref = oracle.bc(rp, ci, srcs)
+    b, st = sp.sp_bc_batch(g, srcs)
+    stats = sp.sp_get_last_stats()
+    assert st == sp.SP_OK and stats["engine"] == sp.SP_ENGINE_BLOCKS
+    assert stats["block_size"] == cfg["block_size"] and stats["batch_width"] == cfg["batch_width"]
+    assert_bc(b.cpu().numpy(), ref, "tuned blocks engine %s" % cfg)
+    a, st = sp.sp_bc(g, srcs)  # the per-source path keeps its own block sizes
+    assert st == sp.SP_OK and sp.sp_get_last_stats()["block_size"] <= 512
+    assert_bc(a.cpu().numpy(), ref, "sp_bc after tuning the blocks engine")
+    g.release()
+    sp.sp_tune_cache_clear()

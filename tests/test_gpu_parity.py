@@ -56,9 +56,9 @@ def csr_of(G):
     return graphs.from_edges(n, e[:, 0], e[:, 1])
 
 
-def check_sources_detail(sp, g, rp, ci, srcs):
+def check_sources_detail(sp, g, rp, ci, srcs, config=None):
     """Per-source dist/sigma/delta: per-source path and one batched pass."""
-    bd, bs, bdl, st = sp.sp_batch_levels(g, srcs)
+    bd, bs, bdl, st = sp.sp_batch_levels(g, srcs, config=config)
     bd, bs, bdl = bd.cpu().numpy(), bs.cpu().numpy(), bdl.cpu().numpy()
     for i, s in enumerate(srcs):
         d_ref, sig_ref, del_ref = oracle.source_detail(rp, ci, int(s))
@@ -259,7 +259,13 @@ def test_road_grid_128(sp, block):
     a, b, _, _ = both_paths(sp, g, srcs)
     assert_bc(a, ref, "sp_bc road")
     assert_bc(b, ref, "sp_bc_batch road")
+    assert sp.sp_get_last_stats()["engine"] == sp.SP_ENGINE_BLOCKS  # the automatic choice on roads
     check_sources_detail(sp, g, rp, ci, srcs)
+    # the bitmap engine on the same road graph
+    c, st = sp.sp_bc_batch(g, srcs, config={"engine": sp.SP_ENGINE_BITMAP})
+    assert st == sp.SP_OK and sp.sp_get_last_stats()["engine"] == sp.SP_ENGINE_BITMAP
+    assert_bc(c.cpu().numpy(), ref, "sp_bc_batch road, bitmap engine")
+    check_sources_detail(sp, g, rp, ci, srcs, config={"engine": sp.SP_ENGINE_BITMAP})
     g.release()
 
 
@@ -290,8 +296,11 @@ def test_sigma_overflow_flag(sp, k, flag):
     g = sp.sp_graph_upload(rp, ci)
     want = sp.SP_WARN_SIGMA_LARGE if flag else sp.SP_OK
     _, sa = sp.sp_bc(g, [0])
-    _, sb = sp.sp_bc_batch(g, [0, n - 1])
-    assert sa == want and sb == want
+    for engine in (sp.SP_ENGINE_BLOCKS, sp.SP_ENGINE_BITMAP):
+        _, sb = sp.sp_bc_batch(g, [0, n - 1], config={"engine": engine})
+        assert sb == want, engine
+        assert (sp.sp_get_last_stats()["sigma_flagged"] > 0) == flag
+    assert sa == want
     if not flag:
         ref = oracle.bc(rp, ci, [0, n - 1])
         assert_bc(sp.sp_bc(g, [0, n - 1])[0].cpu().numpy(), ref)
@@ -402,17 +411,64 @@ def test_hipgraph_capture_matches_direct_launches(sp, case, block):
     rp, ci, srcs, ref = cached("capture-" + case, make)
     g = sp.sp_graph_upload(rp, ci)
     use_launch_config(sp, g, block, 4.0)
-    direct, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": -8})
+    bitmap = sp.SP_ENGINE_BITMAP  # the engine whose levels are captured
+    direct, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": -8, "engine": bitmap})
     assert st == sp.SP_OK and sp.sp_get_last_stats()["graph_launches"] == 0
     direct = direct.cpu().numpy()
     assert_bc(direct, ref, "%s direct launches" % case)
     for rep in range(3):
-        got, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": 8})
+        got, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": 8, "engine": bitmap})
         assert st == sp.SP_OK
         assert sp.sp_get_last_stats()["graph_launches"] > 0
         assert np.array_equal(got.cpu().numpy(), direct), "%s replay %d differs" % (case, rep)
         sp.sp_bc(g, srcs[:2])  # eager work on the same stream between calls
-    got, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": 3, "batch_width": 7})
+    got, st = sp.sp_bc_batch(g, srcs, config={"chunk_levels": 3, "batch_width": 7, "engine": bitmap})
     assert st == sp.SP_OK
     assert_bc(got.cpu().numpy(), ref, "%s odd chunk, width 7" % case)
     g.release()
+
+
+def blocks_engine_cases():
+    """Graphs for the one-workgroup-per-source engine: its automatic target
+    (road-like grids) and, forced, every other shape: a long path (a level
+    per vertex), a uniform graph, RMAT with hubs and isolated vertices, a
+    directed RMAT, and a graph of two components."""
+    from tests import brute
+    yield "road-96", graphs.road(96, 0.02, 23), False
+    yield "path-3000", graphs.from_edges(3000, np.arange(2999), np.arange(1, 3000)), False
+    yield "uniform-4096", graphs.uniform(4096, 32768, 5), False
+    yield "rmat-13", graphs.rmat(13, 16, graphs.RMAT_ABC, 21), False
+    rp, ci = graphs.rmat(12, 16, graphs.RMAT_ABC, 31)
+    yield "rmat-12-directed", graphs.directed_from(rp, ci, 32), True
+    a = graphs.road(20, 0.02, 3)
+    yield "two-components", graphs.from_edges(
+        800, np.concatenate([np.repeat(np.arange(400), np.diff(a[0])), np.arange(400, 799)]),
+        np.concatenate([a[1], np.arange(401, 800)])), False
+
+
+@pytest.mark.parametrize("block", [128, 256, 512])
+@pytest.mark.parametrize("name", ["road-96", "path-3000", "uniform-4096", "rmat-13", "rmat-12-directed",
+                                  "two-components"])
+def test_blocks_engine(sp, name, block):
+    """SP_ENGINE_BLOCKS: BC over several batches (width 64 and 7, duplicate
+    and isolated sources included) and every slot's dist / sigma / delta of
+    one pass against the oracle."""
+    (rp, ci), directed = {k: (v, d) for k, v, d in blocks_engine_cases()}[name]
+    n = len(rp) - 1
+    g = sp.sp_graph_upload(rp, ci, validate=True, directed=directed)
+    srcs = graphs.sources(rp, min(90, n), 40)
+    srcs = np.concatenate([srcs, srcs[:3]]).astype(np.int32)  # duplicates count twice
+    iso = np.nonzero(np.diff(rp) == 0)[0]
+    if len(iso):
+        srcs = np.concatenate([srcs, iso[:2]]).astype(np.int32)
+    print(name, "block", block, "sources", len(srcs), flush=True)
+    ref = oracle.bc(rp, ci, srcs)
+    for width in (64, 7):
+        cfg = {"engine": sp.SP_ENGINE_BLOCKS, "block_size": block, "batch_width": width}
+        got, st = sp.sp_bc_batch(g, srcs, config=cfg)
+        assert st == sp.SP_OK
+        assert sp.sp_get_last_stats()["engine"] == sp.SP_ENGINE_BLOCKS
+        assert_bc(got.cpu().numpy(), ref, "%s block %d width %d" % (name, block, width))
+    check_sources_detail(sp, g, rp, ci, srcs[:64], config={"engine": sp.SP_ENGINE_BLOCKS, "block_size": block})
+    g.release()
+
