@@ -677,7 +677,7 @@ def main():
                     help="per-source BC legs as workload:sources, comma-separated ('' = skip)")
     ap.add_argument("--road-batched", default="road-4096:64",
                     help="batched BC legs on road-like grids as workload:sources ('' = skip)")
-    ap.add_argument("--serving-requests", type=int, default=80,
+    ap.add_argument("--serving-requests", type=int, default=400,
                     help="requests per phase of the serving workload (0 = skip)")
     ap.add_argument("--sssp-sources", default="rmat-22:16,road-4096:2",
                     help="SSSP legs as workload:sources, comma-separated ('' = skip)")

@@ -529,7 +529,7 @@ sp_status sp_profile_read(sp_kernel_profile *out, int32_t cap, int32_t *n_out);
 typedef struct sp_server_config {
     size_t memory_budget;  /* device bytes the server may hold for workspaces (0 = 25% of free) */
     int32_t max_batch;     /* slots per multi-source pass, 1..64 (0 = 64) */
-    int32_t n_streams;     /* concurrent passes on the device, 1..8 (0 = 2) */
+    int32_t n_streams;     /* concurrent passes on the device, 1..8 (0 = 4) */
     int32_t reserved[4];   /* must be zero */
 } sp_server_config;
 
@@ -546,9 +546,10 @@ typedef struct sp_server_stats {
     int64_t workspaces_evicted;  /* idle workspaces freed to admit another graph's */
 } sp_server_stats;
 
-/* Start a server: a scheduler thread packs queued sources of each graph into
- * multi-source passes and runs them on its own HIP streams (on the device
- * current at creation).  Workspaces are admitted against memory_budget. */
+/* Start a server: n_streams worker threads, each with its own HIP stream (on
+ * the device current at creation), pack queued sources of each graph into
+ * multi-source passes and run them.  Workspaces and chunk buffers are
+ * admitted against memory_budget. */
 sp_status sp_server_create(const sp_server_config *cfg, sp_server *out);
 
 /* Make an uploaded graph servable.  The graph must outlive the server. */
@@ -556,10 +557,15 @@ sp_status sp_server_add_graph(sp_server srv, sp_graph g, int32_t *graph_id);
 
 /* Queue BC over `sources` on graph `graph_id`.  out_bc: device double[V],
  * zeroed by the server before the first contribution and complete when the
- * request completes.  The request's sources may share passes with other
- * requests; each request's BC is accumulated per vertex in its own
- * source-list order, so the result is the same alone or in a mix.
- * out_req receives a handle to wait on and release. */
+ * request completes.  The sources are cut into chunks of max_batch
+ * consecutive sources; a pass takes whole chunks, possibly of several
+ * requests, and up to n_streams chunks of one request may run at once on
+ * different streams.  Chunk 0 accumulates into out_bc, each later chunk into
+ * a V-double buffer the server holds (counted with its workspaces) until it
+ * is added into out_bc in chunk order.  A chunk's sources are added in list
+ * order, so each request's BC is a function of its own source list: the
+ * same bits alone or in a mix.  out_req receives a handle to wait on and
+ * release. */
 sp_status sp_stream_submit(sp_server srv, int32_t graph_id, const int32_t *sources,
                            int32_t n_sources, double *out_bc, sp_request *out_req);
 

@@ -11,12 +11,20 @@
 // against the memory budget and kept for reuse (the idle ones of other graphs
 // are freed first when the budget is tight).
 //
-// Result independence: a request never has two passes in flight, its sources
-// occupy slots in list order, and the BC reduction adds slots in ascending
-// order per vertex, so every request's BC is accumulated per vertex in its
-// own source-list order whatever else shares its passes.  Each slot's delta
-// depends only on its own source (batch_path.hip), so a request's result is
-// bit-identical alone and in a mix.
+// A request's sources are cut into chunks of max_batch consecutive sources
+// (the last may be shorter), fixed at submission.  A pass takes whole chunks
+// only, possibly of several requests, and several chunks of one request may
+// be on the device at once, on different workers (up to n_streams chunks
+// past the last one merged).  Chunk 0 accumulates into the request's output;
+// chunk c >= 1 into a V-double buffer of the graph's pool, which is added
+// into the output once chunks 0..c-1 have been (in chunk order, by whichever
+// worker finishes the chunk that completes the prefix).
+//
+// Result independence: each slot's delta depends only on its own source, a
+// chunk's slots are reduced in ascending order into a buffer that starts at
+// zero, and chunk sums are added in chunk order, so every request's BC is
+// ((chunk 0) + chunk 1) + ... over a cut of its own source list: bit-identical
+// alone and in a mix, whatever else shares its passes.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -39,10 +47,14 @@ struct sp_request_s {
     int32_t graph_id = -1;
     std::vector<int32_t> sources;
     double *out_bc = nullptr;
-    int32_t next = 0;          // first source not yet given to a pass
-    int32_t done_sources = 0;  // sources whose pass finished
-    bool in_flight = false;
-    bool started = false;      // output zeroed, first pass issued
+    int32_t chunk = 64;        // sources per chunk
+    int32_t n_chunks = 0;
+    int32_t next_chunk = 0;    // first chunk not yet given to a pass
+    int32_t merged = 0;        // chunks added into out_bc (chunk order)
+    int32_t in_flight = 0;     // chunks on the device
+    bool merging = false;      // a worker is adding finished chunks into out_bc
+    std::vector<double *> part;     // chunk c >= 1: its BC buffer while unmerged
+    std::vector<char> chunk_done;   // chunk c's pass finished
     bool finished = false;
     bool cancelled = false;
     sp_status status = SP_OK;
@@ -53,8 +65,9 @@ struct sp_request_s {
 
 struct GraphSlot {
     sp_graph g = nullptr;
-    std::deque<sp_request> waiting;  // requests with sources left, arrival order
+    std::deque<sp_request> waiting;  // requests with chunks left, arrival order
     std::vector<sp::BatchWorkspace *> idle;
+    std::vector<double *> free_parts;  // V-double chunk buffers for reuse
     Clock::time_point last_used;
 };
 
@@ -76,17 +89,28 @@ namespace sp {
 static int32_t pending_sources(const sp_server_s *srv) {
     int64_t n = 0;
     for (const auto &gs : srv->graphs)
-        for (auto *r : gs.waiting) n += (int64_t)r->sources.size() - r->next;
+        for (auto *r : gs.waiting)
+            n += std::max<int64_t>(0, (int64_t)r->sources.size() - (int64_t)r->next_chunk * r->chunk);
     return (int32_t)std::min<int64_t>(n, INT32_MAX);
 }
 
-// Pick the graph whose oldest waiting request (not in flight) arrived first.
+static int32_t chunk_size(const sp_request_s *r, int32_t c) {
+    return std::min<int32_t>(r->chunk, (int32_t)r->sources.size() - c * r->chunk);
+}
+
+// A request's next chunk may start: it has one, and at most n_streams chunks
+// lie between the merge point and it (bounds its chunk buffers).
+static bool can_start(const sp_server_s *srv, const sp_request_s *r) {
+    return r->status >= 0 && r->next_chunk < r->n_chunks && r->next_chunk < r->merged + srv->cfg.n_streams;
+}
+
+// Pick the graph whose oldest request with a chunk that may start arrived first.
 static int pick_graph(sp_server_s *srv) {
     int best = -1;
     Clock::time_point bt{};
     for (size_t i = 0; i < srv->graphs.size(); ++i)
         for (auto *r : srv->graphs[i].waiting) {
-            if (r->in_flight) continue;
+            if (!can_start(srv, r)) continue;
             if (best < 0 || r->t_submit < bt) {
                 best = (int)i;
                 bt = r->t_submit;
@@ -96,8 +120,21 @@ static int pick_graph(sp_server_s *srv) {
     return best;
 }
 
+__global__ void k_add_f64(double *dst, const double *__restrict__ src, int32_t n) {
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) dst[v] += src[v];
+}
+
 // Make room for `need` more bytes by freeing idle workspaces of other graphs.
 static bool admit(sp_server_s *srv, size_t need, int keep_graph) {
+    for (size_t i = 0; i < srv->graphs.size() && srv->admitted + need > srv->cfg.memory_budget; ++i) {
+        GraphSlot &o = srv->graphs[i];  // pooled chunk buffers go first
+        while (!o.free_parts.empty() && srv->admitted + need > srv->cfg.memory_budget) {
+            dev_free(o.free_parts.back());
+            o.free_parts.pop_back();
+            srv->admitted -= (size_t)std::max(o.g->n, 1) * 8;
+        }
+    }
     while (srv->admitted + need > srv->cfg.memory_budget) {
         int victim = -1;
         for (size_t i = 0; i < srv->graphs.size(); ++i) {
@@ -123,6 +160,22 @@ static void finish_request(sp_server_s *srv, sp_request r, sp_status st) {
     r->cv.notify_all();
 }
 
+// Fail the waiting requests at the front of gs's queue that have nothing on
+// the device; their chunk buffers go back to the pool.
+static void fail_idle_waiting(sp_server_s *srv, GraphSlot &gs, sp_status st, const std::string &why) {
+    while (!gs.waiting.empty() && gs.waiting.front()->in_flight == 0) {
+        sp_request r = gs.waiting.front();
+        gs.waiting.pop_front();
+        for (double *&b : r->part)
+            if (b) {
+                gs.free_parts.push_back(b);
+                b = nullptr;
+            }
+        r->error = why;
+        finish_request(srv, r, st);
+    }
+}
+
 static void worker_main(sp_server_s *srv) {
     (void)hipSetDevice(srv->device);
     hipStream_t stream = nullptr;
@@ -139,8 +192,14 @@ static void worker_main(sp_server_s *srv) {
         GraphSlot &gs = srv->graphs[gi];
         sp_graph g = gs.g;
         int32_t width = 0;
-        const BatchRunOpts o = resolve_batch(g, nullptr, &width);
-        width = std::min(width, srv->cfg.max_batch);
+        BatchRunOpts o = resolve_batch(g, nullptr, &width);
+        width = srv->cfg.max_batch;  // passes are filled with whole chunks of up to max_batch
+        // Workers launch level chunks directly: a hipGraph capture on one
+        // worker's stream while other workers launch and allocate has failed
+        // their calls (the runtime's legacy-stream dependency check), and
+        // capture saves little here (deep road passes run the blocks engine,
+        // which captures nothing).
+        o.chunk_levels = -std::max(1, std::abs(o.chunk_levels));
         // Workspace: reuse an idle one of this graph, else admit a new one.
         BatchWorkspace *ws = nullptr;
         if (!gs.idle.empty()) {
@@ -155,12 +214,8 @@ static void worker_main(sp_server_s *srv) {
                 // admission only fails if one pass exceeds the budget, which
                 // submit already rejects; fail defensively.
                 if (srv->held == 0) {
-                    while (!gs.waiting.empty() && !gs.waiting.front()->in_flight) {
-                        sp_request r = gs.waiting.front();
-                        gs.waiting.pop_front();
-                        r->error = "a pass's workspace does not fit the server's memory budget";
-                        finish_request(srv, r, SP_ERR_OUT_OF_MEMORY);
-                    }
+                    fail_idle_waiting(srv, gs, SP_ERR_OUT_OF_MEMORY,
+                                      "a pass's workspace does not fit the server's memory budget");
                     continue;
                 }
                 srv->work_cv.wait(lk);
@@ -183,50 +238,67 @@ static void worker_main(sp_server_s *srv) {
                 }
                 srv->admitted -= need;
                 srv->held--;
-                while (!gs.waiting.empty() && !gs.waiting.front()->in_flight) {
-                    sp_request r = gs.waiting.front();
-                    gs.waiting.pop_front();
-                    r->error = sp_last_error();
-                    finish_request(srv, r, st);
-                }
+                fail_idle_waiting(srv, gs, st, sp_last_error());
                 srv->work_cv.notify_all();
                 continue;
             }
             ws->bytes = need;
         }
-        // Fill the pass: waiting requests of this graph in arrival order.
+        // Fill the pass with whole chunks of this graph's waiting requests, in
+        // arrival order (a chunk that does not fit the room left is skipped).
         std::vector<int32_t> srcs;
         std::vector<double *> outs;
         struct Part {
             sp_request r;
-            int32_t count;
-            bool first;
+            int32_t c;      // chunk index
+            int32_t count;  // its sources (= its slots in this pass)
+            double *dst;    // its accumulation buffer
         };
         std::vector<Part> parts;
+        bool no_buffer = false;
         for (auto *r : gs.waiting) {
-            if ((int32_t)srcs.size() >= width) break;
-            if (r->in_flight) continue;
-            const int32_t take = std::min<int32_t>(width - (int32_t)srcs.size(),
-                                                   (int32_t)r->sources.size() - r->next);
-            if (take <= 0) continue;
-            parts.push_back({r, take, !r->started});
-            for (int32_t k = 0; k < take; ++k) {
-                srcs.push_back(r->sources[r->next + k]);
-                outs.push_back(r->out_bc);
+            while (can_start(srv, r)) {
+                const int32_t c = r->next_chunk, cnt = chunk_size(r, c);
+                if ((int32_t)srcs.size() + cnt > width) break;
+                double *dst = r->out_bc;
+                if (c > 0) {
+                    // A pooled buffer, else a new one admitted against the
+                    // budget; over budget only when the pass has nothing
+                    // else to run (so every request keeps making progress).
+                    const size_t pb = (size_t)std::max(g->n, 1) * 8;
+                    if (!gs.free_parts.empty()) {
+                        dst = gs.free_parts.back();
+                        gs.free_parts.pop_back();
+                    } else if ((admit(srv, pb, gi) || srcs.empty()) &&
+                               dev_alloc((void **)&dst, pb) == SP_OK) {
+                        srv->admitted += pb;
+                        srv->stats.peak_admitted_bytes = std::max(srv->stats.peak_admitted_bytes, srv->admitted);
+                    } else {
+                        no_buffer = true;
+                        break;
+                    }
+                    r->part[c] = dst;
+                }
+                parts.push_back({r, c, cnt, dst});
+                for (int32_t k = 0; k < cnt; ++k) {
+                    srcs.push_back(r->sources[c * r->chunk + k]);
+                    outs.push_back(dst);
+                }
+                r->next_chunk++;
+                r->in_flight++;
             }
-            r->next += take;
-            r->in_flight = true;
-            r->started = true;
+            if ((int32_t)srcs.size() >= width || no_buffer) break;
         }
-        if (srcs.empty()) {  // another worker took these sources while we allocated
+        if (srcs.empty()) {  // nothing fits now (taken by another worker, or no buffer memory)
             gs.idle.push_back(ws);
             srv->held--;
+            if (no_buffer) srv->work_cv.wait_for(lk, std::chrono::milliseconds(1));
             srv->work_cv.notify_all();
             continue;
         }
-        // Requests whose every source is now assigned leave the waiting list.
+        // Requests whose every chunk is now assigned leave the waiting list.
         gs.waiting.erase(std::remove_if(gs.waiting.begin(), gs.waiting.end(),
-                                        [](sp_request r) { return r->next >= (int32_t)r->sources.size(); }),
+                                        [](sp_request r) { return r->next_chunk >= r->n_chunks; }),
                          gs.waiting.end());
         srv->stats.in_flight++;
         srv->stats.passes++;
@@ -236,8 +308,8 @@ static void worker_main(sp_server_s *srv) {
 
         sp_status st = SP_OK;
         clear_error();
-        for (auto &p : parts)
-            if (p.first && st >= 0) st = launch_fill_f64(p.r->out_bc, g->n, 0.0, stream);
+        for (auto &p : parts)  // every chunk sums into a buffer that starts at zero
+            if (st >= 0) st = launch_fill_f64(p.dst, g->n, 0.0, stream);
         BatchResult res;
         if (st >= 0) st = batch_run(g, *ws, srcs.data(), (int32_t)srcs.size(), outs.data(), o, stream, &res);
         if (st >= 0 && hipStreamSynchronize(stream) != hipSuccess) {
@@ -258,24 +330,62 @@ static void worker_main(sp_server_s *srv) {
         gs.idle.push_back(ws);
         gs.last_used = Clock::now();
         int32_t slot0 = 0;  // the part's slots are [slot0, slot0 + count)
+        std::vector<sp_request> touched;
         for (auto &p : parts) {
             sp_request r = p.r;
-            r->in_flight = false;
-            r->done_sources += p.count;
+            r->in_flight--;
+            r->chunk_done[p.c] = 1;
             const unsigned long long mine =
                 (p.count >= 64 ? ~0ull : ((1ull << p.count) - 1ull)) << slot0;
             slot0 += p.count;
             if (st < 0) {
+                if (r->status >= 0) r->error = err;
                 r->status = st;
-                r->error = err;
             } else if (r->status >= 0 && (res.flagged_mask & mine)) {
                 r->status |= SP_WARN_SIGMA_LARGE;  // only the request that owns the slot
             }
             srv->stats.edges_traversed += (int64_t)p.count * (g->nnz / 2);
-            if (r->done_sources >= (int32_t)r->sources.size() || r->status < 0) {
-                if (r->status < 0)
-                    gs.waiting.erase(std::remove(gs.waiting.begin(), gs.waiting.end(), r), gs.waiting.end());
-                if (!r->finished) finish_request(srv, r, r->status);
+            if (std::find(touched.begin(), touched.end(), r) == touched.end()) touched.push_back(r);
+        }
+        // Add finished chunks into each touched request's output in chunk
+        // order; finish the request when all are in (or, after a failure,
+        // when none is left on the device).
+        for (sp_request r : touched) {
+            if (r->status < 0)
+                gs.waiting.erase(std::remove(gs.waiting.begin(), gs.waiting.end(), r), gs.waiting.end());
+            if (!r->merging) {
+                r->merging = true;
+                while (r->status >= 0 && r->merged < r->n_chunks && r->chunk_done[r->merged]) {
+                    const int32_t c = r->merged;
+                    if (c > 0) {
+                        double *src = r->part[c];
+                        lk.unlock();
+                        hipLaunchKernelGGL(k_add_f64, dim3(grid_for(g->n, 256, 2048)), dim3(256), 0, stream,
+                                           r->out_bc, (const double *)src, g->n);
+                        hipError_t e = hipGetLastError();
+                        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+                        lk.lock();
+                        if (e != hipSuccess) {
+                            r->error = "serving: adding a chunk's BC failed";
+                            r->status = SP_ERR_DEVICE;
+                            break;
+                        }
+                        gs.free_parts.push_back(src);
+                        r->part[c] = nullptr;
+                    }
+                    r->merged++;
+                }
+                r->merging = false;
+            }
+            const bool complete = r->status >= 0 && r->merged == r->n_chunks;
+            const bool failed_and_idle = r->status < 0 && r->in_flight == 0 && !r->merging;
+            if ((complete || failed_and_idle) && !r->finished) {
+                for (double *&b : r->part)
+                    if (b) {
+                        gs.free_parts.push_back(b);
+                        b = nullptr;
+                    }
+                finish_request(srv, r, r->status);
             }
         }
         srv->stats.admitted_bytes = srv->admitted;
@@ -312,7 +422,7 @@ sp_status sp_server_create(const sp_server_config *cfg, sp_server *out) {
             return SP_ERR_NOT_SUPPORTED;
         }
         if (!c.max_batch) c.max_batch = kSlots;
-        if (!c.n_streams) c.n_streams = 2;
+        if (!c.n_streams) c.n_streams = 4;
         if (!c.memory_budget) {
             size_t fr = 0, tot = 0;
             if (hipMemGetInfo(&fr, &tot) != hipSuccess) return SP_ERR_DEVICE;
@@ -384,6 +494,10 @@ sp_status sp_stream_submit(sp_server srv, int32_t graph_id, const int32_t *sourc
         r->graph_id = graph_id;
         r->sources.assign(sources, sources + n_sources);
         r->out_bc = out_bc;
+        r->chunk = srv->cfg.max_batch;
+        r->n_chunks = (n_sources + r->chunk - 1) / r->chunk;
+        r->part.assign(r->n_chunks, nullptr);
+        r->chunk_done.assign(r->n_chunks, 0);
         r->t_submit = Clock::now();
         srv->stats.submitted++;
         if (n_sources == 0 || g->n == 0) {
@@ -429,7 +543,7 @@ sp_status sp_request_cancel(sp_request r) {
     if (__atomic_load_n(&r->finished, __ATOMIC_ACQUIRE)) return SP_ERR_REJECTED;
     sp_server_s *srv = r->srv;
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (r->started || r->finished) return SP_ERR_REJECTED;
+    if (r->next_chunk > 0 || r->finished) return SP_ERR_REJECTED;
     auto &w = srv->graphs[r->graph_id].waiting;
     w.erase(std::remove(w.begin(), w.end(), r), w.end());
     r->cancelled = true;
@@ -485,11 +599,13 @@ sp_status sp_server_destroy(sp_server srv) {
     }
     for (auto &t : srv->workers) t.join();
     (void)hipSetDevice(srv->device);
-    for (auto &gs : srv->graphs)
+    for (auto &gs : srv->graphs) {
         for (auto *ws : gs.idle) {
             batch_ws_destroy(*ws);
             delete ws;
         }
+        for (double *b : gs.free_parts) dev_free(b);
+    }
     delete srv;
     return SP_OK;
 }
