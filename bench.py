@@ -572,7 +572,7 @@ def cpu_model():
     return None
 
 
-def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
+def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=200):
     """Serving workload: eight resident graphs, seeded requests (graph uniform,
     1..512 sources log-uniform), continuous batching by the library's server.
     Phase "burst" submits every request at once (saturation throughput);
@@ -588,7 +588,9 @@ def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
     handles = [sp.sp_graph_upload(rp, ci) for _, rp, ci in gs]
     edges = [len(ci) // 2 for _, _, ci in gs]
     # an explicit workspace budget (the library's default is a quarter of the
-    # free memory at creation, which depends on what ran before)
+    # free memory at creation, which depends on what ran before): room for a
+    # workspace of every graph on each of the four workers (about 190 GB, most
+    # of it road-4096's 30 GB per worker), so admission never has to evict
     srv = sp.Server(memory_budget=budget_gb << 30)
     ids = [srv.add_graph(h) for h in handles]
     outs = [torch.empty(max(h.n, 1), dtype=torch.float64, device="cuda") for h in handles]
@@ -628,12 +630,19 @@ def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=96):
         lat = np.array([r.latency_us() for r in live]) / 1e3
         for r in live:
             r.release()
+        by_graph = {}
+        for gi in sorted(set(g for g, _ in reqs)):
+            sel = np.array([g == gi for g, _ in reqs])
+            big = max(len(src) for g, src in reqs if g == gi)
+            by_graph[gs[gi][0]] = {"requests": int(sel.sum()), "largest_sources": big,
+                                   "p50_ms": round(float(np.percentile(lat[sel], 50)), 1),
+                                   "p99_ms": round(float(np.percentile(lat[sel], 99)), 1)}
         print("serving phase rate=%s: %.1f s" % (rate, wall), file=sys.stderr, flush=True)
         return {"offered_qps": round(rate, 3) if rate else None, "achieved_qps": round(len(reqs) / wall, 3),
                 "teps": work / wall, "p50_ms": round(float(np.percentile(lat, 50)), 2),
                 "p99_ms": round(float(np.percentile(lat, 99)), 2), "max_ms": round(float(lat.max()), 2),
                 "wall_s": round(wall, 2), "failed": int(bad), "sigma_warnings": int(warned),
-                "errors": errors or None}
+                "errors": errors or None, "by_graph": by_graph}
 
     burst = phase(0)
     sat = burst["achieved_qps"]
@@ -699,6 +708,8 @@ def main():
                     help="run only the PageRank legs and print their JSON object")
     ap.add_argument("--only-road", action="store_true",
                     help="run only the road-like batched BC legs and print their JSON object")
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run only the serving workload and print its JSON object")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="first run one elementwise kernel that reads and writes this many GiB "
                          "(a known-size kernel that calibrates hardware byte counters in a "
@@ -747,8 +758,11 @@ def main():
         rate = 2 * cbuf.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         copy_gbps = rate if copy_gbps != copy_gbps else max(copy_gbps, rate)
     del cbuf, cdst
-    if args.only_sssp or args.only_pagerank or args.only_tc or args.only_directed or args.only_road:
+    if args.only_sssp or args.only_pagerank or args.only_tc or args.only_directed or args.only_road or \
+            args.only_serving:
         legs = {}
+        if args.only_serving:
+            legs["serving"] = serving_benchmark(sp, torch, args.serving_requests)
         if args.only_road:
             legs["road_batched"] = {wl: road_batched_benchmark(sp, torch, wl, int(ns)) for wl, ns in
                                     (leg.split(":") for leg in filter(None, args.road_batched.split(",")))}
