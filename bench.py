@@ -57,6 +57,11 @@ WORKLOADS = {"uniform-4096": 1, "rmat-20": 2, "rmat-22": 3, "road-4096": 4}
 BYTE_MODEL = {
     "ms_sigma": dict(items=72, edges=20, pairs=8, item_slots=8),
     "ms_sigma_hub": dict(edges=20, pairs=8),
+    # pushed path counts: items = parent entries (queue, qmask, qvb, row
+    # offsets), edges = their outgoing entries (column id, child's front
+    # record), pairs = (slot, DAG edge) atomic adds (read and write of the
+    # child's value)
+    "ms_sigma_push": dict(items=24, edges=20, pairs=16),
     "ms_delta": dict(items=40, edges=20, pairs=8, item_slots=24),
     "ms_delta_hub": dict(edges=20, pairs=8),
     "ms_topdown": dict(items=20, edges=20),
@@ -93,7 +98,7 @@ BYTE_MODEL = {
     # separately from the oriented-entry count
     "tc_count": dict(edges=4),
 }
-FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_expand")
+FORWARD = ("ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_sigma_push", "ms_expand")
 
 
 _WORKLOAD_CACHE = {}

@@ -82,12 +82,35 @@ __device__ __forceinline__ int rank_in(unsigned long long m, int s) {
 // window k+2 are already on their way (issued first, so waiting for the
 // values does not wait for more than they need).
 
+// A value every lane holds alike, moved into scalar registers, so that the
+// mask arithmetic on it below runs once per wave.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
+
+// Whether the lane's slot is in the wave-uniform mask m (m used as the exec
+// mask itself).
+__device__ __forceinline__ bool lane_in(unsigned long long m) {
+    return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+
+// rank_in(m, lane) for a wave-uniform m: set bits of m below the lane.
+__device__ __forceinline__ int lane_rank(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // One window: add the values of the matching neighbours whose front records
-// are `fu` (lane i holds the record of the window's i-th entry).
+// are `fu` (lane i holds the record of the window's i-th entry); m is
+// wave-uniform.  A neighbour's mask and value base are read into scalar
+// registers, so per neighbour a lane only computes its rank and loads; lanes
+// whose slot the neighbour lacks add +0.0, which leaves their sum (never
+// negative) unchanged bit for bit.
 __device__ __forceinline__ void window_acc(uint4 fu, unsigned long long m, uint32_t tag,
                                            const double *__restrict__ val, double &acc,
                                            unsigned long long &pairs) {
-    const int lane = lane_id();
     unsigned long long mu = 0;
     uint32_t vb = 0;
     if (fu.z == tag) {
@@ -113,12 +136,12 @@ __device__ __forceinline__ void window_acc(uint4 fu, unsigned long long m, uint3
         double x[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const bool on = ((mj[t] & m) >> lane) & 1ull;
-            x[t] = on ? val[(int64_t)vj[t] + rank_in(mj[t], lane)] : 0.0;
+            x[t] = 0.0;
+            if (lane_in(mj[t] & m)) x[t] = val[(int64_t)vj[t] + lane_rank(mj[t])];
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            if (((mj[t] & m) >> lane) & 1ull) acc += x[t];
+            acc += x[t];
             pairs += (unsigned long long)__popcll(mj[t] & m);
         }
     }
@@ -135,6 +158,7 @@ __device__ __forceinline__ double dense_sum_from(uint4 f, int32_t beg, int32_t e
                                                  unsigned long long &pairs) {
     const int lane = lane_id();
     double acc = 0.0;
+    m = uniform_u64(m);  // one entry's slots: the same in every lane
     int32_t un = beg + kWave + lane < end ? ci[beg + kWave + lane] : -1;
     for (int32_t e0 = beg; e0 < end; e0 += kWave) {
         const uint4 fn = un >= 0 ? front[un] : no_front();  // window k+1
@@ -307,6 +331,7 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->next_deg_.v = 0;
         c->settled_deg_.v = 0;
         c->reached_pairs = pairs;  // = s_vb[n0]
+        c->val_lo = 0;
         c->vtail_.v = s_vb[n0];
         c->unset_deg = (unsigned long long)nnz - settled;
         c->sigma_max_bits_.v = (unsigned long long)__double_as_longlong(1.0);
@@ -324,6 +349,8 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
         c->in_hub_pack_.v = 0;
         c->in_hub_n = 0;
         c->in_hub_nchunks = 0;
+        c->pull_cost_.v = 0;
+        c->sigma_push = 0;
         c->hub_lo = 0;
         c->hub_hi = nh;
         c->hub_nchunks = nch;
@@ -343,7 +370,8 @@ __global__ void k_ms_init(LevelCtl *c, const int32_t *__restrict__ rp, const int
 // the chunks of the frontier's hubs.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ ci, int32_t *queue,
+                                                   const int32_t *__restrict__ ci,
+                                                   const int32_t *__restrict__ rpi, int32_t *queue,
                                                    const unsigned long long *__restrict__ qmask,
                                                    const unsigned long long *__restrict__ seen,
                                                    unsigned long long *nxt,
@@ -359,10 +387,15 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
     StagedQueue<BS, 4 * BS> q;
     q.init(s_qbuf, s_meta);
     const int32_t lo = c->lo, hi = c->hi;
-    unsigned long long my_items = 0, my_edges = 0;
+    unsigned long long my_items = 0, my_edges = 0, my_pull = 0;
+    // claims a new vertex for the next level; its incoming row length is the
+    // work a pull of its path counts would do (the push/pull choice)
     auto visit = [&](int32_t w, unsigned long long fm) {
         const unsigned long long nm = fm & ~seen[w];
-        if (nm && (nm & ~*(volatile unsigned long long *)&nxt[w])) return atomicOr(&nxt[w], nm) == 0ull;
+        if (nm && (nm & ~*(volatile unsigned long long *)&nxt[w]) && atomicOr(&nxt[w], nm) == 0ull) {
+            my_pull += (unsigned long long)(rpi[w + 1] - rpi[w]);
+            return true;
+        }
         return false;
     };
     if (blockIdx.y == 0) {
@@ -425,6 +458,7 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
         }
     }
     q.finish(&c->tail_.v, queue, qcap, &c->overflow_.v);
+    block_add_u64<BS>(my_pull, s_red, &c->pull_cost_.v);
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
@@ -453,7 +487,7 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
     const uint32_t lvl = (uint32_t)c->level;
     const int32_t n = c->n_vertices;
     const int g = lane >> 3, j = lane & 7;
-    unsigned long long my_items = 0, my_edges = 0;
+    unsigned long long my_items = 0, my_edges = 0, my_pull = 0;
     for (int32_t b = blockIdx.x * BS; b < n; b += gridDim.x * BS) {
         const int32_t v = b + threadIdx.x;
         int32_t beg = 0, deg = 0;
@@ -504,10 +538,14 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
         }
         __builtin_amdgcn_wave_barrier();
         const unsigned long long found = acc[lane];
-        if (found) nxt[v] = found;
+        if (found) {
+            nxt[v] = found;
+            my_pull += (unsigned long long)deg;  // rows here are the incoming ones
+        }
         q.stage(found != 0ull, v, &c->tail_.v, queue, qcap, &c->overflow_.v);
     }
     q.finish(&c->tail_.v, queue, qcap, &c->overflow_.v);
+    block_add_u64<BS>(my_pull, s_red, &c->pull_cost_.v);
     flush_counters<BS>(prof, my_items, my_edges, 0, s_red);
 }
 
@@ -516,8 +554,10 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
 // direction, or set `done`.
 __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
                               int32_t *hub_lvl_chunks, long long qcap, long long hub_cap,
-                              int32_t *chunk_off, long long owner_cap) {
+                              int32_t *chunk_off, long long owner_cap, int32_t push) {
     if (c->done) return;
+    c->sigma_push = push;  // how the level being closed gets its path counts
+    c->pull_cost_.v = 0;
     if (c->mode == MODE_TOPDOWN) c->topdown_levels++; else c->bottomup_levels++;
     const int32_t tail = ld_agent(&c->tail_.v);
     const unsigned long long hp = ld_agent(&c->hub_pack_.v);
@@ -553,6 +593,7 @@ __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
     c->unset_deg -= ld_agent(&c->settled_deg_.v);
     c->next_deg_.v = 0;
     c->settled_deg_.v = 0;
+    c->val_lo = c->reached_pairs;  // the new level's values: [val_lo, reached_pairs)
     c->reached_pairs = ld_agent(&c->vtail_.v);  // every reached (slot, vertex) pair owns one value
     c->live = ld_agent(&c->nlive_.v);
     c->nlive_.v = 0;
@@ -564,6 +605,19 @@ __device__ void advance_level(LevelCtl *c, int32_t *level_off, int32_t *hub_off,
     } else {
         if ((double)nf * c->beta < (double)c->n_vertices) c->mode = MODE_TOPDOWN;
     }
+}
+
+// Push threshold: the parents' outgoing entries must be fewer than the new
+// entries' incoming ones by this factor (an atomic add per (slot, DAG edge)
+// costs more than the load a pull makes instead).
+constexpr double kPushFactor = 2.0;
+
+// Whether the level being built gets its path counts pushed (see k_ms_sigma).
+__device__ __forceinline__ bool push_sigma(const LevelCtl *c, int32_t max_deg) {
+    const double smax = __longlong_as_double((long long)ld_agent(&c->sigma_max_bits_.v));
+    const bool exact = smax * (double)max_deg < 9007199254740992.0;  // 2^53
+    const double pull = (double)ld_agent(&c->pull_cost_.v);
+    return exact && (double)c->front_deg * kPushFactor < pull;
 }
 
 // Path counts of the new entries [hi, tail).  Wave takes 64 entries, gives
@@ -585,12 +639,25 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                                                  long long qcap, int32_t track_deg, int32_t *level_off,
                                                  int32_t *hub_off, int32_t *hub_lvl_chunks,
                                                  int32_t *owner, long long owner_cap,
-                                                 int32_t *chunk_off, unsigned long long *prof) {
+                                                 int32_t *chunk_off, int32_t max_deg,
+                                                 unsigned long long *prof) {
     if (c->done) return;
     const unsigned long long active = c->active;
     __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
     __shared__ int32_t s_scan[BS / kWave + 1];
     const uint32_t lvl = (uint32_t)c->level;
+    // Path counts of the new level by pull (each new entry sums its parents
+    // over its incoming row) or by push (k_ms_sigma_push: each parent adds
+    // its values into its children with float atomics), whichever reads
+    // fewer adjacency entries: the new entries' incoming rows (counted by
+    // discovery) against the parents' outgoing rows.  The push is taken only
+    // while every sum it builds stays an exact integer -- below 2^53 with
+    // at most max_deg terms of at most the largest path count so far -- so
+    // the order of the atomics cannot change a bit: both ways give the same
+    // values.  Every block of the grid computes the same decision from
+    // control-block fields this kernel does not change before its last block
+    // closes the level.
+    const bool push = push_sigma(c, max_deg);
     const int32_t hi = c->hi;
     const int32_t tail = (int32_t)min((long long)c->tail_.v, qcap);
     const int lane = lane_id();
@@ -624,8 +691,10 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
         const uint32_t vb = (uint32_t)vb64;
         if (valid && !fits) atomicOr(&c->overflow_.v, 1);
         const bool hub = valid && fits && deg > kHubDeg;
-        const bool sparse = valid && fits && !hub && pc <= kSparseSlots && deg <= kSparseDeg;
-        const bool dense = valid && fits && !hub && !sparse;
+        const bool sparse = !push && valid && fits && !hub && pc <= kSparseSlots && deg <= kSparseDeg;
+        const bool dense = !push && valid && fits && !hub && !sparse;
+        if (push && valid && fits)  // the parents add into these values
+            for (int r = 0; r < pc; ++r) val[vb + r] = 0.0;
         if (sparse) {
             unsigned long long bits = m;
             while (bits) {
@@ -653,7 +722,7 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
         // are kept for the whole pass; on a directed graph the path counts
         // chunk the incoming rows, listed afresh for this level only.
         if (in_hub_list) {
-            if (hub) hub_register(&c->in_hub_pack_.v, in_hub_list, in_hub_cap, 0, w, i, deg);
+            if (hub && !push) hub_register(&c->in_hub_pack_.v, in_hub_list, in_hub_cap, 0, w, i, deg);
             if (valid && fits && dout > kHubDeg)
                 hub_register(&c->hub_pack_.v, hub_list, hub_cap, c->hub_next, w, i, dout, owner,
                              c->chunk_next, owner_cap);
@@ -693,8 +762,8 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
         const unsigned long long cur = *(volatile unsigned long long *)&c->nlive_.v;
         if ((cur | s_or[0]) != cur) atomicOr(&c->nlive_.v, s_or[0]);
     }
-    if (track_deg) {  // only the direction switch needs these sums
-        block_add_u64<BS>(my_deg, s_red, &c->next_deg_.v);
+    block_add_u64<BS>(my_deg, s_red, &c->next_deg_.v);  // direction switch and push choice
+    if (track_deg) {  // only the direction switch needs this one
         __syncthreads();
         block_add_u64<BS>(my_settled, s_red, &c->settled_deg_.v);
     }
@@ -710,7 +779,7 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
     }
     // the last block to finish closes the level
     if (last_block(c, working_blocks((int64_t)tail - hi, BS)) && threadIdx.x == 0)
-        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap, chunk_off, owner_cap);
+        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap, chunk_off, owner_cap, push);
 }
 
 
@@ -884,7 +953,7 @@ __global__ __launch_bounds__(BS) void k_ms_expand(
         block_add_u64<BS>(my_pull, s_red, prof + 3);
     }
     if (last_block(c, working_blocks((int64_t)hi - lo, BS)) && threadIdx.x == 0)
-        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap, chunk_off, owner_cap);
+        advance_level(c, level_off, hub_off, hub_lvl_chunks, qcap, hub_cap, chunk_off, owner_cap, 0);
 }
 
 // Hubs, lane = slot: each chunk of kHubChunk adjacency entries is reduced by
@@ -939,7 +1008,7 @@ __global__ __launch_bounds__(BS) void k_ms_sigma_hub(LevelCtl *c, const int32_t 
                                                      const int32_t *__restrict__ chunk_off,
                                                      const HubEntry *in_hub_list,
                                                      double *partial, unsigned long long *prof) {
-    if (c->done) return;
+    if (c->done || c->sigma_push) return;  // pushed: k_ms_sigma_push
     __shared__ unsigned long long s_red[1];
     const bool in = in_hub_list != nullptr;
     const int32_t nch = in ? c->in_hub_nchunks : c->hub_nchunks;
@@ -972,7 +1041,7 @@ __global__ void k_ms_sigma_hub_fin(LevelCtl *c, const unsigned long long *__rest
                                    const HubEntry *__restrict__ hub_list,
                                    const double *__restrict__ partial,
                                    const HubEntry *__restrict__ in_hub_list) {
-    if (c->done) return;
+    if (c->done || c->sigma_push) return;
     if (in_hub_list) hub_list = in_hub_list;  // directed: the level's incoming-row hubs
     const int32_t hlo = in_hub_list ? 0 : c->hub_lo, hhi = in_hub_list ? c->in_hub_n : c->hub_hi;
     const int lane = lane_id();
@@ -996,6 +1065,245 @@ __global__ void k_ms_sigma_hub_fin(LevelCtl *c, const unsigned long long *__rest
         atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
         if (my_flag) atomicOr(&c->flagged_slots_.v, my_flag);
     }
+}
+
+// Pushed path counts, for a level whose sigma_push k_ms_sigma set: every
+// entry of the parent level adds its value of each slot into the entries of
+// its children (outgoing row, next level) that hold that slot, with float
+// atomics; k_ms_sigma zeroed the children's values.  The sums are exact
+// integers whenever the push is taken, so they equal the pulled ones bit for
+// bit whatever order the atomics land in.
+
+// One window of a parent's row, lane = slot: lane i holds the front record
+// `fu` of the window's i-th child; every lane of a slot in both masks adds
+// the parent's value `sig` of that slot into the child's value of it.  m is
+// wave-uniform.
+__device__ __forceinline__ void push_window(uint4 fu, unsigned long long m, uint32_t tag,
+                                            double sig, double *val, unsigned long long &pairs) {
+    unsigned long long mu = 0;
+    uint32_t vb = 0;
+    if (fu.z == tag) {
+        mu = mask_of(fu);
+        vb = fu.w;
+    }
+    unsigned long long nz = __ballot((mu & m) != 0ull);
+    while (nz) {
+        const int j = __ffsll((long long)nz) - 1;
+        nz &= nz - 1;
+        const unsigned long long mj = rl_u64(mu, j);
+        const uint32_t vj = (uint32_t)rl_i32((int32_t)vb, j);
+        if (lane_in(mj & m)) unsafeAtomicAdd(&val[(int64_t)vj + lane_rank(mj)], sig);
+        pairs += (unsigned long long)__popcll(mj & m);
+    }
+}
+
+// A wave pushes one parent over row entries [beg, end) (lane = slot, parent
+// mask m, `sig` = the parent's value of the lane's slot).  The column ids of
+// the window after next and the records of the next one are loaded while the
+// current window is pushed.
+__device__ __forceinline__ void push_row(int32_t beg, int32_t end, unsigned long long m,
+                                         uint32_t tag, double sig,
+                                         const int32_t *__restrict__ ci,
+                                         const uint4 *__restrict__ front, double *val,
+                                         unsigned long long &pairs) {
+    const int lane = lane_id();
+    m = uniform_u64(m);
+    const int32_t u = beg + lane < end ? ci[beg + lane] : -1;
+    uint4 f = u >= 0 ? front[u] : no_front();
+    int32_t un = beg + kWave + lane < end ? ci[beg + kWave + lane] : -1;
+    for (int32_t e0 = beg; e0 < end; e0 += kWave) {
+        const uint4 fn = un >= 0 ? front[un] : no_front();
+        const int32_t e2 = e0 + 2 * kWave + lane;
+        un = e2 < end ? ci[e2] : -1;
+        push_window(f, m, tag, sig, val, pairs);
+        f = fn;
+    }
+}
+
+// Parents with at most this many slots push lane = row entry
+// (push_row_lanes): one pass over the window per parent slot beats one per
+// matching child.
+constexpr int kPushLaneSlots = 16;
+
+// A wave pushes one parent with few slots over row entries [beg, end), lane
+// = entry: for each of the parent's slots in turn (value `pv` of lane r =
+// the parent's r-th value), every lane whose child holds that slot adds the
+// parent's value of it.  m is wave-uniform.
+__device__ __forceinline__ void push_row_lanes(int32_t beg, int32_t end, unsigned long long m,
+                                               double pv, uint32_t tag,
+                                               const int32_t *__restrict__ ci,
+                                               const uint4 *__restrict__ front, double *val,
+                                               unsigned long long &pairs) {
+    const int lane = lane_id();
+    m = uniform_u64(m);
+    const int32_t u = beg + lane < end ? ci[beg + lane] : -1;
+    uint4 f = u >= 0 ? front[u] : no_front();
+    int32_t un = beg + kWave + lane < end ? ci[beg + kWave + lane] : -1;
+    for (int32_t e0 = beg; e0 < end; e0 += kWave) {
+        const uint4 fn = un >= 0 ? front[un] : no_front();
+        const int32_t e2 = e0 + 2 * kWave + lane;
+        un = e2 < end ? ci[e2] : -1;
+        const unsigned long long mu = f.z == tag ? mask_of(f) & m : 0ull;
+        if (__ballot(mu != 0ull)) {
+            unsigned long long rest = m;
+            for (int r = 0; rest; ++r) {
+                const int sl = __ffsll((long long)rest) - 1;
+                rest &= rest - 1;
+                const double x = __longlong_as_double(
+                    (long long)rl_u64((unsigned long long)__double_as_longlong(pv), r));
+                if ((mu >> sl) & 1ull) {
+                    unsafeAtomicAdd(&val[(int64_t)f.w + rank_in(mask_of(f), sl)], x);
+                    ++pairs;
+                }
+            }
+        }
+        f = fn;
+    }
+}
+
+// One lane pushes a parent with at most kSparseSlots slots over its short
+// row, four entries in flight.
+__device__ __forceinline__ void push_sparse(int32_t beg, int32_t end, unsigned long long m,
+                                            uint32_t vb, uint32_t tag,
+                                            const int32_t *__restrict__ ci,
+                                            const uint4 *__restrict__ front, double *val,
+                                            unsigned long long &pairs) {
+    double pv[kSparseSlots];
+#pragma unroll
+    for (int r = 0; r < kSparseSlots; ++r) pv[r] = r < __popcll(m) ? val[vb + r] : 0.0;
+    for (int32_t e0 = beg; e0 < end; e0 += 4) {
+        int32_t u[4];
+        uint4 f[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) u[t] = e0 + t < end ? ci[e0 + t] : -1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f[t] = u[t] >= 0 ? front[u[t]] : no_front();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (f[t].z != tag) continue;
+            const unsigned long long mu = mask_of(f[t]);
+            unsigned long long both = mu & m;
+            while (both) {
+                const int sl = __ffsll((long long)both) - 1;
+                both &= both - 1;
+                const int r = rank_in(m, sl);
+                unsafeAtomicAdd(&val[(int64_t)f[t].w + rank_in(mu, sl)], r == 0 ? pv[0] : pv[1]);
+                ++pairs;
+            }
+        }
+    }
+}
+
+// A wave pushes one parent (wave-uniform mask m and value base vb) over row
+// entries [beg, end), lane = entry for few slots, else lane = slot.  `pairs`
+// counts in lane 0 only.
+__device__ __forceinline__ void push_parent(int32_t beg, int32_t end, unsigned long long m,
+                                            uint32_t vb, uint32_t tag,
+                                            const int32_t *__restrict__ ci,
+                                            const uint4 *__restrict__ front, double *val,
+                                            unsigned long long &pairs) {
+    const int lane = lane_id();
+    m = uniform_u64(m);
+    const int pc = __popcll(m);
+    unsigned long long pr = 0;
+    if (pc <= kPushLaneSlots) {
+        const double pv = lane < pc ? val[vb + lane] : 0.0;
+        push_row_lanes(beg, end, m, pv, tag, ci, front, val, pr);
+        for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o, kWave);
+    } else {
+        const double sig = lane_in(m) ? val[vb + lane_rank(m)] : 0.0;
+        push_row(beg, end, m, tag, sig, ci, front, val, pr);
+    }
+    if (lane == 0) pairs += pr;
+}
+
+// blockIdx.y == 0: the parent level's entries without a hub row, like
+// k_ms_sigma's (a lane alone for few slots and a short row, else the wave in
+// turn); blockIdx.y == 1: the chunks of the parents' hub rows, one wave each.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ms_sigma_push(LevelCtl *c,
+                                                      const int32_t *__restrict__ level_off,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const int32_t *__restrict__ queue,
+                                                      const unsigned long long *__restrict__ qmask,
+                                                      const uint32_t *__restrict__ qvb,
+                                                      const uint4 *__restrict__ front_child,
+                                                      double *val, const HubEntry *hub_list,
+                                                      const int32_t *__restrict__ owner,
+                                                      const int32_t *__restrict__ chunk_off,
+                                                      const int32_t *__restrict__ hub_lvl_chunks,
+                                                      unsigned long long *prof) {
+    if (c->done || !c->sigma_push) return;
+    __shared__ unsigned long long s_red[1];
+    const int32_t pl = c->level - 1;  // parents
+    const uint32_t tag = (uint32_t)c->level;
+    const int lane = lane_id();
+    unsigned long long my_items = 0, my_edges = 0, my_pairs = 0;
+    if (blockIdx.y == 0) {
+        const int32_t plo = level_off[pl], phi = level_off[pl + 1];
+        for (int32_t b = plo + (int32_t)(blockIdx.x * BS); b < phi; b += gridDim.x * BS) {
+            const int32_t i = b + (int32_t)threadIdx.x;
+            const bool valid = i < phi;
+            int32_t beg = 0, end = 0;
+            unsigned long long m = 0;
+            uint32_t vb = 0;
+            if (valid) {
+                const int32_t v = queue[i];
+                m = qmask[i];
+                vb = qvb[i];
+                beg = rp[v];
+                end = rp[v + 1];
+            }
+            const int32_t deg = end - beg;
+            const bool hub = deg > kHubDeg;  // blockIdx.y == 1
+            const bool sparse = valid && !hub && __popcll(m) <= kSparseSlots && deg <= kSparseDeg;
+            const bool dense = valid && !hub && !sparse;
+            unsigned long long pr = 0;
+            if (sparse) push_sparse(beg, end, m, vb, tag, ci, front_child, val, pr);
+            my_pairs += pr;
+            unsigned long long dm = __ballot(dense);
+            while (dm) {
+                const int j = __ffsll((long long)dm) - 1;
+                dm &= dm - 1;
+                const unsigned long long mj = rl_u64(m, j);
+                const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, j);
+                unsigned long long wp = 0;
+                push_parent(rl_i32(beg, j), rl_i32(end, j), mj, vbj, tag, ci, front_child, val, wp);
+                my_pairs += wp;
+            }
+            if (valid) {
+                ++my_items;
+                if (!hub) my_edges += (unsigned long long)deg;
+            }
+        }
+    } else {
+        const int32_t nch = hub_lvl_chunks[pl], obase = chunk_off[pl];
+        for_xcd_chunks<BS>(nch, [&](int64_t k) {
+            const HubEntry h = hub_list[owner[obase + k]];
+            int32_t beg, end;
+            if (!hub_chunk_range(h, k, rp, beg, end)) return;
+            unsigned long long wp = 0;
+            push_parent(beg, end, qmask[h.entry], qvb[h.entry], tag, ci, front_child, val, wp);
+            my_pairs += wp;
+            if (lane == 0) my_edges += (unsigned long long)(end - beg);
+        });
+    }
+    flush_counters<BS>(prof, my_items, my_edges, my_pairs, s_red);
+}
+
+// Largest path count of a pushed level: one pass over its values
+// [val_lo, reached_pairs), contiguous in the value store.  (Pushed sums are
+// below 2^53, so no slot is flagged here.)
+__global__ void k_ms_sigma_push_fin(LevelCtl *c, const double *__restrict__ val) {
+    if (c->done || !c->sigma_push) return;
+    const int64_t lo = (int64_t)c->val_lo, hi = (int64_t)c->reached_pairs;
+    double my_max = 0.0;
+    for (int64_t k = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < hi;
+         k += (int64_t)gridDim.x * blockDim.x)
+        my_max = fmax(my_max, val[k]);
+    my_max = wave_max_f64(my_max);
+    if (lane_id() == 0) atomic_max_nonneg_f64(&c->sigma_max_bits_.v, my_max);
 }
 
 // Finish slot `s` of an entry in the reverse pass: acc = sum of the
@@ -1434,7 +1742,7 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
         {
             ProfScope ps(P_MS_TOPDOWN, s);
             hipLaunchKernelGGL(k_ms_topdown<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s, ws.ctl,
-                               g->row_ptr, g->col_idx, ws.queue, ws.qmask, ws.seen, ws.nxt,
+                               g->row_ptr, g->col_idx, (const int32_t *)g->rp_in, ws.queue, ws.qmask, ws.seen, ws.nxt,
                                (const HubEntry *)ws.hub_list, (const int32_t *)ws.owner,
                                (const int32_t *)ws.chunk_off, (long long)ws.qcap,
                                prof_counters(P_MS_TOPDOWN));
@@ -1454,7 +1762,7 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
                                ws.val, (long long)ws.vcap, ws.hub_list, (long long)ws.hub_cap,
                                (long long)ws.qcap, (int32_t)may_pull, ws.level_off,
                                ws.hub_off, ws.hub_lvl_chunks, ws.owner, (long long)ws.owner_cap,
-                               ws.chunk_off, prof_counters(P_MS_SIGMA));
+                               ws.chunk_off, (int32_t)g->max_degree, prof_counters(P_MS_SIGMA));
         }
         if (sigma_hubs) {
             ProfScope ps(P_MS_SIGMA_HUB, s);
@@ -1469,6 +1777,19 @@ static void enqueue_levels(sp_graph g, BatchWorkspace &ws, int64_t first, int co
                                (const unsigned long long *)ws.qmask, (const uint32_t *)ws.qvb,
                                ws.val, (const HubEntry *)ws.hub_list, (const double *)ws.partial,
                                in_list);
+        }
+        {
+            ProfScope ps(P_MS_SIGMA_PUSH, s);
+            hipLaunchKernelGGL(k_ms_sigma_push<BS>, dim3(grid, hubs ? 2 : 1), dim3(BS), 0, s,
+                               ws.ctl, (const int32_t *)ws.level_off, g->row_ptr, g->col_idx,
+                               (const int32_t *)ws.queue, (const unsigned long long *)ws.qmask,
+                               (const uint32_t *)ws.qvb, (const uint4 *)fnxt, ws.val,
+                               (const HubEntry *)ws.hub_list, (const int32_t *)ws.owner,
+                               (const int32_t *)ws.chunk_off, (const int32_t *)ws.hub_lvl_chunks,
+                               prof_counters(P_MS_SIGMA_PUSH));
+            // (timed with the push kernel)
+            hipLaunchKernelGGL(k_ms_sigma_push_fin, dim3(grid), dim3(256), 0, s, ws.ctl,
+                               (const double *)ws.val);
         }
     }
 }

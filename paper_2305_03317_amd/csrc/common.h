@@ -226,6 +226,13 @@ struct LevelCtl {
     // in_hub_pack_ accumulates the level being built as (count << 40) | chunks.
     int32_t in_hub_n, in_hub_nchunks;
     HotU64 in_hub_pack_;
+    // Batched path, path counts of the level being built: pull_cost_
+    // accumulates the incoming row lengths of its new vertices (the entries a
+    // pull reads); sigma_push = 1 when the level's path counts are pushed from
+    // the parents instead (set by `advance`, for the level it opens).
+    HotU64 pull_cost_;
+    int32_t sigma_push;
+    unsigned long long val_lo;  // batched: first value of the current level
 };
 
 
@@ -235,7 +242,7 @@ enum ProfKind : int {
     P_SRC_TOPDOWN, P_SRC_BOTTOMUP, P_SRC_SIGMA, P_SRC_SIGMA_HUB, P_SRC_DELTA, P_SRC_DELTA_HUB,
     P_MS_TOPDOWN, P_MS_BOTTOMUP, P_MS_SIGMA, P_MS_SIGMA_HUB, P_MS_EXPAND, P_MS_DELTA, P_MS_DELTA_HUB,
     P_MS_BC, P_SSSP_PUSH, P_SSSP_PULL, P_PR_PULL, P_PR_HUB, P_TC_COUNT, P_WG_BC,
-    P_COUNT
+    P_MS_SIGMA_PUSH, P_COUNT
 };
 constexpr int kProfCounters = 4;  // items, edges, pairs, item_slots
 extern const char *const kProfNames[P_COUNT];

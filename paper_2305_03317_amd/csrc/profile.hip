@@ -14,6 +14,7 @@ const char *const kProfNames[P_COUNT] = {
     "src_topdown", "src_bottomup", "src_sigma", "src_sigma_hub", "src_delta", "src_delta_hub",
     "ms_topdown", "ms_bottomup", "ms_sigma", "ms_sigma_hub", "ms_expand", "ms_delta", "ms_delta_hub",
     "ms_bc", "sssp_push", "sssp_pull", "pr_pull", "pr_hub", "tc_count", "wg_bc",
+    "ms_sigma_push",
 };
 
 namespace {
