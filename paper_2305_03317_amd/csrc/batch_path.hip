@@ -226,6 +226,131 @@ __device__ __forceinline__ void dense_each(unsigned long long dm, int32_t beg, i
     }
 }
 
+// Dense entries with rows of at most kPackDeg entries go through packed_each,
+// which loads the values of kPackBatch matches at a time.
+constexpr int32_t kPackDeg = 64;
+constexpr int kPackBatch = 8;
+
+// dense_sum for every lane j set in pm, with short rows packed: the rows of
+// the set lanes, in lane order, are laid end to end and walked 64 entries per
+// window (lane k of a window finds its entry by binary search over the row
+// offsets in LDS), so one window's loads serve several entries.  Matches are
+// taken in window order, which is entry order and CSR order inside an entry;
+// a running sum is handed to fin(j, sum, pairs) when the entry changes, and
+// an entry without a match gets fin(j, 0.0, 0).  Each entry's sum therefore
+// adds the same terms in the same order as dense_sum: the same bits.  The
+// column ids two windows ahead and the front records one window ahead are
+// loaded while a window is summed.  s_off/s_beg: 64 ints of LDS for the wave.
+template <class Fin>
+__device__ __forceinline__ void packed_each(unsigned long long pm, int32_t beg, int32_t end,
+                                            unsigned long long m, uint32_t tag,
+                                            const int32_t *__restrict__ ci,
+                                            const uint4 *__restrict__ front,
+                                            const double *__restrict__ val, int32_t *s_off,
+                                            int32_t *s_beg, Fin fin) {
+    if (!pm) return;
+    const int lane = lane_id();
+    const int32_t d = ((pm >> lane) & 1ull) ? end - beg : 0;
+    const int32_t incl = wave_incl_scan(d);
+    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    s_off[lane] = incl - d;
+    s_beg[lane] = beg;
+    __builtin_amdgcn_wave_barrier();
+    // entry (lane index) and neighbour of virtual position p, or -1 past the end
+    auto locate = [&](int32_t p, int32_t &e, int32_t &u) {
+        e = -1;
+        u = -1;
+        if (p < total) {
+            int32_t a = 0, z = kWave - 1;
+            while (a < z) {
+                const int32_t mid = (a + z + 1) >> 1;
+                if (s_off[mid] <= p) a = mid; else z = mid - 1;
+            }
+            e = a;
+            u = ci[s_beg[a] + (p - s_off[a])];
+        }
+    };
+    int32_t e0, u0, e1, u1;
+    locate(lane, e0, u0);
+    locate(kWave + lane, e1, u1);
+    uint4 f = u0 >= 0 ? front[u0] : no_front();
+    int32_t cur = -1;
+    double acc = 0.0;
+    unsigned long long pairs = 0, done = 0;
+    for (int32_t p0 = 0; p0 < total; p0 += kWave) {
+        const uint4 fn = u1 >= 0 ? front[u1] : no_front();  // window k+1
+        int32_t e2, u2;
+        locate(p0 + 2 * kWave + lane, e2, u2);               // window k+2
+        // the slots of the lane's entry, read from the entry's lane; every
+        // lane takes part in the shuffle (a lane switched off would hand
+        // zero to the lanes reading from it)
+        const int src = e0 >= 0 ? e0 : 0;
+        const uint32_t me_lo = (uint32_t)__shfl((int)(uint32_t)m, src, kWave);
+        const uint32_t me_hi = (uint32_t)__shfl((int)(uint32_t)(m >> 32), src, kWave);
+        const unsigned long long me =
+            e0 >= 0 ? ((unsigned long long)me_lo | ((unsigned long long)me_hi << 32)) : 0ull;
+        unsigned long long mu = 0;
+        uint32_t vbu = 0;
+        if (f.z == tag) {
+            mu = mask_of(f);
+            vbu = f.w;
+        }
+        unsigned long long nz = __ballot((mu & me) != 0ull);
+        while (nz) {
+            int32_t ej[kPackBatch];
+            unsigned long long mj[kPackBatch], bj[kPackBatch];
+            uint32_t vj[kPackBatch];
+#pragma unroll
+            for (int t = 0; t < kPackBatch; ++t) {
+                if (nz) {
+                    const int j = __ffsll((long long)nz) - 1;
+                    nz &= nz - 1;
+                    ej[t] = rl_i32(e0, j);
+                    mj[t] = rl_u64(mu, j);
+                    vj[t] = (uint32_t)rl_i32((int32_t)vbu, j);
+                    bj[t] = mj[t] & rl_u64(m, ej[t]);
+                } else {  // past the last match: adds +0.0 to no entry
+                    ej[t] = -1;
+                    mj[t] = 0;
+                    vj[t] = 0;
+                    bj[t] = 0;
+                }
+            }
+            double x[kPackBatch];
+#pragma unroll
+            for (int t = 0; t < kPackBatch; ++t) {
+                x[t] = 0.0;
+                if (lane_in(bj[t])) x[t] = val[(int64_t)vj[t] + lane_rank(mj[t])];
+            }
+#pragma unroll
+            for (int t = 0; t < kPackBatch; ++t) {
+                if (ej[t] >= 0 && ej[t] != cur) {
+                    if (cur >= 0) {
+                        fin(cur, acc, pairs);
+                        done |= 1ull << cur;
+                    }
+                    cur = ej[t];
+                    acc = 0.0;
+                    pairs = 0;
+                }
+                acc += x[t];
+                pairs += (unsigned long long)__popcll(bj[t]);
+            }
+        }
+        f = fn;
+        e0 = e1;
+        e1 = e2;
+        u1 = u2;
+    }
+    if (cur >= 0) {
+        fin(cur, acc, pairs);
+        done |= 1ull << cur;
+    }
+    for (unsigned long long rest = pm & ~done; rest; rest &= rest - 1)
+        fin(__ffsll((long long)rest) - 1, 0.0, 0ull);
+    __builtin_amdgcn_wave_barrier();  // the wave's LDS rows are free again
+}
+
 // One lane, one slot s: the same sum as dense_sum for slot s alone.  Four
 // adjacency entries are in flight at a time (their column ids, then their
 // front records, then the values), and added in CSR order.
@@ -646,7 +771,7 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
     if (c->done) return;
     const unsigned long long active = c->active;
     __shared__ unsigned long long s_red[1], s_base[1], s_or[1];
-    __shared__ int32_t s_scan[BS / kWave + 1];
+    __shared__ int32_t s_scan[BS / kWave + 1], s_poff[BS], s_pbeg[BS];
     const uint32_t lvl = (uint32_t)c->level;
     // Path counts of the new level by pull (each new entry sums its parents
     // over its incoming row) or by push (k_ms_sigma_push: each parent adds
@@ -708,18 +833,21 @@ __global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *
                 if (sigma_is_large(acc)) my_flag |= 1ull << s;
             }
         }
-        dense_each(__ballot(dense), beg, end, m, lvl, cii, front_cur, val,
-                   [&](int jl, double acc, unsigned long long pr) {
-                       const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
-                       const unsigned long long mj = rl_u64(m, jl);
-                       if (lane == 0) my_dag += pr;
-                       const bool mine = (mj >> lane) & 1ull;
-                       if (mine) {
-                           val[vbj + rank_in(mj, lane)] = acc;
-                           my_max = fmax(my_max, acc);
-                       }
-                       my_flag |= __ballot(mine && sigma_is_large(acc));
-                   });
+        auto fin = [&](int jl, double acc, unsigned long long pr) {
+            const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
+            const unsigned long long mj = rl_u64(m, jl);
+            if (lane == 0) my_dag += pr;
+            const bool mine = lane_in(mj);
+            if (mine) {
+                val[vbj + lane_rank(mj)] = acc;
+                my_max = fmax(my_max, acc);
+            }
+            my_flag |= __ballot(mine && sigma_is_large(acc));
+        };
+        const bool packed = dense && deg <= kPackDeg;
+        packed_each(__ballot(packed), beg, end, m, lvl, cii, front_cur, val,
+                    s_poff + (threadIdx.x & ~(kWave - 1)), s_pbeg + (threadIdx.x & ~(kWave - 1)), fin);
+        dense_each(__ballot(dense && !packed), beg, end, m, lvl, cii, front_cur, val, fin);
         // Hub chunks of the level's outgoing rows (discovery, reverse pass)
         // are kept for the whole pass; on a directed graph the path counts
         // chunk the incoming rows, listed afresh for this level only.
@@ -1332,6 +1460,7 @@ __global__ __launch_bounds__(BS, 6) void k_ms_delta(LevelCtl *c, int32_t step,
                                                  uint4 *f1, double *val, double *dlt,
                                                  int32_t parity, unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
+    __shared__ int32_t s_poff[BS], s_pbeg[BS];
     // The reverse sweep's level (0 = finished), read once by the block.  With
     // `step` this kernel moves the sweep up in its last working block; the
     // parity of the launch's step (levels swept before it) lets a block that
@@ -1391,19 +1520,21 @@ __global__ __launch_bounds__(BS, 6) void k_ms_delta(LevelCtl *c, int32_t step,
                 finish_slot(acc, val + vb + rank_in(m, s), dlt + (int64_t)v * kSlots + s);
             }
         }
-        dense_each(__ballot(dense), beg, end, m, nl, ci, front_rd, val,
-                   [&](int jl, double acc, unsigned long long pr) {
-                       const int32_t vj = rl_i32(v, jl);
-                       const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
-                       const unsigned long long mj = rl_u64(m, jl);
-                       if (lane == 0) {
-                           my_pairs += pr;
-                           my_edges += (unsigned long long)(rl_i32(end, jl) - rl_i32(beg, jl));
-                       }
-                       if ((mj >> lane) & 1ull)
-                           finish_slot(acc, val + vbj + rank_in(mj, lane),
-                                       dlt + (int64_t)vj * kSlots + lane);
-                   });
+        auto fin = [&](int jl, double acc, unsigned long long pr) {
+            const int32_t vj = rl_i32(v, jl);
+            const uint32_t vbj = (uint32_t)rl_i32((int32_t)vb, jl);
+            const unsigned long long mj = rl_u64(m, jl);
+            if (lane == 0) {
+                my_pairs += pr;
+                my_edges += (unsigned long long)(rl_i32(end, jl) - rl_i32(beg, jl));
+            }
+            if (lane_in(mj))
+                finish_slot(acc, val + vbj + lane_rank(mj), dlt + (int64_t)vj * kSlots + lane);
+        };
+        const bool packed = dense && deg <= kPackDeg;
+        packed_each(__ballot(packed), beg, end, m, nl, ci, front_rd, val,
+                    s_poff + (threadIdx.x & ~(kWave - 1)), s_pbeg + (threadIdx.x & ~(kWave - 1)), fin);
+        dense_each(__ballot(dense && !packed), beg, end, m, nl, ci, front_rd, val, fin);
     }
     if (prof) {
         block_add_u64<BS>(my_items, s_red, prof + 0);
