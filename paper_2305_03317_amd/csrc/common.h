@@ -357,6 +357,12 @@ struct BatchWorkspace {
     int32_t *wg_dist = nullptr, *wg_queue = nullptr, *wg_loff = nullptr;  // loff: [slot][V + 2]
     double *wg_sigma = nullptr, *wg_delta = nullptr;
     WgSlotResult *wg_res = nullptr, *wg_res_host = nullptr;
+    // Rows of width wg_ell_w (4 or 8; 0: rows read through the CSR offsets):
+    // neighbour k of v at [v * w + k], -1 past the row's end; the incoming
+    // rows' copy too on a directed graph.  Built on the first pass.
+    int32_t *wg_ell = nullptr, *wg_ell_in = nullptr;
+    int32_t wg_ell_w = 0;
+    bool wg_ell_built = false;
     int32_t n = 0;
     unsigned long long *seen = nullptr;  // V: slots that reached v at any level so far
     unsigned long long *nxt = nullptr;   // V: slots discovering v at the level being built

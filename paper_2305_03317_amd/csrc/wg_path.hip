@@ -38,6 +38,18 @@
 // each issued together, so one step of a level costs a few dependent round
 // trips for kEntries x kRowStep adjacency entries.  Sums still run in CSR
 // order per vertex.
+//
+// Latency: a level is a chain of dependent round trips to memory, so on a
+// graph whose rows hold at most 8 entries the rows are copied once into a
+// fixed-width layout (W = 4 or 8 ids per vertex, -1 padding): a vertex's
+// neighbours come in one load instead of an offset load followed by an id
+// load.  With it a discovery step is queue entry -> row -> claim (a
+// compare-and-swap straight away, which returns the level of a vertex
+// already reached), a path-count step queue entry -> row -> the neighbours'
+// level and path count together, and a reverse step queue entry -> row (and
+// the vertex's own path count) -> the neighbours' level, path count and
+// dependency together: values of a neighbour that turns out not to be a
+// parent (child) are loaded and dropped.
 #include "common.h"
 #include "devutil.h"
 
@@ -79,6 +91,189 @@ __device__ __forceinline__ int32_t claim_level(int32_t *p, int32_t lvl) {
 __global__ void k_wg_fill(int32_t *dist, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dist[i] = -1;
+}
+
+// Fixed-width copy of the rows: ell[v * W + k] = k-th neighbour, -1 past the
+// row's end (every row holds at most W entries).
+template <int W>
+__global__ void k_wg_ell(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int32_t n,
+                         int32_t *ell) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int32_t b = rp[v], d = rp[v + 1] - b;
+#pragma unroll
+        for (int k = 0; k < W; ++k) ell[v * W + k] = k < d ? ci[b + k] : -1;
+    }
+}
+
+// Row of v in the fixed-width layout (v < 0: an empty row).
+template <int W>
+__device__ __forceinline__ void ell_row(const int32_t *__restrict__ ell, int32_t v, int32_t (&nb)[W]) {
+    if (v < 0) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) nb[k] = -1;
+        return;
+    }
+    const int4 *r = reinterpret_cast<const int4 *>(ell + (int64_t)v * W);
+#pragma unroll
+    for (int q = 0; q < W / 4; ++q) {
+        const int4 x = r[q];
+        nb[4 * q + 0] = x.x;
+        nb[4 * q + 1] = x.y;
+        nb[4 * q + 2] = x.z;
+        nb[4 * q + 3] = x.w;
+    }
+}
+
+// k_wg_bc over fixed-width rows (see the latency note above): the same sums
+// in the same order.
+template <int BS, int W>
+__global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ ell,
+                                                  const int32_t *__restrict__ ell_in,
+                                                  const int32_t *__restrict__ slot_src, int32_t n,
+                                                  int32_t *dist_all, double *sigma_all, double *delta_all,
+                                                  int32_t *queue_all, int32_t *loff_all, WgSlotResult *res,
+                                                  unsigned long long *prof) {
+    constexpr int E = W == 8 ? 2 : kEntries;  // entries in flight per thread (registers)
+    const int32_t slot = blockIdx.x;
+    const int64_t base = (int64_t)slot * n;
+    int32_t *dist = dist_all + base;
+    double *sigma = sigma_all + base;
+    double *delta = delta_all + base;
+    int32_t *queue = queue_all + base;
+    int32_t *loff = loff_all + (int64_t)slot * ((int64_t)n + 2);
+    const int32_t src = slot_src[slot];
+    __shared__ int32_t s_tail, s_flag;
+    __shared__ double s_max[BS / kWave];
+    __shared__ unsigned long long s_red[1];
+    if (threadIdx.x == 0) {
+        dist[src] = 0;
+        sigma[src] = 1.0;
+        queue[0] = src;
+        loff[0] = 0;
+        loff[1] = 1;
+        s_tail = 1;
+        s_flag = 0;
+    }
+    __syncthreads();
+    int32_t lo = 0, hi = 1, level = 0;
+    double my_max = 1.0;
+    unsigned long long my_edges = 0, my_pairs = 0;
+    for (;;) {
+        // Discovery of level + 1 from the frontier [lo, hi): the claim
+        // (dist -1 -> level + 1) decides who appends the vertex.
+        for (int32_t i0 = lo + (int32_t)threadIdx.x; i0 < hi; i0 += BS * E) {
+            int32_t v[E], nb[E][W], old[E][W];
+#pragma unroll
+            for (int u = 0; u < E; ++u) v[u] = i0 + u * BS < hi ? queue[i0 + u * BS] : -1;
+#pragma unroll
+            for (int u = 0; u < E; ++u) ell_row<W>(ell, v[u], nb[u]);
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int k = 0; k < W; ++k) old[u][k] = nb[u][k] >= 0 ? claim_level(&dist[nb[u][k]], level + 1) : 0;
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    if (nb[u][k] >= 0) ++my_edges;
+                    if (nb[u][k] >= 0 && old[u][k] == -1) queue[atomicAdd(&s_tail, 1)] = nb[u][k];  // LDS
+                }
+        }
+        __syncthreads();
+        const int32_t tail = s_tail;
+        if (tail == hi) break;  // block-uniform: every thread read the same tail
+        // Path counts of the new vertices [hi, tail): parents over incoming
+        // rows, added in row order.
+        for (int32_t j0 = hi + (int32_t)threadIdx.x; j0 < tail; j0 += BS * E) {
+            int32_t w[E], p[E][W], d[E][W];
+            double x[E][W];
+#pragma unroll
+            for (int u = 0; u < E; ++u) w[u] = j0 + u * BS < tail ? queue[j0 + u * BS] : -1;
+#pragma unroll
+            for (int u = 0; u < E; ++u) ell_row<W>(ell_in, w[u], p[u]);
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    d[u][k] = p[u][k] >= 0 ? ld_level(&dist[p[u][k]]) : -1;
+                    x[u][k] = p[u][k] >= 0 ? sigma[p[u][k]] : 0.0;  // kept for parents only
+                }
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    if (d[u][k] == level) {
+                        acc += x[u][k];
+                        ++my_pairs;
+                    }
+                if (w[u] >= 0) {
+                    sigma[w[u]] = acc;
+                    my_max = fmax(my_max, acc);
+                    if (sigma_is_large(acc)) s_flag = 1;
+                }
+            }
+        }
+        if (threadIdx.x == 0) loff[level + 2] = tail;
+        __syncthreads();
+        lo = hi;
+        hi = tail;
+        ++level;
+    }
+    // Reverse sweep from the deepest level up to level 1 (the deepest has no
+    // children: its delta is 0); children over outgoing rows, in row order.
+    for (int32_t l = level; l >= 1; --l) {
+        const int32_t a = loff[l], z = loff[l + 1];
+        for (int32_t j0 = a + (int32_t)threadIdx.x; j0 < z; j0 += BS * E) {
+            int32_t v[E], nb[E][W], d[E][W];
+            double sv[E], sw[E][W], dw[E][W];
+#pragma unroll
+            for (int u = 0; u < E; ++u) v[u] = j0 + u * BS < z ? queue[j0 + u * BS] : -1;
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                ell_row<W>(ell, v[u], nb[u]);
+                sv[u] = v[u] >= 0 ? sigma[v[u]] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const int32_t y = nb[u][k];
+                    d[u][k] = y >= 0 ? ld_level(&dist[y]) : -1;
+                    sw[u][k] = y >= 0 ? sigma[y] : 1.0;  // kept for children only
+                    dw[u][k] = y >= 0 ? delta[y] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    if (d[u][k] == l + 1) {
+                        acc += (sv[u] / sw[u][k]) * (1.0 + dw[u][k]);
+                        ++my_pairs;
+                    }
+                if (v[u] >= 0) delta[v[u]] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    my_max = wave_max_f64(my_max);
+    if (lane_id() == 0) s_max[threadIdx.x / kWave] = my_max;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int w = 0; w < BS / kWave; ++w) m = fmax(m, s_max[w]);
+        res[slot] = WgSlotResult{level + 1, hi, m, s_flag};
+    }
+    if (prof) {
+        __syncthreads();
+        block_add_u64<BS>(threadIdx.x == 0 ? (unsigned long long)hi : 0ull, s_red, prof + 0);
+        __syncthreads();
+        block_add_u64<BS>(my_edges, s_red, prof + 1);
+        __syncthreads();
+        block_add_u64<BS>(my_pairs, s_red, prof + 2);
+    }
 }
 
 // One source per workgroup: blockIdx.x = slot.
@@ -312,9 +507,15 @@ __global__ void k_wg_extract(int64_t count, const int32_t *__restrict__ dist, co
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+// Width of the fixed-width rows for g: 4 or 8 when every row fits, else 0.
+static int32_t ell_width(sp_graph g) {
+    return g->max_degree <= 4 ? 4 : g->max_degree <= 8 ? 8 : 0;
+}
+
 size_t wg_ws_bytes(sp_graph g, int32_t width) {
     const size_t V = (size_t)std::max(g->n, 1);
-    return (size_t)width * (V * (4 + 8 + 8 + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult);
+    const size_t ell = V * (size_t)ell_width(g) * 4 * (g->directed ? 2 : 1);
+    return (size_t)width * (V * (4 + 8 + 8 + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult) + ell;
 }
 
 sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
@@ -326,6 +527,13 @@ sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
     SP_TRY(dev_alloc((void **)&ws.wg_loff, W * (V + 2) * 4));
     SP_TRY(dev_alloc((void **)&ws.wg_res, W * sizeof(WgSlotResult)));
     SP_HIP(hipHostMalloc((void **)&ws.wg_res_host, W * sizeof(WgSlotResult), hipHostMallocDefault));
+    ws.wg_ell_w = ell_width(g);
+    ws.wg_ell_built = false;
+    if (ws.wg_ell_w) {
+        const size_t cells = V * (size_t)ws.wg_ell_w;
+        SP_TRY(dev_alloc((void **)&ws.wg_ell, cells * 4));
+        if (g->directed) SP_TRY(dev_alloc((void **)&ws.wg_ell_in, cells * 4));
+    }
     return SP_OK;
 }
 
@@ -336,6 +544,11 @@ void wg_ws_free(BatchWorkspace &ws) {
     dev_free(ws.wg_queue);
     dev_free(ws.wg_loff);
     dev_free(ws.wg_res);
+    dev_free(ws.wg_ell);
+    dev_free(ws.wg_ell_in);
+    ws.wg_ell = ws.wg_ell_in = nullptr;
+    ws.wg_ell_w = 0;
+    ws.wg_ell_built = false;
     if (ws.wg_res_host) (void)hipHostFree(ws.wg_res_host);
     ws.wg_dist = ws.wg_queue = ws.wg_loff = nullptr;
     ws.wg_sigma = ws.wg_delta = nullptr;
@@ -352,12 +565,33 @@ static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, 
     for (int32_t i = 0; i < kSlots; ++i) h_src[i] = i < nslots ? srcs[i] : -1;
     SP_HIP(hipMemcpyAsync(ws.slot_src, h_src, kSlots * 4, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_wg_fill, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, ws.wg_dist, count);
+    const int ew = ws.wg_ell_w;
+    if (ew && !ws.wg_ell_built) {
+        auto build = ew == 4 ? k_wg_ell<4> : k_wg_ell<8>;
+        hipLaunchKernelGGL(build, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, (const int32_t *)g->row_ptr,
+                           (const int32_t *)g->col_idx, n, ws.wg_ell);
+        if (g->directed)
+            hipLaunchKernelGGL(build, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, (const int32_t *)g->rp_in,
+                               (const int32_t *)g->ci_in, n, ws.wg_ell_in);
+        SP_HIP(hipGetLastError());
+        ws.wg_ell_built = true;
+    }
     {
         ProfScope ps(P_WG_BC, s);
-        hipLaunchKernelGGL(k_wg_bc<BS>, dim3(nslots), dim3(BS), 0, s, (const int32_t *)g->row_ptr,
-                           (const int32_t *)g->col_idx, (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
-                           (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta, ws.wg_queue,
-                           ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
+        const int32_t *ell_in = g->directed ? ws.wg_ell_in : ws.wg_ell;
+        if (ew == 4)
+            hipLaunchKernelGGL((k_wg_bc_ell<BS, 4>), dim3(nslots), dim3(BS), 0, s, (const int32_t *)ws.wg_ell,
+                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta,
+                               ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
+        else if (ew == 8)
+            hipLaunchKernelGGL((k_wg_bc_ell<BS, 8>), dim3(nslots), dim3(BS), 0, s, (const int32_t *)ws.wg_ell,
+                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta,
+                               ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
+        else
+            hipLaunchKernelGGL(k_wg_bc<BS>, dim3(nslots), dim3(BS), 0, s, (const int32_t *)g->row_ptr,
+                               (const int32_t *)g->col_idx, (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
+                               (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta,
+                               ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
     }
     SP_HIP(hipGetLastError());
     if (ex)

@@ -430,11 +430,25 @@ def test_hipgraph_capture_matches_direct_launches(sp, case, block):
 
 def blocks_engine_cases():
     """Graphs for the one-workgroup-per-source engine: its automatic target
-    (road-like grids) and, forced, every other shape: a long path (a level
-    per vertex), a uniform graph, RMAT with hubs and isolated vertices, a
-    directed RMAT, and a graph of two components."""
+    (road-like grids, rows of at most 4: fixed-width rows of 4), a grid with
+    diagonal moves (rows of up to 8: fixed-width rows of 8), a directed road
+    grid (fixed-width incoming rows too) and, forced, every other shape: a
+    long path (a level per vertex), a uniform graph and RMAT with hubs and
+    isolated vertices (rows through the CSR offsets), a directed RMAT, and a
+    graph of two components."""
     from tests import brute
     yield "road-96", graphs.road(96, 0.02, 23), False
+    k = 40
+    x, y = np.meshgrid(np.arange(k), np.arange(k))
+    x, y = x.ravel(), y.ravel()
+    src, dst = [], []
+    for dx, dy in ((1, 0), (0, 1), (1, 1), (-1, 1)):  # king moves, each edge once
+        ok = (x + dx >= 0) & (x + dx < k) & (y + dy < k)
+        src.append((y * k + x)[ok])
+        dst.append(((y + dy) * k + x + dx)[ok])
+    yield "king-40", graphs.from_edges(k * k, np.concatenate(src), np.concatenate(dst)), False
+    rp, ci = graphs.road(60, 0.02, 25)
+    yield "road-60-directed", graphs.directed_from(rp, ci, 26), True
     yield "path-3000", graphs.from_edges(3000, np.arange(2999), np.arange(1, 3000)), False
     yield "uniform-4096", graphs.uniform(4096, 32768, 5), False
     yield "rmat-13", graphs.rmat(13, 16, graphs.RMAT_ABC, 21), False
@@ -446,9 +460,9 @@ def blocks_engine_cases():
         np.concatenate([a[1], np.arange(401, 800)])), False
 
 
-@pytest.mark.parametrize("block", [128, 256, 512])
-@pytest.mark.parametrize("name", ["road-96", "path-3000", "uniform-4096", "rmat-13", "rmat-12-directed",
-                                  "two-components"])
+@pytest.mark.parametrize("block", [128, 256, 512, 1024])
+@pytest.mark.parametrize("name", ["road-96", "king-40", "road-60-directed", "path-3000", "uniform-4096",
+                                  "rmat-13", "rmat-12-directed", "two-components"])
 def test_blocks_engine(sp, name, block):
     """SP_ENGINE_BLOCKS: BC over several batches (width 64 and 7, duplicate
     and isolated sources included) and every slot's dist / sigma / delta of
