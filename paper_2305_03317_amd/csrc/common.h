@@ -337,6 +337,16 @@ struct SlotTable {
 };
 
 // Per-slot summary written by the workgroup engine.
+// Blocks engine, per (slot, vertex): the BFS level (-1 unreached) and a
+// value -- sigma after the forward pass, rho = (1 + delta) / sigma once the
+// reverse pass has finished the vertex (rows read through the fixed-width
+// layout; the CSR-offset kernel keeps sigma and delta in their own arrays).
+struct alignas(16) WgRec {
+    int32_t dist;
+    int32_t pad;
+    double val;
+};
+
 struct WgSlotResult {
     int32_t levels;   // levels including level 0
     int32_t reached;  // vertices reached
@@ -354,7 +364,8 @@ struct BatchWorkspace {
     int device = -1;
     int32_t engine = SP_ENGINE_BITMAP;   // SP_ENGINE_BITMAP or SP_ENGINE_BLOCKS
     // Workgroup engine (wg_path.hip), source-major [slot][V] per slot:
-    int32_t *wg_dist = nullptr, *wg_queue = nullptr, *wg_loff = nullptr;  // loff: [slot][V + 2]
+    WgRec *wg_rec = nullptr;
+    int32_t *wg_queue = nullptr, *wg_loff = nullptr;  // loff: [slot][V + 2]
     double *wg_sigma = nullptr, *wg_delta = nullptr;
     WgSlotResult *wg_res = nullptr, *wg_res_host = nullptr;
     // Rows of width wg_ell_w (4 or 8; 0: rows read through the CSR offsets):

@@ -5,7 +5,11 @@
 // in StarPlat"; DAG semantics of Section 2.3.2), as on the per-source path:
 //   sigma(w) = sum over parents u (incoming row, CSR order) of sigma(u),
 //   delta(v) = sum over children w (outgoing row, CSR order) of
-//              (sigma(v) / sigma(w)) * (1 + delta(w)).
+//              (sigma(v) / sigma(w)) * (1 + delta(w))
+// (rows through the CSR offsets), or, regrouped as in the bitmap engine,
+//   delta(v) = sigma(v) * sum over children w of rho(w),
+//   rho(w) = (1 + delta(w)) / sigma(w)
+// (fixed-width rows, below).
 // What differs is the schedule.  On a road-like graph a source's BFS has
 // thousands of levels of a few hundred vertices each; the bitmap engine runs
 // the batch's sources in lockstep, one kernel per level for the whole batch,
@@ -18,19 +22,24 @@
 // and Bader, "Scalable and high performance betweenness centrality on the
 // GPU", SC 2014.)
 //
-// Layout, per slot s (source-major): dist[s*V + v], sigma[s*V + v],
-// delta[s*V + v], the BFS-order queue queue[s*V + i], and the level offsets
-// loff[s*(V+2) + l].  dist is filled with -1 before each pass; every other
-// value is written before it is read.  BC: for each vertex, the slots'
-// delta in ascending slot order, skipping unreached vertices and the
-// vertex's own source (dist <= 0).
+// Layout, per slot s (source-major): a 16-byte record rec[s*V + v] = {level
+// (-1: unreached), value}, sigma[s*V + v], delta[s*V + v], the BFS-order
+// queue queue[s*V + i] and the level offsets loff[s*(V+2) + l].  Records are
+// filled with level -1 before each pass; every other value is written before
+// it is read.  The record's value is unused by the CSR-offset kernel (it
+// keeps sigma and delta in their arrays); the fixed-width kernel holds sigma
+// there in the forward pass and rho once the reverse pass has finished the
+// vertex, so a neighbour costs one 16-byte load (level and value together).
+// BC: for each vertex, the slots' delta in ascending slot order, skipping
+// unreached vertices and the vertex's own source (level <= 0).
 //
 // Only the slot's own workgroup touches its arrays during the pass, so the
-// claim on dist is a workgroup-scope compare-and-swap and the reads of
-// levels another wave may have claimed are workgroup-scope atomic loads
-// (coherent within the CU, and served by the XCD's L2 rather than the
-// memory-side point device-scope atomics need).  Everything else is written
-// with plain stores by waves of the same workgroup and read after a barrier.
+// claim on a level is a workgroup-scope compare-and-swap, performed in the
+// XCD's L2.  The CSR-offset kernel reads levels another wave may have
+// claimed with workgroup-scope atomic loads; the fixed-width kernel reads
+// records with plain loads and invalidates the CU's L1 after each level
+// barrier instead.  Everything else is written with plain stores by waves of
+// the same workgroup and read after a barrier.
 //
 // Memory-level parallelism: a thread takes kEntries queue entries at once
 // and walks their rows kRowStep entries at a time; for all of them the
@@ -39,17 +48,20 @@
 // trips for kEntries x kRowStep adjacency entries.  Sums still run in CSR
 // order per vertex.
 //
-// Latency: a level is a chain of dependent round trips to memory, so on a
-// graph whose rows hold at most 8 entries the rows are copied once into a
-// fixed-width layout (W = 4 or 8 ids per vertex, -1 padding): a vertex's
-// neighbours come in one load instead of an offset load followed by an id
-// load.  With it a discovery step is queue entry -> row -> claim (a
-// compare-and-swap straight away, which returns the level of a vertex
-// already reached), a path-count step queue entry -> row -> the neighbours'
-// level and path count together, and a reverse step queue entry -> row (and
-// the vertex's own path count) -> the neighbours' level, path count and
-// dependency together: values of a neighbour that turns out not to be a
-// parent (child) are loaded and dropped.
+// Fixed-width rows: on a graph whose rows hold at most 8 entries the rows
+// are copied once into a fixed-width layout (W = 4 or 8 ids per vertex, -1
+// padding), so a vertex's neighbours come in one load instead of an offset
+// load followed by an id load.  A discovery step is then queue entry -> row
+// -> claim, a path-count step queue entry -> row -> the neighbours' records,
+// and a reverse step queue entry -> row (and the vertex's own record) -> the
+// neighbours' records; the record of a neighbour that turns out not to be a
+// parent (child) is loaded and dropped.  Measured on a 2048 x 2048 grid
+// (64 sources, one per workgroup): a level costs about 46 us and scales with
+// the frontier, not with the chain of round trips -- the 64 workgroups'
+// record and row lines (128 bytes fetched per 16 used) keep the memory
+// system busy; spreading a source over 2 or 4 workgroups of one XCD, with a
+// barrier between the groups' phases, was slower (201 and 339 ms against
+// 181 ms for the whole pass).
 #include "common.h"
 #include "devutil.h"
 
@@ -88,9 +100,10 @@ __device__ __forceinline__ int32_t claim_level(int32_t *p, int32_t lvl) {
     return expected;
 }
 
-__global__ void k_wg_fill(int32_t *dist, int64_t count) {
+__global__ void k_wg_fill(WgRec *rec, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) dist[i] = -1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        rec[i] = WgRec{-1, 0, 0.0};
 }
 
 // Fixed-width copy of the rows: ell[v * W + k] = k-th neighbour, -1 past the
@@ -106,22 +119,63 @@ __global__ void k_wg_ell(const int32_t *__restrict__ rp, const int32_t *__restri
     }
 }
 
+// The loads below are issued unconditionally, from a valid address (row 0,
+// vertex 0) when there is nothing to read, and their results dropped: a load
+// under a branch of its own is waited for before the branch closes, which
+// would turn a group of independent loads into a chain of round trips.
+
+// queue[i] for i < end, else -1 (i < end for some lane of the call, end > 0).
+__device__ __forceinline__ int32_t at_or_none(const int32_t *queue, int32_t i, int32_t end) {
+    const int32_t x = queue[min(i, end - 1)];
+    return i < end ? x : -1;
+}
+
+// Level barrier of the fixed-width kernel, whose records are read with plain
+// loads: after the workgroup barrier the CU's L1 is invalidated, so the next
+// phase sees in L2 the levels other waves claimed there with
+// compare-and-swap and the values they stored.
+__device__ __forceinline__ void sync_records() {
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// A record in one 16-byte load (the empty asm marks the pad word used, so
+// the load is not narrowed into a 4-byte and an 8-byte one: two requests).
+__device__ __forceinline__ WgRec load_rec(const WgRec *p) {
+    int4 x = *reinterpret_cast<const int4 *>(p);
+    asm("" : "+v"(x.y));
+    WgRec r;
+    r.dist = x.x;
+    r.pad = x.y;
+    r.val = __hiloint2double(x.w, x.z);
+    return r;
+}
+
+// Append x to the queue where `take` holds: one LDS add per wave reserves
+// the wave's entries, lanes in lane order.
+__device__ __forceinline__ void append_wave(bool take, int32_t x, int32_t *queue, int32_t *s_tail) {
+    const unsigned long long bal = __ballot(take);
+    if (!bal) return;
+    const int first = __ffsll((long long)bal) - 1;
+    int32_t at = 0;
+    if (lane_id() == first) at = atomicAdd(s_tail, __popcll(bal));  // LDS
+    at = __shfl(at, first, kWave);
+    const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (take) queue[at + r] = x;
+}
+
 // Row of v in the fixed-width layout (v < 0: an empty row).
 template <int W>
 __device__ __forceinline__ void ell_row(const int32_t *__restrict__ ell, int32_t v, int32_t (&nb)[W]) {
-    if (v < 0) {
-#pragma unroll
-        for (int k = 0; k < W; ++k) nb[k] = -1;
-        return;
-    }
-    const int4 *r = reinterpret_cast<const int4 *>(ell + (int64_t)v * W);
+    const int4 *r = reinterpret_cast<const int4 *>(ell + (int64_t)max(v, 0) * W);
 #pragma unroll
     for (int q = 0; q < W / 4; ++q) {
         const int4 x = r[q];
-        nb[4 * q + 0] = x.x;
-        nb[4 * q + 1] = x.y;
-        nb[4 * q + 2] = x.z;
-        nb[4 * q + 3] = x.w;
+        nb[4 * q + 0] = v >= 0 ? x.x : -1;
+        nb[4 * q + 1] = v >= 0 ? x.y : -1;
+        nb[4 * q + 2] = v >= 0 ? x.z : -1;
+        nb[4 * q + 3] = v >= 0 ? x.w : -1;
     }
 }
 
@@ -131,13 +185,13 @@ template <int BS, int W>
 __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ ell,
                                                   const int32_t *__restrict__ ell_in,
                                                   const int32_t *__restrict__ slot_src, int32_t n,
-                                                  int32_t *dist_all, double *sigma_all, double *delta_all,
+                                                  WgRec *rec_all, double *sigma_all, double *delta_all,
                                                   int32_t *queue_all, int32_t *loff_all, WgSlotResult *res,
                                                   unsigned long long *prof) {
     constexpr int E = W == 8 ? 2 : kEntries;  // entries in flight per thread (registers)
     const int32_t slot = blockIdx.x;
     const int64_t base = (int64_t)slot * n;
-    int32_t *dist = dist_all + base;
+    WgRec *rec = rec_all + base;
     double *sigma = sigma_all + base;
     double *delta = delta_all + base;
     int32_t *queue = queue_all + base;
@@ -147,7 +201,8 @@ __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ el
     __shared__ double s_max[BS / kWave];
     __shared__ unsigned long long s_red[1];
     if (threadIdx.x == 0) {
-        dist[src] = 0;
+        rec[src].dist = 0;
+        rec[src].val = 1.0;
         sigma[src] = 1.0;
         queue[0] = src;
         loff[0] = 0;
@@ -155,60 +210,59 @@ __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ el
         s_tail = 1;
         s_flag = 0;
     }
-    __syncthreads();
+    sync_records();
     int32_t lo = 0, hi = 1, level = 0;
     double my_max = 1.0;
     unsigned long long my_edges = 0, my_pairs = 0;
     for (;;) {
         // Discovery of level + 1 from the frontier [lo, hi): the claim
-        // (dist -1 -> level + 1) decides who appends the vertex.
+        // (dist -1 -> level + 1) decides who appends the vertex; a wave
+        // reserves its appends with one LDS add.
         for (int32_t i0 = lo + (int32_t)threadIdx.x; i0 < hi; i0 += BS * E) {
             int32_t v[E], nb[E][W], old[E][W];
 #pragma unroll
-            for (int u = 0; u < E; ++u) v[u] = i0 + u * BS < hi ? queue[i0 + u * BS] : -1;
+            for (int u = 0; u < E; ++u) v[u] = at_or_none(queue, i0 + u * BS, hi);
 #pragma unroll
             for (int u = 0; u < E; ++u) ell_row<W>(ell, v[u], nb[u]);
 #pragma unroll
             for (int u = 0; u < E; ++u)
 #pragma unroll
-                for (int k = 0; k < W; ++k) old[u][k] = nb[u][k] >= 0 ? claim_level(&dist[nb[u][k]], level + 1) : 0;
+                for (int k = 0; k < W; ++k) old[u][k] = nb[u][k] >= 0 ? claim_level(&rec[nb[u][k]].dist, level + 1) : 0;
 #pragma unroll
             for (int u = 0; u < E; ++u)
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
                     if (nb[u][k] >= 0) ++my_edges;
-                    if (nb[u][k] >= 0 && old[u][k] == -1) queue[atomicAdd(&s_tail, 1)] = nb[u][k];  // LDS
+                    append_wave(nb[u][k] >= 0 && old[u][k] == -1, nb[u][k], queue, &s_tail);
                 }
         }
-        __syncthreads();
+        sync_records();
         const int32_t tail = s_tail;
         if (tail == hi) break;  // block-uniform: every thread read the same tail
         // Path counts of the new vertices [hi, tail): parents over incoming
-        // rows, added in row order.
+        // rows, added in row order; one record load per neighbour.
         for (int32_t j0 = hi + (int32_t)threadIdx.x; j0 < tail; j0 += BS * E) {
-            int32_t w[E], p[E][W], d[E][W];
-            double x[E][W];
+            int32_t w[E], p[E][W];
+            WgRec r[E][W];
 #pragma unroll
-            for (int u = 0; u < E; ++u) w[u] = j0 + u * BS < tail ? queue[j0 + u * BS] : -1;
+            for (int u = 0; u < E; ++u) w[u] = at_or_none(queue, j0 + u * BS, tail);
 #pragma unroll
             for (int u = 0; u < E; ++u) ell_row<W>(ell_in, w[u], p[u]);
 #pragma unroll
             for (int u = 0; u < E; ++u)
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    d[u][k] = p[u][k] >= 0 ? ld_level(&dist[p[u][k]]) : -1;
-                    x[u][k] = p[u][k] >= 0 ? sigma[p[u][k]] : 0.0;  // kept for parents only
-                }
+                for (int k = 0; k < W; ++k) r[u][k] = load_rec(&rec[max(p[u][k], 0)]);
 #pragma unroll
             for (int u = 0; u < E; ++u) {
                 double acc = 0.0;
 #pragma unroll
                 for (int k = 0; k < W; ++k)
-                    if (d[u][k] == level) {
-                        acc += x[u][k];
+                    if (p[u][k] >= 0 && r[u][k].dist == level) {
+                        acc += r[u][k].val;
                         ++my_pairs;
                     }
                 if (w[u] >= 0) {
+                    rec[w[u]].val = acc;
                     sigma[w[u]] = acc;
                     my_max = fmax(my_max, acc);
                     if (sigma_is_large(acc)) s_flag = 1;
@@ -216,47 +270,50 @@ __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ el
             }
         }
         if (threadIdx.x == 0) loff[level + 2] = tail;
-        __syncthreads();
+        sync_records();
         lo = hi;
         hi = tail;
         ++level;
     }
     // Reverse sweep from the deepest level up to level 1 (the deepest has no
     // children: its delta is 0); children over outgoing rows, in row order.
+    // A finished vertex's record holds rho = (1 + delta) / sigma, so a parent
+    // reads one record per neighbour: delta(v) = sigma(v) * sum of its
+    // children's rho (the regrouping of the bitmap engine).
     for (int32_t l = level; l >= 1; --l) {
         const int32_t a = loff[l], z = loff[l + 1];
         for (int32_t j0 = a + (int32_t)threadIdx.x; j0 < z; j0 += BS * E) {
-            int32_t v[E], nb[E][W], d[E][W];
-            double sv[E], sw[E][W], dw[E][W];
+            int32_t v[E], nb[E][W];
+            double sv[E];
+            WgRec r[E][W];
 #pragma unroll
-            for (int u = 0; u < E; ++u) v[u] = j0 + u * BS < z ? queue[j0 + u * BS] : -1;
+            for (int u = 0; u < E; ++u) v[u] = at_or_none(queue, j0 + u * BS, z);
 #pragma unroll
             for (int u = 0; u < E; ++u) {
                 ell_row<W>(ell, v[u], nb[u]);
-                sv[u] = v[u] >= 0 ? sigma[v[u]] : 0.0;
+                sv[u] = rec[max(v[u], 0)].val;  // sigma(v)
             }
 #pragma unroll
             for (int u = 0; u < E; ++u)
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    const int32_t y = nb[u][k];
-                    d[u][k] = y >= 0 ? ld_level(&dist[y]) : -1;
-                    sw[u][k] = y >= 0 ? sigma[y] : 1.0;  // kept for children only
-                    dw[u][k] = y >= 0 ? delta[y] : 0.0;
-                }
+                for (int k = 0; k < W; ++k) r[u][k] = load_rec(&rec[max(nb[u][k], 0)]);
 #pragma unroll
             for (int u = 0; u < E; ++u) {
                 double acc = 0.0;
 #pragma unroll
                 for (int k = 0; k < W; ++k)
-                    if (d[u][k] == l + 1) {
-                        acc += (sv[u] / sw[u][k]) * (1.0 + dw[u][k]);
+                    if (nb[u][k] >= 0 && r[u][k].dist == l + 1) {
+                        acc += r[u][k].val;
                         ++my_pairs;
                     }
-                if (v[u] >= 0) delta[v[u]] = acc;
+                if (v[u] >= 0) {
+                    const double dv = sv[u] * acc;
+                    delta[v[u]] = dv;
+                    rec[v[u]].val = (1.0 + dv) / sv[u];
+                }
             }
         }
-        __syncthreads();
+        sync_records();
     }
     my_max = wave_max_f64(my_max);
     if (lane_id() == 0) s_max[threadIdx.x / kWave] = my_max;
@@ -282,12 +339,12 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
                                               const int32_t *__restrict__ rpi,
                                               const int32_t *__restrict__ cii,
                                               const int32_t *__restrict__ slot_src, int32_t n,
-                                              int32_t *dist_all, double *sigma_all, double *delta_all,
+                                              WgRec *rec_all, double *sigma_all, double *delta_all,
                                               int32_t *queue_all, int32_t *loff_all, WgSlotResult *res,
                                               unsigned long long *prof) {
     const int32_t slot = blockIdx.x;
     const int64_t base = (int64_t)slot * n;
-    int32_t *dist = dist_all + base;
+    WgRec *rec = rec_all + base;
     double *sigma = sigma_all + base;
     double *delta = delta_all + base;
     int32_t *queue = queue_all + base;
@@ -297,7 +354,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
     __shared__ double s_max[BS / kWave];
     __shared__ unsigned long long s_red[1];
     if (threadIdx.x == 0) {
-        dist[src] = 0;
+        rec[src].dist = 0;
         sigma[src] = 1.0;
         queue[0] = src;
         loff[0] = 0;
@@ -324,12 +381,12 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
-                    for (int t = 0; t < kRowStep; ++t) d[u][t] = w[u][t] >= 0 ? ld_level(&dist[w[u][t]]) : 0;
+                    for (int t = 0; t < kRowStep; ++t) d[u][t] = w[u][t] >= 0 ? ld_level(&rec[w[u][t]].dist) : 0;
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
                     for (int t = 0; t < kRowStep; ++t)
-                        old[u][t] = d[u][t] < 0 ? claim_level(&dist[w[u][t]], level + 1) : 0;
+                        old[u][t] = d[u][t] < 0 ? claim_level(&rec[w[u][t]].dist, level + 1) : 0;
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
@@ -359,7 +416,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
-                    for (int t = 0; t < kRowStep; ++t) par[u][t] = p[u][t] >= 0 && ld_level(&dist[p[u][t]]) == level;
+                    for (int t = 0; t < kRowStep; ++t) par[u][t] = p[u][t] >= 0 && ld_level(&rec[p[u][t]].dist) == level;
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
@@ -418,7 +475,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
-                    for (int t = 0; t < kRowStep; ++t) ch[u][t] = w[u][t] >= 0 && ld_level(&dist[w[u][t]]) == l + 1;
+                    for (int t = 0; t < kRowStep; ++t) ch[u][t] = w[u][t] >= 0 && ld_level(&rec[w[u][t]].dist) == l + 1;
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
@@ -463,7 +520,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
 // ascending slot order; consecutive slots with the same output array are
 // summed in a register.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, const int32_t *__restrict__ dist,
+__global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, const WgRec *__restrict__ rec,
                                                   const double *__restrict__ delta, SlotTable tbl,
                                                   unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
@@ -480,7 +537,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, con
                 acc = out[v];
             }
             const int64_t o = (int64_t)s * n + v;
-            if (dist[o] > 0) {
+            if (rec[o].dist > 0) {
                 acc += delta[o];
                 ++my_items;
             }
@@ -492,12 +549,12 @@ __global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, con
 
 // Per-slot results into the caller's source-major arrays (sp_batch_levels):
 // dist as is, sigma of reached vertices, delta of vertices below the source.
-__global__ void k_wg_extract(int64_t count, const int32_t *__restrict__ dist, const double *__restrict__ sigma,
+__global__ void k_wg_extract(int64_t count, const WgRec *__restrict__ rec, const double *__restrict__ sigma,
                              const double *__restrict__ delta, int32_t *out_dist, double *out_sigma,
                              double *out_delta) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        const int32_t d = dist[i];
+        const int32_t d = rec[i].dist;
         if (out_dist) out_dist[i] = d;
         if (out_sigma) out_sigma[i] = d >= 0 ? sigma[i] : 0.0;
         if (out_delta) out_delta[i] = d > 0 ? delta[i] : 0.0;
@@ -515,12 +572,13 @@ static int32_t ell_width(sp_graph g) {
 size_t wg_ws_bytes(sp_graph g, int32_t width) {
     const size_t V = (size_t)std::max(g->n, 1);
     const size_t ell = V * (size_t)ell_width(g) * 4 * (g->directed ? 2 : 1);
-    return (size_t)width * (V * (4 + 8 + 8 + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult) + ell;
+    return (size_t)width * (V * (sizeof(WgRec) + 8 + 8 + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult) +
+           ell;
 }
 
 sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
     const size_t V = (size_t)std::max(g->n, 1), W = (size_t)width;
-    SP_TRY(dev_alloc((void **)&ws.wg_dist, W * V * 4));
+    SP_TRY(dev_alloc((void **)&ws.wg_rec, W * V * sizeof(WgRec)));
     SP_TRY(dev_alloc((void **)&ws.wg_sigma, W * V * 8));
     SP_TRY(dev_alloc((void **)&ws.wg_delta, W * V * 8));
     SP_TRY(dev_alloc((void **)&ws.wg_queue, W * V * 4));
@@ -538,7 +596,7 @@ sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
 }
 
 void wg_ws_free(BatchWorkspace &ws) {
-    dev_free(ws.wg_dist);
+    dev_free(ws.wg_rec);
     dev_free(ws.wg_sigma);
     dev_free(ws.wg_delta);
     dev_free(ws.wg_queue);
@@ -550,7 +608,8 @@ void wg_ws_free(BatchWorkspace &ws) {
     ws.wg_ell_w = 0;
     ws.wg_ell_built = false;
     if (ws.wg_res_host) (void)hipHostFree(ws.wg_res_host);
-    ws.wg_dist = ws.wg_queue = ws.wg_loff = nullptr;
+    ws.wg_rec = nullptr;
+    ws.wg_queue = ws.wg_loff = nullptr;
     ws.wg_sigma = ws.wg_delta = nullptr;
     ws.wg_res = ws.wg_res_host = nullptr;
 }
@@ -564,7 +623,7 @@ static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, 
     int32_t *h_src = (int32_t *)ws.staging;
     for (int32_t i = 0; i < kSlots; ++i) h_src[i] = i < nslots ? srcs[i] : -1;
     SP_HIP(hipMemcpyAsync(ws.slot_src, h_src, kSlots * 4, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_wg_fill, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, ws.wg_dist, count);
+    hipLaunchKernelGGL(k_wg_fill, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, ws.wg_rec, count);
     const int ew = ws.wg_ell_w;
     if (ew && !ws.wg_ell_built) {
         auto build = ew == 4 ? k_wg_ell<4> : k_wg_ell<8>;
@@ -581,22 +640,22 @@ static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, 
         const int32_t *ell_in = g->directed ? ws.wg_ell_in : ws.wg_ell;
         if (ew == 4)
             hipLaunchKernelGGL((k_wg_bc_ell<BS, 4>), dim3(nslots), dim3(BS), 0, s, (const int32_t *)ws.wg_ell,
-                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta,
+                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_rec, ws.wg_sigma, ws.wg_delta,
                                ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
         else if (ew == 8)
             hipLaunchKernelGGL((k_wg_bc_ell<BS, 8>), dim3(nslots), dim3(BS), 0, s, (const int32_t *)ws.wg_ell,
-                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta,
+                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_rec, ws.wg_sigma, ws.wg_delta,
                                ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
         else
             hipLaunchKernelGGL(k_wg_bc<BS>, dim3(nslots), dim3(BS), 0, s, (const int32_t *)g->row_ptr,
                                (const int32_t *)g->col_idx, (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
-                               (const int32_t *)ws.slot_src, n, ws.wg_dist, ws.wg_sigma, ws.wg_delta,
+                               (const int32_t *)ws.slot_src, n, ws.wg_rec, ws.wg_sigma, ws.wg_delta,
                                ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
     }
     SP_HIP(hipGetLastError());
     if (ex)
         hipLaunchKernelGGL(k_wg_extract, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, count,
-                           (const int32_t *)ws.wg_dist, (const double *)ws.wg_sigma,
+                           (const WgRec *)ws.wg_rec, (const double *)ws.wg_sigma,
                            (const double *)ws.wg_delta, ex->dist, ex->sigma, ex->delta);
     SlotTable tbl{};
     bool any_out = false;
@@ -607,7 +666,7 @@ static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, 
     if (any_out) {
         ProfScope ps(P_MS_BC, s);
         hipLaunchKernelGGL(k_wg_bc_sum<BS>, dim3(grid_for(n, BS, device_cu_count() * 8)), dim3(BS), 0, s, n,
-                           nslots, (const int32_t *)ws.wg_dist, (const double *)ws.wg_delta, tbl,
+                           nslots, (const WgRec *)ws.wg_rec, (const double *)ws.wg_delta, tbl,
                            prof_counters(P_MS_BC));
     }
     SP_HIP(hipGetLastError());
