@@ -508,7 +508,7 @@ def per_source_benchmark(sp, torch, workload, n_sources, profile_sample=32, orac
     return res
 
 
-def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_sources=2):
+def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_sources=2, compare_bitmap=True):
     """Batched BC on the road-like grid: every source in one batch, in the
     library's automatic engine for road-like graphs (one workgroup per source,
     the whole pass in one launch); wall time per pass with the graph resident
@@ -537,14 +537,16 @@ def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_source
     best = float(np.min(times))
     kernels, roofline = profile_kernels(sp, lambda: sp.sp_bc_batch(g, srcs, out), 1)
     attach_traffic(roofline, "bc_batch_" + workload)
-    bitmap = {"engine": sp.SP_ENGINE_BITMAP}
-    sp.sp_bc_batch(g, srcs, out, config=bitmap)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sp.sp_bc_batch(g, srcs, out, config=bitmap)
-    torch.cuda.synchronize()
-    bitmap_ms = (time.perf_counter() - t0) * 1e3
-    bitmap_levels = sp.sp_get_last_stats()["graph_launches"]
+    bitmap_ms = bitmap_levels = None
+    if compare_bitmap:
+        bitmap = {"engine": sp.SP_ENGINE_BITMAP}
+        sp.sp_bc_batch(g, srcs, out, config=bitmap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sp.sp_bc_batch(g, srcs, out, config=bitmap)
+        torch.cuda.synchronize()
+        bitmap_ms = round((time.perf_counter() - t0) * 1e3, 1)
+        bitmap_levels = sp.sp_get_last_stats()["graph_launches"]
     cs = srcs[:oracle_sources]
     t0 = time.perf_counter()
     ref = oracle.bc(rp, ci, cs)
@@ -560,7 +562,7 @@ def road_batched_benchmark(sp, torch, workload, n_sources, runs=3, oracle_source
             "block_size": stats["block_size"],
             "chunk_levels": stats["chunk_levels"], "graph_launches": stats["graph_launches"],
             "roofline": roofline, "kernels": kernels,
-            "bitmap_engine": {"ms_per_pass": round(bitmap_ms, 1), "graph_launches": bitmap_levels},
+            "bitmap_engine": {"ms_per_pass": bitmap_ms, "graph_launches": bitmap_levels},
             "cpu_baseline": {"value": len(cs) * m / cpu_s, "unit": "TEPS", "cores": 1, "kind": "oracle",
                              "sample": "first %d sources, single-threaded C oracle, %.1f s" % (len(cs), cpu_s)},
             "parity": dict(sources=len(cs), **bc_parity(got.cpu().numpy(), ref))}
@@ -711,6 +713,8 @@ def main():
                     help="run only the SSSP legs and print their JSON object")
     ap.add_argument("--only-pagerank", action="store_true",
                     help="run only the PageRank legs and print their JSON object")
+    ap.add_argument("--road-no-bitmap", action="store_true",
+                    help="skip the road leg's timing of the other (bitmap) engine (profiling runs)")
     ap.add_argument("--only-road", action="store_true",
                     help="run only the road-like batched BC legs and print their JSON object")
     ap.add_argument("--only-serving", action="store_true",
@@ -769,7 +773,8 @@ def main():
         if args.only_serving:
             legs["serving"] = serving_benchmark(sp, torch, args.serving_requests)
         if args.only_road:
-            legs["road_batched"] = {wl: road_batched_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+            legs["road_batched"] = {wl: road_batched_benchmark(sp, torch, wl, int(ns),
+                                                               compare_bitmap=not args.road_no_bitmap) for wl, ns in
                                     (leg.split(":") for leg in filter(None, args.road_batched.split(",")))}
         if args.only_directed:
             legs["directed_bc"] = {wl: directed_benchmark(sp, torch, wl, int(ns)) for wl, ns in
@@ -969,7 +974,8 @@ def main():
     del out
     per_source_legs = {wl: per_source_benchmark(sp, torch, wl, int(ns)) for wl, ns in
                        (leg.split(":") for leg in filter(None, args.per_source_legs.split(",")))}
-    road = {wl: road_batched_benchmark(sp, torch, wl, int(ns)) for wl, ns in
+    road = {wl: road_batched_benchmark(sp, torch, wl, int(ns), compare_bitmap=not args.road_no_bitmap)
+            for wl, ns in
             (leg.split(":") for leg in filter(None, args.road_batched.split(",")))}
     sssp = {}
     for leg in filter(None, args.sssp_sources.split(",")):
