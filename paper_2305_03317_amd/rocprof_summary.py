@@ -41,7 +41,7 @@ FAMILY = {
     "k_src_sigma": "src_sigma", "k_src_sigma_hub": "src_sigma_hub", "k_src_delta": "src_delta",
     "k_src_delta_hub": "src_delta_hub", "k_sssp_push": "sssp_push", "k_sssp_pull": "sssp_pull",
     "k_pr_pull": "pr_pull", "k_pr_hub_fin": "pr_hub", "k_tc_count": "tc_count",
-    "k_wg_bc": "wg_bc", "k_wg_bc_sum": "wg_bc_sum", "k_ms_sigma_push": "ms_sigma_push",
+    "k_wg_bc": "wg_bc", "k_wg_bc_ell": "wg_bc", "k_wg_bc_sum": "wg_bc_sum", "k_ms_sigma_push": "ms_sigma_push",
 }
 
 
