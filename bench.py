@@ -579,7 +579,7 @@ def cpu_model():
     return None
 
 
-def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=200):
+def serving_benchmark(sp, torch, n_requests, seed=2005, budget_gb=230):
     """Serving workload: eight resident graphs, seeded requests (graph uniform,
     1..512 sources log-uniform), continuous batching by the library's server.
     Phase "burst" submits every request at once (saturation throughput);

@@ -337,16 +337,13 @@ struct SlotTable {
 };
 
 // Per-slot summary written by the workgroup engine.
-// Blocks engine, per (slot, vertex): the BFS level (-1 unreached), a value
-// -- sigma after the forward pass, rho = (1 + delta) / sigma once the
-// reverse pass has finished the vertex (fixed-width rows; unused by the
-// CSR-offset kernel) -- and the vertex's sigma and delta.
-struct alignas(32) WgRec {
+// Blocks engine, per (slot, vertex): the BFS level (-1 unreached) and a
+// value -- sigma after the forward pass; with fixed-width rows, rho =
+// (1 + delta) / sigma once the reverse pass has finished the vertex.
+struct alignas(16) WgRec {
     int32_t dist;
     int32_t pad;
     double val;
-    double sigma;  // the vertex's path count and dependency, kept beside its
-    double delta;  // level so that a vertex's stores dirty one 32-byte sector
 };
 
 struct WgSlotResult {
@@ -368,6 +365,7 @@ struct BatchWorkspace {
     // Workgroup engine (wg_path.hip), source-major [slot][V] per slot:
     WgRec *wg_rec = nullptr;
     int32_t *wg_queue = nullptr, *wg_loff = nullptr;  // loff: [slot][V + 2]
+    double *wg_delta = nullptr;  // [slot][V]
     WgSlotResult *wg_res = nullptr, *wg_res_host = nullptr;
     // Rows of width wg_ell_w (4 or 8; 0: rows read through the CSR offsets):
     // neighbour k of v at [v * w + k], -1 past the row's end; the incoming

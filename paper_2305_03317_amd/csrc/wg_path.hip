@@ -22,16 +22,15 @@
 // and Bader, "Scalable and high performance betweenness centrality on the
 // GPU", SC 2014.)
 //
-// Layout, per slot s (source-major): a 32-byte record rec[s*V + v] = {level
-// (-1: unreached), value, sigma, delta}, the BFS-order queue queue[s*V + i]
-// and the level offsets loff[s*(V+2) + l].  Records are filled with level -1
-// before each pass; every other field is written before it is read.  The
-// value is unused by the CSR-offset kernel; the fixed-width kernel holds
-// sigma there in the forward pass and rho once the reverse pass has finished
-// the vertex, so a neighbour costs one 16-byte load (level and value
-// together), and all the stores a vertex takes land in its one 32-byte
-// sector (scattered 8-byte stores to separate arrays each dirtied a line of
-// their own).
+// Layout, per slot s (source-major): a 16-byte record rec[s*V + v] = {level
+// (-1: unreached), value}, delta[s*V + v], the BFS-order queue
+// queue[s*V + i] and the level offsets loff[s*(V+2) + l] -- 32 bytes per
+// vertex and slot.  Records are filled with level -1 before each pass; every
+// other field is written before it is read.  The value is sigma after the
+// forward pass; the fixed-width kernel replaces it by rho once the reverse
+// pass has finished the vertex, so a neighbour costs one 16-byte load (level
+// and value together).  sigma itself is written out only for sp_batch_levels
+// (straight into the caller's array).
 // BC: for each vertex, the slots' delta in ascending slot order, skipping
 // unreached vertices and the vertex's own source (level <= 0).
 //
@@ -187,13 +186,15 @@ template <int BS, int W>
 __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ ell,
                                                   const int32_t *__restrict__ ell_in,
                                                   const int32_t *__restrict__ slot_src, int32_t n,
-                                                  WgRec *rec_all,
+                                                  WgRec *rec_all, double *delta_all, double *sigma_out,
                                                   int32_t *queue_all, int32_t *loff_all, WgSlotResult *res,
                                                   unsigned long long *prof) {
     constexpr int E = W == 8 ? 2 : kEntries;  // entries in flight per thread (registers)
     const int32_t slot = blockIdx.x;
     const int64_t base = (int64_t)slot * n;
     WgRec *rec = rec_all + base;
+    double *delta = delta_all + base;
+    double *sig_out = sigma_out ? sigma_out + base : nullptr;  // sp_batch_levels' sigma
     int32_t *queue = queue_all + base;
     int32_t *loff = loff_all + (int64_t)slot * ((int64_t)n + 2);
     const int32_t src = slot_src[slot];
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ el
     if (threadIdx.x == 0) {
         rec[src].dist = 0;
         rec[src].val = 1.0;
-        rec[src].sigma = 1.0;
+        if (sig_out) sig_out[src] = 1.0;
         queue[0] = src;
         loff[0] = 0;
         loff[1] = 1;
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ el
                     }
                 if (w[u] >= 0) {
                     rec[w[u]].val = acc;
-                    rec[w[u]].sigma = acc;
+                    if (sig_out) sig_out[w[u]] = acc;
                     my_max = fmax(my_max, acc);
                     if (sigma_is_large(acc)) s_flag = 1;
                 }
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc_ell(const int32_t *__restrict__ el
                     }
                 if (v[u] >= 0) {
                     const double dv = sv[u] * acc;
-                    rec[v[u]].delta = dv;
+                    delta[v[u]] = dv;
                     rec[v[u]].val = (1.0 + dv) / sv[u];
                 }
             }
@@ -339,12 +340,14 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
                                               const int32_t *__restrict__ rpi,
                                               const int32_t *__restrict__ cii,
                                               const int32_t *__restrict__ slot_src, int32_t n,
-                                              WgRec *rec_all,
+                                              WgRec *rec_all, double *delta_all, double *sigma_out,
                                               int32_t *queue_all, int32_t *loff_all, WgSlotResult *res,
                                               unsigned long long *prof) {
     const int32_t slot = blockIdx.x;
     const int64_t base = (int64_t)slot * n;
     WgRec *rec = rec_all + base;
+    double *delta = delta_all + base;
+    double *sig_out = sigma_out ? sigma_out + base : nullptr;  // sp_batch_levels' sigma
     int32_t *queue = queue_all + base;
     int32_t *loff = loff_all + (int64_t)slot * ((int64_t)n + 2);
     const int32_t src = slot_src[slot];
@@ -353,7 +356,8 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
     __shared__ unsigned long long s_red[1];
     if (threadIdx.x == 0) {
         rec[src].dist = 0;
-        rec[src].sigma = 1.0;
+        rec[src].val = 1.0;
+        if (sig_out) sig_out[src] = 1.0;
         queue[0] = src;
         loff[0] = 0;
         loff[1] = 1;
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
-                    for (int t = 0; t < kRowStep; ++t) x[u][t] = par[u][t] ? rec[p[u][t]].sigma : 0.0;
+                    for (int t = 0; t < kRowStep; ++t) x[u][t] = par[u][t] ? rec[p[u][t]].val : 0.0;
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
@@ -432,7 +436,8 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
             for (int u = 0; u < kEntries; ++u) {
                 const int32_t j = j0 + u * BS;
                 if (j < tail) {
-                    rec[queue[j]].sigma = acc[u];
+                    rec[queue[j]].val = acc[u];
+                    if (sig_out) sig_out[queue[j]] = acc[u];
                     my_max = fmax(my_max, acc[u]);
                     if (sigma_is_large(acc[u])) s_flag = 1;
                 }
@@ -459,7 +464,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
             for (int u = 0; u < kEntries; ++u) {
                 b[u] = v[u] >= 0 ? rp[v[u]] : 0;
                 e[u] = v[u] >= 0 ? rp[v[u] + 1] : 0;
-                sv[u] = v[u] >= 0 ? rec[v[u]].sigma : 0.0;
+                sv[u] = v[u] >= 0 ? rec[v[u]].val : 0.0;
                 len = max(len, e[u] - b[u]);
             }
             for (int32_t k0 = 0; k0 < len; k0 += kRowStep) {
@@ -478,8 +483,8 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
                 for (int u = 0; u < kEntries; ++u)
 #pragma unroll
                     for (int t = 0; t < kRowStep; ++t) {
-                        sw[u][t] = ch[u][t] ? rec[w[u][t]].sigma : 1.0;
-                        dw[u][t] = ch[u][t] ? rec[w[u][t]].delta : 0.0;
+                        sw[u][t] = ch[u][t] ? rec[w[u][t]].val : 1.0;
+                        dw[u][t] = ch[u][t] ? delta[w[u][t]] : 0.0;
                     }
 #pragma unroll
                 for (int u = 0; u < kEntries; ++u)
@@ -492,7 +497,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
             }
 #pragma unroll
             for (int u = 0; u < kEntries; ++u)
-                if (v[u] >= 0) rec[v[u]].delta = acc[u];
+                if (v[u] >= 0) delta[v[u]] = acc[u];
         }
         __syncthreads();
     }
@@ -519,7 +524,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc(const int32_t *__restrict__ rp, co
 // summed in a register.
 template <int BS>
 __global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, const WgRec *__restrict__ rec,
-                                                  SlotTable tbl,
+                                                  const double *__restrict__ delta, SlotTable tbl,
                                                   unsigned long long *prof) {
     __shared__ unsigned long long s_red[1];
     unsigned long long my_items = 0;
@@ -536,7 +541,7 @@ __global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, con
             }
             const int64_t o = (int64_t)s * n + v;
             if (rec[o].dist > 0) {
-                acc += rec[o].delta;
+                acc += delta[o];
                 ++my_items;
             }
         }
@@ -547,14 +552,15 @@ __global__ __launch_bounds__(BS) void k_wg_bc_sum(int32_t n, int32_t nslots, con
 
 // Per-slot results into the caller's source-major arrays (sp_batch_levels):
 // dist as is, sigma of reached vertices, delta of vertices below the source.
-__global__ void k_wg_extract(int64_t count, const WgRec *__restrict__ rec, int32_t *out_dist, double *out_sigma,
+__global__ void k_wg_extract(int64_t count, const WgRec *__restrict__ rec, const double *__restrict__ delta,
+                             int32_t *out_dist, double *out_sigma,
                              double *out_delta) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         const int32_t d = rec[i].dist;
         if (out_dist) out_dist[i] = d;
-        if (out_sigma) out_sigma[i] = d >= 0 ? rec[i].sigma : 0.0;
-        if (out_delta) out_delta[i] = d > 0 ? rec[i].delta : 0.0;
+        if (out_sigma && d < 0) out_sigma[i] = 0.0;  // reached: written by the pass
+        if (out_delta) out_delta[i] = d > 0 ? delta[i] : 0.0;
     }
 }
 
@@ -569,12 +575,13 @@ static int32_t ell_width(sp_graph g) {
 size_t wg_ws_bytes(sp_graph g, int32_t width) {
     const size_t V = (size_t)std::max(g->n, 1);
     const size_t ell = V * (size_t)ell_width(g) * 4 * (g->directed ? 2 : 1);
-    return (size_t)width * (V * (sizeof(WgRec) + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult) + ell;
+    return (size_t)width * (V * (sizeof(WgRec) + 8 + 4) + (V + 2) * 4) + (size_t)width * sizeof(WgSlotResult) + ell;
 }
 
 sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
     const size_t V = (size_t)std::max(g->n, 1), W = (size_t)width;
     SP_TRY(dev_alloc((void **)&ws.wg_rec, W * V * sizeof(WgRec)));
+    SP_TRY(dev_alloc((void **)&ws.wg_delta, W * V * 8));
     SP_TRY(dev_alloc((void **)&ws.wg_queue, W * V * 4));
     SP_TRY(dev_alloc((void **)&ws.wg_loff, W * (V + 2) * 4));
     SP_TRY(dev_alloc((void **)&ws.wg_res, W * sizeof(WgSlotResult)));
@@ -591,6 +598,7 @@ sp_status wg_ws_alloc(sp_graph g, int32_t width, BatchWorkspace &ws) {
 
 void wg_ws_free(BatchWorkspace &ws) {
     dev_free(ws.wg_rec);
+    dev_free(ws.wg_delta);
     dev_free(ws.wg_queue);
     dev_free(ws.wg_loff);
     dev_free(ws.wg_res);
@@ -601,6 +609,7 @@ void wg_ws_free(BatchWorkspace &ws) {
     ws.wg_ell_built = false;
     if (ws.wg_res_host) (void)hipHostFree(ws.wg_res_host);
     ws.wg_rec = nullptr;
+    ws.wg_delta = nullptr;
     ws.wg_queue = ws.wg_loff = nullptr;
     ws.wg_res = ws.wg_res_host = nullptr;
 }
@@ -631,22 +640,23 @@ static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, 
         const int32_t *ell_in = g->directed ? ws.wg_ell_in : ws.wg_ell;
         if (ew == 4)
             hipLaunchKernelGGL((k_wg_bc_ell<BS, 4>), dim3(nslots), dim3(BS), 0, s, (const int32_t *)ws.wg_ell,
-                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_rec,
+                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_rec, ws.wg_delta, ex ? ex->sigma : nullptr,
                                ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
         else if (ew == 8)
             hipLaunchKernelGGL((k_wg_bc_ell<BS, 8>), dim3(nslots), dim3(BS), 0, s, (const int32_t *)ws.wg_ell,
-                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_rec,
+                               ell_in, (const int32_t *)ws.slot_src, n, ws.wg_rec, ws.wg_delta, ex ? ex->sigma : nullptr,
                                ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
         else
             hipLaunchKernelGGL(k_wg_bc<BS>, dim3(nslots), dim3(BS), 0, s, (const int32_t *)g->row_ptr,
                                (const int32_t *)g->col_idx, (const int32_t *)g->rp_in, (const int32_t *)g->ci_in,
-                               (const int32_t *)ws.slot_src, n, ws.wg_rec,
+                               (const int32_t *)ws.slot_src, n, ws.wg_rec, ws.wg_delta, ex ? ex->sigma : nullptr,
                                ws.wg_queue, ws.wg_loff, ws.wg_res, prof_counters(P_WG_BC));
     }
     SP_HIP(hipGetLastError());
     if (ex)
         hipLaunchKernelGGL(k_wg_extract, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, count,
-                           (const WgRec *)ws.wg_rec, ex->dist, ex->sigma, ex->delta);
+                           (const WgRec *)ws.wg_rec, (const double *)ws.wg_delta, ex->dist, ex->sigma,
+                           ex->delta);
     SlotTable tbl{};
     bool any_out = false;
     for (int32_t i = 0; i < kSlots; ++i) {
@@ -656,7 +666,7 @@ static sp_status wg_run_bs(sp_graph g, BatchWorkspace &ws, const int32_t *srcs, 
     if (any_out) {
         ProfScope ps(P_MS_BC, s);
         hipLaunchKernelGGL(k_wg_bc_sum<BS>, dim3(grid_for(n, BS, device_cu_count() * 8)), dim3(BS), 0, s, n,
-                           nslots, (const WgRec *)ws.wg_rec, tbl,
+                           nslots, (const WgRec *)ws.wg_rec, (const double *)ws.wg_delta, tbl,
                            prof_counters(P_MS_BC));
     }
     SP_HIP(hipGetLastError());
