@@ -588,8 +588,9 @@ __global__ __launch_bounds__(BS) void k_ms_topdown(LevelCtl *c, const int32_t *_
 }
 
 // Bottom-up discovery: every vertex with unsettled slots ORs the level-l masks
-// of its neighbours, 8 entries per lane group, until all its unsettled slots
-// are found.
+// of its neighbours, 8 * kBuPerLane entries per lane group and step, until
+// all its unsettled slots are found.
+constexpr int kBuPerLane = 4;
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *__restrict__ rp,
                                                     const int32_t *__restrict__ ci,
@@ -625,7 +626,8 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
                 ++my_items;
             }
         }
-        const int32_t nch = (deg + 7) >> 3;
+        constexpr int32_t kChunk = 8 * kBuPerLane;  // a lane group's entries per step
+        const int32_t nch = (deg + kChunk - 1) / kChunk;
         const int32_t incl = wave_incl_scan(nch);
         const int32_t total = __shfl(incl, kWave - 1, kWave);
         coff[lane] = incl - nch;
@@ -645,12 +647,20 @@ __global__ __launch_bounds__(BS) void k_ms_bottomup(LevelCtl *c, const int32_t *
                     if (coff[mid] <= k) lo = mid; else hi = mid - 1;
                 }
                 a = lo;
-                const int32_t off = (k - coff[a]) * 8 + j;
+                const int32_t off = (k - coff[a]) * kChunk + j, da = dg[a], ba = bg[a];
                 const unsigned long long want = uns[a];
-                if (off < dg[a] && acc[a] != want) {
-                    const uint4 f = front_cur[ci[bg[a] + off]];
-                    if (f.z == lvl) x = mask_of(f) & want;
-                    ++my_edges;
+                if (off < da && acc[a] != want) {
+                    // the lane's kBuPerLane entries (8 apart) loaded together,
+                    // past the row's end from its last entry, then dropped
+                    uint4 f[kBuPerLane];
+#pragma unroll
+                    for (int r = 0; r < kBuPerLane; ++r) f[r] = front_cur[ci[ba + min(off + 8 * r, da - 1)]];
+#pragma unroll
+                    for (int r = 0; r < kBuPerLane; ++r)
+                        if (off + 8 * r < da) {
+                            if (f[r].z == lvl) x |= mask_of(f[r]) & want;
+                            ++my_edges;
+                        }
                 }
             }
             x |= __shfl_xor(x, 1, kWave);
