@@ -166,14 +166,17 @@ typedef struct sp_batch_config {
  *                     a few grid-wide kernels (levels captured in hipGraphs).
  *   SP_ENGINE_BLOCKS  one workgroup per source, the whole pass (forward and
  *                     reverse levels) inside one launch with the workgroup
- *                     barrier between levels; per-slot dist/sigma/delta
- *                     source-major.  For graphs of many small levels.
+ *                     barrier between levels; per-slot level/value records
+ *                     and delta source-major (32 bytes per vertex and slot),
+ *                     rows copied once to a fixed width of 4 or 8 when every
+ *                     row fits.  For graphs of many small levels.
  *   SP_ENGINE_AUTO    SP_ENGINE_BLOCKS on road-like graphs (no vertex with
  *                     more than 8 neighbours in or out), else SP_ENGINE_BITMAP.
- * Both compute the same per-source quantities; the bitmap engine regroups the
- * reverse sum (sigma(v) times the sum of (1 + delta(w)) / sigma(w)), the
- * blocks engine sums (sigma(v) / sigma(w)) (1 + delta(w)) as written, so
- * their BC differs by rounding only. */
+ * Both compute the same per-source quantities; the bitmap engine, and the
+ * blocks engine over fixed-width rows, regroup the reverse sum (sigma(v)
+ * times the sum of (1 + delta(w)) / sigma(w)); the blocks engine over longer
+ * rows sums (sigma(v) / sigma(w)) (1 + delta(w)) as written, so their BC
+ * differs by rounding only. */
 #define SP_ENGINE_AUTO 0
 #define SP_ENGINE_BITMAP 1
 #define SP_ENGINE_BLOCKS 2
