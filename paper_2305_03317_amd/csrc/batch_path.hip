@@ -762,9 +762,12 @@ __device__ __forceinline__ bool push_sigma(const LevelCtl *c, int32_t max_deg) {
 // each its value range, then: sparse entries are reduced by their own lane,
 // dense ones by the whole wave in turn, hubs are registered for
 // k_ms_sigma_hub.  Every entry's bookkeeping (qmask, value base, nxt reset,
-// seen, front of the new level) is done here.
+// seen, front of the new level) is done here.  Six waves per SIMD, with some
+// registers spilled, beat fewer waves without spills (rmat-22, 64-source
+// batches, per 1,024 sources: 4 waves 55.4 ms in this kernel, 5: 56.1,
+// 6: 53.1).
 template <int BS>
-__global__ __launch_bounds__(BS, 5) void k_ms_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(BS, 6) void k_ms_sigma(LevelCtl *c, const int32_t *__restrict__ rp,
                                                  const int32_t *__restrict__ rpi,
                                                  const int32_t *__restrict__ cii,
                                                  HubEntry *in_hub_list, long long in_hub_cap,
