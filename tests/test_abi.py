@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2305_03317_amd import sp
@@ -161,3 +162,13 @@ def test_header_constants_match_binding():
     assert {"SP_OK", "SP_PTR_DEVICE", "SP_VALIDATE", "SP_PROFILE_TIMES", "SP_PROFILE_COUNTS"} <= set(mirrored)
     for k in mirrored:
         assert getattr(sp, k) == defs[k], k
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without the built library every call raises."""
+    monkeypatch.setattr(sp, "_lib", None)
+    monkeypatch.setattr(sp, "LIB_PATH", str(tmp_path / "libsp.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        sp.lib()
+    with pytest.raises(RuntimeError):
+        sp.sp_graph_upload(np.array([0, 0], dtype=np.int32), np.array([], dtype=np.int32))
