@@ -436,7 +436,6 @@ def blocks_engine_cases():
     long path (a level per vertex), a uniform graph and RMAT with hubs and
     isolated vertices (rows through the CSR offsets), a directed RMAT, and a
     graph of two components."""
-    from tests import brute
     yield "road-96", graphs.road(96, 0.02, 23), False
     k = 40
     x, y = np.meshgrid(np.arange(k), np.arange(k))

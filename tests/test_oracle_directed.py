@@ -11,7 +11,6 @@ betweenness on DiGraphs (unnormalised, ordered pairs).
 """
 from __future__ import annotations
 
-from fractions import Fraction
 
 import networkx as nx
 import numpy as np

@@ -10,7 +10,6 @@ fail these pins.
 from __future__ import annotations
 
 import math
-from fractions import Fraction
 
 import networkx as nx
 import numpy as np

@@ -23,7 +23,6 @@ with Dijkstra's algorithm.  Checked here against:
 from __future__ import annotations
 
 import ctypes
-import itertools
 import os
 import subprocess
 
